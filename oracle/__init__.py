@@ -1,0 +1,248 @@
+"""CPU oracle of hashed path space filtering -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the GPU library: the arithmetic is in
+oracle/pf_oracle.c (plain C, built with gcc, fp-contract off) and the
+MLP reference in oracle/mlp.py (numpy, float64).
+
+filter_frame() composes the steps in the paper's order:
+  keys (Algorithm 1) -> fixed-point radiance -> exact group-by on the key
+  (Eq. (7)/(8), Section 3.2's gather form) -> linear-probing simulation
+  (Section 3.2) -> average = sum / counter (Sections 3.2, 3.3.1) ->
+  exponential moving average with the previous frame's set (Section 3.4.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pf_oracle.c")
+LIB = os.path.join(HERE, "libpf_oracle.so")
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+INVALID, KEYRANGE, OVERFLOW, RADRANGE = 1, 2, 4, 8
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (x86-64 SSE, no contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        u64, u32, i32, f32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
+        L.orc_pcg32_outputs.argtypes = [u64, u64, u32, vp]
+        L.orc_fmix64.argtypes = [u64]; L.orc_fmix64.restype = u64
+        L.orc_splitmix64.argtypes = [u64]; L.orc_splitmix64.restype = u64
+        L.orc_level_of_detail.argtypes = [vp, f32, f32, f32]; L.orc_level_of_detail.restype = ctypes.c_int
+        L.orc_build_keys.argtypes = [u64] + [vp] * 7 + [vp, f32, u64, u64, u32] + [vp] * 4 + [vp] * 3
+        L.orc_quantize_radiance.argtypes = [u64, vp, vp, vp, i32, vp, vp]
+        L.orc_group_by.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp]; L.orc_group_by.restype = ctypes.c_int64
+        L.orc_simulate_table.argtypes = [u64, vp, vp, vp, u32, u32, vp, vp, vp]
+        L.orc_average.argtypes = [u64, vp, vp, i32, vp]
+        L.orc_query.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_temporal_ema.argtypes = [u64, vp, vp, u64, vp, vp, f32, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float32)
+
+
+# ---------------------------------------------------------------- primitives
+def pcg32_outputs(initstate: int, initseq: int, count: int) -> np.ndarray:
+    out = np.zeros(count, np.uint32)
+    lib().orc_pcg32_outputs(initstate, initseq, count, _p(out))
+    return out
+
+
+def fmix64(k: int) -> int:
+    return int(lib().orc_fmix64(k))
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().orc_splitmix64(x))
+
+
+def level_of_detail(cam, x, y, z) -> int:
+    c = _f32(cam)
+    return int(lib().orc_level_of_detail(_p(c), float(np.float32(x)), float(np.float32(y)), float(np.float32(z))))
+
+
+def build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, log2_slots, steps=False):
+    """Key, fingerprint, home and flags per vertex (Algorithm 1)."""
+    arrs = [_f32(a) for a in (px, py, pz, nx, ny, nz)]
+    n = arrs[0].shape[0]
+    v = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
+    key = np.zeros(n, np.uint64); fp = np.zeros(n, np.uint32); home = np.zeros(n, np.uint32)
+    flags = np.zeros(n, np.uint8)
+    lvl = np.zeros(2 * n, np.int32) if steps else None
+    xj = np.zeros(3 * n, np.float32) if steps else None
+    xq = np.zeros(3 * n, np.int32) if steps else None
+    camv = _f32(cam)
+    lib().orc_build_keys(n, *[_p(a) for a in arrs], _p(v), _p(camv), float(np.float32(s)), seed, idx_base,
+                         log2_slots, _p(key), _p(fp), _p(home), _p(flags), _p(lvl), _p(xj), _p(xq))
+    out = {"key": key, "fp": fp, "home": home, "flags": flags}
+    if steps:
+        out["lvl"] = lvl.reshape(n, 2); out["xj"] = xj.reshape(n, 3); out["xq"] = xq.reshape(n, 3)
+    return out
+
+
+def quantize_radiance(r, g, b, frac_bits, flags):
+    """int64 fixed point [n,3]; updates flags in place for unflagged vertices."""
+    r, g, b = _f32(r), _f32(g), _f32(b)
+    n = r.shape[0]
+    q = np.zeros(3 * n, np.int64)
+    lib().orc_quantize_radiance(n, _p(r), _p(g), _p(b), frac_bits, _p(flags), _p(q))
+    return q.reshape(n, 3)
+
+
+def group_by(key, flags, q):
+    n = key.shape[0]
+    gkey = np.zeros(max(n, 1), np.uint64); gcnt = np.zeros(max(n, 1), np.uint32)
+    gsum = np.zeros(3 * max(n, 1), np.int64); vgroup = np.zeros(max(n, 1), np.int64)
+    qq = np.ascontiguousarray(q, dtype=np.int64).reshape(-1)
+    G = lib().orc_group_by(n, _p(np.ascontiguousarray(key, np.uint64)), _p(np.ascontiguousarray(flags, np.uint8)),
+                           _p(qq), _p(gkey), _p(gcnt), _p(gsum), _p(vgroup))
+    if G < 0:
+        raise OverflowError("a cell sum leaves int64")
+    return gkey[:G].copy(), gcnt[:G].copy(), gsum[:3 * G].reshape(G, 3).copy(), vgroup[:n].copy()
+
+
+@dataclass
+class TableSim:
+    occupied: np.ndarray
+    gslot: np.ndarray
+    total_disp: int
+    lmax: int
+    alias: bool
+    n_overflow: int
+    hist: np.ndarray
+
+    @property
+    def order_free(self) -> bool:
+        """True when every insertion order gives this exact outcome."""
+        return not self.alias and self.n_overflow == 0
+
+
+def simulate_table(gkey, gfp, ghome, log2_slots, max_probe) -> TableSim:
+    G = gkey.shape[0]
+    occ = np.zeros(1 << log2_slots, np.uint8)
+    gslot = np.zeros(max(G, 1), np.int64)
+    res = np.zeros(4 + 65, np.uint64)
+    lib().orc_simulate_table(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(np.ascontiguousarray(gfp, np.uint32)),
+                             _p(np.ascontiguousarray(ghome, np.uint32)), log2_slots, max_probe,
+                             _p(occ), _p(gslot), _p(res))
+    lmax = int(res[1])
+    return TableSim(occ, gslot[:G].copy(), int(res[0]), lmax, bool(res[2]), int(res[3]), res[4:].copy())
+
+
+def average(gcnt, gsum, frac_bits):
+    G = gcnt.shape[0]
+    out = np.zeros(3 * max(G, 1), np.float32)
+    lib().orc_average(G, _p(np.ascontiguousarray(gcnt, np.uint32)), _p(np.ascontiguousarray(gsum, np.int64)),
+                      frac_bits, _p(out))
+    return out[:3 * G].reshape(G, 3).copy()
+
+
+def temporal_ema(gkey, gnew, pkey, pold, alpha_old):
+    G = gkey.shape[0]
+    out = np.zeros(3 * max(G, 1), np.float32)
+    pk = np.ascontiguousarray(pkey, np.uint64)
+    assert np.all(pk[1:] > pk[:-1]), "previous keys must be strictly ascending"
+    lib().orc_temporal_ema(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(_f32(gnew).reshape(-1)),
+                           pk.shape[0], _p(pk), _p(_f32(pold).reshape(-1)), float(np.float32(alpha_old)), _p(out))
+    return out[:3 * G].reshape(G, 3).copy()
+
+
+def query(vgroup, gslot, gval, gcnt, r, g, b, flags):
+    n = vgroup.shape[0]
+    out = np.zeros(3 * max(n, 1), np.float32)
+    cnt = np.zeros(max(n, 1), np.uint32)
+    lib().orc_query(n, _p(np.ascontiguousarray(vgroup, np.int64)),
+                    _p(None if gslot is None else np.ascontiguousarray(gslot, np.int64)),
+                    _p(_f32(gval).reshape(-1)), _p(np.ascontiguousarray(gcnt, np.uint32)),
+                    _p(_f32(r)), _p(_f32(g)), _p(_f32(b)), _p(out), _p(cnt), _p(flags))
+    return out[:3 * n].reshape(n, 3).copy(), cnt[:n].copy()
+
+
+# ---------------------------------------------------------------- one frame
+@dataclass
+class FrameResult:
+    key: np.ndarray
+    fp: np.ndarray
+    home: np.ndarray
+    flags: np.ndarray        # final flags (keys, radiance, overflow)
+    q: np.ndarray            # [n,3] fixed point
+    vgroup: np.ndarray
+    gkey: np.ndarray         # distinct keys, ascending
+    gfp: np.ndarray
+    ghome: np.ndarray
+    gcnt: np.ndarray
+    gsum: np.ndarray         # [G,3] int64
+    gavg: np.ndarray         # [G,3] float32
+    gval: np.ndarray         # [G,3] value returned by lookup (blend when temporal)
+    table: TableSim
+    out: np.ndarray          # [n,3] per-vertex result
+    cnt: np.ndarray          # [n] per-vertex cell count (0 when unfiltered)
+    state: tuple             # (keys ascending, values) of placed cells, for the next frame
+
+
+def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
+                 idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None):
+    """The whole hot path for one view and frame on the CPU.
+
+    f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
+    parameters cam, s, seed, log2_slots, max_probe, frac_bits (overridable).
+    With temporal=True the lookup returns the moving average against
+    prev_state (the state of the previous frame, None for the first frame).
+    """
+    A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
+         ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
+    cam = f["cam"] if cam is None else cam
+    s = f["s"] if s is None else s
+    seed = f["seed"] if seed is None else seed
+    m = f["log2_slots"] if log2_slots is None else log2_slots
+    P = f["max_probe"] if max_probe is None else max_probe
+    F = f["frac_bits"] if frac_bits is None else frac_bits
+
+    k = build_keys(A["px"], A["py"], A["pz"], A["nx"], A["ny"], A["nz"], A["valid"], cam, s, seed, idx_base, m)
+    flags = k["flags"].copy()
+    q = quantize_radiance(A["r"], A["g"], A["b"], F, flags)
+    gkey, gcnt, gsum, vgroup = group_by(k["key"], flags, q)
+    # fingerprint and home of each distinct key, taken from any of its vertices
+    first = np.full(gkey.shape[0], -1, np.int64)
+    idx = np.nonzero(vgroup >= 0)[0]
+    first[vgroup[idx][::-1]] = idx[::-1]
+    gfp = k["fp"][first] if gkey.shape[0] else np.zeros(0, np.uint32)
+    ghome = k["home"][first] if gkey.shape[0] else np.zeros(0, np.uint32)
+    sim = simulate_table(gkey, gfp, ghome, m, P)
+    gavg = average(gcnt, gsum, F)
+    placed = sim.gslot >= 0
+    if temporal and prev_state is not None:
+        gval = temporal_ema(gkey, gavg, prev_state[0], prev_state[1], alpha_old)
+    else:
+        gval = gavg
+    out, cnt = query(vgroup, sim.gslot, gval, gcnt, A["r"], A["g"], A["b"], flags)
+    state = (gkey[placed].copy(), gval[placed].copy())
+    return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,
+                       sim, out, cnt, state)

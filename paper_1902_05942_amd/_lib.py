@@ -1,0 +1,188 @@
+"""ctypes binding of libpf.so (include/pf.h): argument marshalling only.
+
+Every function here has the name of the C entry point without the pf_
+prefix, takes torch tensors where the C function takes device pointers, and
+enqueues on torch's current HIP stream unless a stream is given.  No step of
+the filter runs in Python or in PyTorch; if the library is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpf.so")
+
+PF_OK, PF_EINVAL, PF_ERANGE, PF_ELAUNCH = 0, -1, -2, -3
+V_INVALID, V_KEYRANGE, V_OVERFLOW, V_RADRANGE = 1, 2, 4, 8
+STAT_USED, STAT_DISP, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_HIST, STATS_LEN = 0, 1, 2, 3, 8, 80
+CELL_BYTES = 32
+
+
+class PfError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__(f"{fn} returned {status}")
+        self.status = status
+
+
+class pf_table(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_void_p), ("key", ctypes.c_void_p), ("blend", ctypes.c_void_p),
+                ("used", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32),
+                ("max_probe", ctypes.c_uint32), ("frac_bits", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+class pf_key_params(ctypes.Structure):
+    _fields_ = [("cam", ctypes.c_float * 3), ("s", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("idx_base", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
+                          "python paper_1902_05942_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32, f32, i = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                 ctypes.c_float, ctypes.c_int)
+    T = ctypes.POINTER(pf_table)
+    sig = {
+        "pf_version": ([], ctypes.c_char_p),
+        "pf_table_bytes": ([u32, i], ctypes.c_size_t),
+        "pf_table_carve": ([vp, u32, i, u32, i32, T], i),
+        "pf_table_init": ([T, vp], i),
+        "pf_clear": ([T, vp], i),
+        "pf_build_keys": ([vp] * 7 + [u64, ctypes.POINTER(pf_key_params), u32, vp, vp, vp, vp, vp], i),
+        "pf_insert_accumulate": ([T, vp, vp, vp, vp, vp, vp, u64, u32, vp], i),
+        "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
+        "pf_temporal_update": ([T, T, f32, i, vp], i),
+        "pf_read_stats": ([T, vp, vp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "pf_clear", "pf_build_keys",
+            "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda, "device tensor expected"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(fn, st):
+    if st != PF_OK:
+        raise PfError(fn, st)
+
+
+def version() -> str:
+    return lib.pf_version().decode()
+
+
+def table_bytes(log2_slots: int, with_blend: bool = True) -> int:
+    return int(lib.pf_table_bytes(log2_slots, int(with_blend)))
+
+
+class Table:
+    """One table arena (a torch uint8 tensor) carved into the pf_table views."""
+
+    def __init__(self, log2_slots: int, max_probe: int = 64, frac_bits: int = 24, with_blend: bool = True,
+                 device="cuda", arena=None):
+        nbytes = table_bytes(log2_slots, with_blend)
+        if nbytes == 0:
+            raise PfError("pf_table_bytes", PF_ERANGE)
+        self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.t = pf_table()
+        _check("pf_table_carve", lib.pf_table_carve(_ptr(self.arena), log2_slots, int(with_blend), max_probe,
+                                                    frac_bits, ctypes.byref(self.t)))
+        self.log2_slots = log2_slots
+        self.with_blend = with_blend
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.t)
+
+    def _view(self, addr, nbytes, dtype):
+        base = self.arena.data_ptr()
+        off = addr - base
+        return self.arena[off:off + nbytes].view(dtype)
+
+    def cells(self) -> torch.Tensor:
+        """[2^m, 8] int32 view: fp, count, sum0 lo/hi, sum1 lo/hi, sum2 lo/hi."""
+        S = 1 << self.log2_slots
+        return self._view(self.t.cell, S * CELL_BYTES, torch.int32).view(S, 8)
+
+    def keys(self) -> torch.Tensor:
+        S = 1 << self.log2_slots
+        return self._view(self.t.key, S * 8, torch.int64)
+
+    def blend(self) -> torch.Tensor:
+        S = 1 << self.log2_slots
+        return self._view(self.t.blend, S * 16, torch.float32).view(S, 4)
+
+    def used(self) -> torch.Tensor:
+        S = 1 << self.log2_slots
+        return self._view(self.t.used, S * 4, torch.int32)
+
+
+def table_init(t: Table, stream=None):
+    _check("pf_table_init", lib.pf_table_init(t.ref, _stream(stream)))
+
+
+def clear(t: Table, stream=None):
+    _check("pf_clear", lib.pf_clear(t.ref, _stream(stream)))
+
+
+def build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, log2_slots, key, fp, home, vflags,
+               stream=None):
+    kp = pf_key_params()
+    for c in range(3):
+        kp.cam[c] = float(cam[c])
+    kp.s = float(s)
+    kp.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    kp.idx_base = int(idx_base)
+    n = key.numel()
+    _check("pf_build_keys", lib.pf_build_keys(_ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz),
+                                              _ptr(valid), n, ctypes.byref(kp), log2_slots, _ptr(key), _ptr(fp),
+                                              _ptr(home), _ptr(vflags), _stream(stream)))
+
+
+def insert_accumulate(t: Table, key, r, g, b, vflags, slot_out=None, agg_width=0, stream=None):
+    _check("pf_insert_accumulate", lib.pf_insert_accumulate(t.ref, _ptr(key), _ptr(r), _ptr(g), _ptr(b),
+                                                            _ptr(vflags), _ptr(slot_out), key.numel(), agg_width,
+                                                            _stream(stream)))
+
+
+def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_out, g_out, b_out, count_out=None,
+                  stream=None):
+    n = vflags.numel()
+    _check("pf_query_average", lib.pf_query_average(t.ref, _ptr(key), _ptr(slot), _ptr(r_in), _ptr(g_in),
+                                                    _ptr(b_in), _ptr(vflags), n, int(bool(use_blend)), _ptr(r_out),
+                                                    _ptr(g_out), _ptr(b_out), _ptr(count_out), _stream(stream)))
+
+
+def temporal_update(cur: Table, prev, alpha_old: float, mode: int = 0, stream=None):
+    _check("pf_temporal_update", lib.pf_temporal_update(cur.ref, None if prev is None else prev.ref,
+                                                        float(alpha_old), mode, _stream(stream)))
+
+
+def read_stats(t: Table, stream=None):
+    import numpy as np
+    out = np.zeros(STATS_LEN, np.uint64)
+    _check("pf_read_stats", lib.pf_read_stats(t.ref, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return out

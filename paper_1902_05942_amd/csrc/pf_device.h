@@ -1,0 +1,131 @@
+// Device-side building blocks of hashed path space filtering for gfx950.
+//
+// Everything here is inline and used by the kernels of this library only.
+// All binary32 arithmetic is written as separate, individually rounded
+// operations; translation units including this header are compiled with
+// -ffp-contract=off and additionally request it below, so no multiply-add is
+// ever fused and results are bit-reproducible against any IEEE binary32
+// evaluation of the same expressions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf.h"
+
+#pragma clang fp contract(off)
+
+namespace pfk {
+
+constexpr int kLevelMin = -16;
+constexpr int kLevelMax = 15;
+constexpr float kCellIndexLimit = 65536.0f;   // |x~| < 2^16
+constexpr uint64_t kPosMask = (1ull << 56) - 1;  // key bits holding x~ and l'
+constexpr uint32_t kNoSlot = 0xffffffffu;
+constexpr int kBlock = 256;
+
+// Level of detail of Algorithm 1: floor(log2 d) from the binary32 value
+// d^2 = (dx*dx + dy*dy) + dz*dz.  The exponent field of d^2 is
+// floor(log2 d^2) for normal numbers, and floor(e / 2) (arithmetic shift)
+// is floor(log2 d).  Zero and subnormal d^2 give the lowest level, an
+// infinite d^2 the highest.
+__device__ __forceinline__ int level_of_detail(float cx, float cy, float cz, float x, float y, float z) {
+    const float dx = cx - x;
+    const float dy = cy - y;
+    const float dz = cz - z;
+    const float xx = dx * dx;
+    const float yy = dy * dy;
+    const float zz = dz * dz;
+    const float d2 = (xx + yy) + zz;
+    const int e = (int)((__float_as_uint(d2) >> 23) & 0xffu);
+    int l = (e == 0) ? kLevelMin : ((e == 255) ? kLevelMax : ((e - 127) >> 1));
+    l = l < kLevelMin ? kLevelMin : l;
+    l = l > kLevelMax ? kLevelMax : l;
+    return l;
+}
+
+// PCG32 (O'Neill 2014): 64-bit LCG, XSH-RR output, standard seeding.
+struct Pcg32 {
+    uint64_t state;
+    uint64_t inc;
+
+    __device__ __forceinline__ uint32_t next() {
+        const uint64_t old = state;
+        state = old * 6364136223846793005ull + inc;
+        const uint32_t xs = (uint32_t)(((old >> 18) ^ old) >> 27);
+        const uint32_t rot = (uint32_t)(old >> 59);
+        return (xs >> rot) | (xs << ((32u - rot) & 31u));
+    }
+
+    __device__ __forceinline__ Pcg32(uint64_t initstate, uint64_t initseq) {
+        state = 0;
+        inc = (initseq << 1) | 1ull;
+        next();
+        state += initstate;
+        next();
+    }
+};
+
+// MurmurHash3 64-bit finaliser: the home index hash.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// SplitMix64 output function: the fingerprint hash.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t home_of(uint64_t key, uint32_t mask) {
+    return (uint32_t)(fmix64(key & kPosMask)) & mask;
+}
+
+__device__ __forceinline__ uint32_t fingerprint_of(uint64_t key) {
+    const uint32_t f = (uint32_t)(splitmix64(key) >> 32);
+    return f ? f : 1u;
+}
+
+__device__ __forceinline__ uint32_t normal_class(float c) {
+    return (c > 0.0f) ? 1u : ((c < 0.0f) ? 2u : 0u);
+}
+
+// Cell average: (float)((double)sum * 2^-F / (double)count), one rounding
+// of the quotient to binary32 after an exact scaling.
+__device__ __forceinline__ float cell_average(int64_t sum, uint32_t count, int frac_bits) {
+    const double s = ldexp((double)sum, -frac_bits);
+    return (float)(s / (double)count);
+}
+
+// Table handle passed to kernels by value.
+struct Tab {
+    pf_cell *cell;
+    uint64_t *key;
+    float4 *blend;
+    uint32_t *used;
+    unsigned long long *stats;
+    uint32_t mask;
+    uint32_t max_probe;
+    int32_t frac_bits;
+};
+
+__device__ __forceinline__ uint32_t load_fp_relaxed(uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_u64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_u32(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace pfk

@@ -1,0 +1,249 @@
+// Hash table kernels for gfx950: initialisation, sparse clearing,
+// accumulation with linear probing (Section 3.2) and lookup of cell averages.
+#include "pf_device.h"
+#include "pf_kernels.h"
+
+namespace pfk {
+
+constexpr uint32_t kListGrid = 1024;  // blocks of the grid-stride kernels over the used list
+
+// ----------------------------------------------------------------- init
+__global__ __launch_bounds__(kBlock) void table_init_kernel(uint4 *__restrict__ cells16, uint64_t n16,
+                                                            unsigned long long *__restrict__ stats) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n16; j += stride)
+        cells16[j] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < PF_STATS_LEN) stats[threadIdx.x] = 0;
+}
+
+hipError_t launch_table_init(const Tab &t, hipStream_t st) {
+    const uint64_t n16 = ((uint64_t)t.mask + 1) * sizeof(pf_cell) / sizeof(uint4);
+    uint64_t blocks = (n16 + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    table_init_kernel<<<(uint32_t)blocks, kBlock, 0, st>>>(reinterpret_cast<uint4 *>(t.cell), n16, t.stats);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- clear
+// Zeroes the cells on the used list, then (last block to finish) the
+// statistics, which include the list length itself.
+__global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) {
+    const uint32_t count = (uint32_t)t.stats[PF_STAT_USED];
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < count; j += stride) {
+        uint4 *c = reinterpret_cast<uint4 *>(t.cell + t.used[j]);
+        c[0] = make_uint4(0, 0, 0, 0);
+        c[1] = make_uint4(0, 0, 0, 0);
+    }
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long done = atomicAdd(&t.stats[PF_STAT_DONE], 1ull);
+        last = (done == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        for (uint32_t k = threadIdx.x; k < PF_STATS_LEN; k += kBlock) t.stats[k] = 0;
+    }
+}
+
+hipError_t launch_clear(const Tab &t, hipStream_t st) {
+    clear_kernel<<<kListGrid, kBlock, 0, st>>>(t);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- insert
+__device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, int64_t q0, int64_t q1,
+                                           int64_t q2) {
+    pf_cell *c = t.cell + slot;
+    add_u32(&c->count, cnt);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[0]), (unsigned long long)q0);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[1]), (unsigned long long)q1);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[2]), (unsigned long long)q2);
+}
+
+// Probes from home(key) for the key's fingerprint or claims the first empty
+// cell.  Returns the slot or kNoSlot after max_probe slots.
+__device__ __forceinline__ uint32_t find_or_claim(const Tab &t, uint64_t key) {
+    const uint32_t f = fingerprint_of(key);
+    uint32_t s = home_of(key, t.mask);
+    for (uint32_t d = 0; d < t.max_probe; ++d) {
+        uint32_t *pfp = &t.cell[s].fp;
+        uint32_t cur = load_fp_relaxed(pfp);
+        if (cur == 0) {
+            uint32_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                t.key[s] = key;
+                const unsigned long long u =
+                    __hip_atomic_fetch_add(&t.stats[PF_STAT_USED], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                t.used[u] = s;
+                add_u64(&t.stats[PF_STAT_DISP], d);
+                add_u64(&t.stats[PF_STAT_HIST + (d < 64 ? d : 64)], 1ull);
+                return s;
+            }
+            cur = expected;  // claimed meanwhile by someone else
+        }
+        if (cur == f) return s;
+        s = (s + 1) & t.mask;
+    }
+    return kNoSlot;
+}
+
+// kAgg: lanes of one aggregation group (agg consecutive lanes of a block)
+// that reach the same slot add their contributions in LDS first; one lane
+// per (group, slot) then issues the device atomics.  Groups meet through a
+// bucket array indexed by the slot's low bits; a lane whose bucket was taken
+// by a different slot falls back to its own atomics.
+template <bool kAgg>
+__global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *__restrict__ key,
+                                                        const float *__restrict__ r, const float *__restrict__ g,
+                                                        const float *__restrict__ b, uint8_t *__restrict__ flags,
+                                                        uint32_t *__restrict__ slot_out, uint32_t n, uint32_t agg) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const bool in = i < n;
+    uint8_t fl = in ? flags[i] : (uint8_t)PF_V_INVALID;
+    const uint8_t fl0 = fl;
+    int64_t q0 = 0, q1 = 0, q2 = 0;
+    if (fl == 0) {
+        const float c0 = r[i], c1 = g[i], c2 = b[i];
+        if (!(isfinite(c0) && isfinite(c1) && isfinite(c2))) {
+            fl = PF_V_INVALID;
+        } else {
+            const float s0 = ldexpf(c0, t.frac_bits), s1 = ldexpf(c1, t.frac_bits), s2 = ldexpf(c2, t.frac_bits);
+            const float lim = 4611686018427387904.0f;  // 2^62
+            if (!(fabsf(s0) < lim && fabsf(s1) < lim && fabsf(s2) < lim)) {
+                fl = PF_V_RADRANGE;
+            } else {
+                q0 = (int64_t)rintf(s0);
+                q1 = (int64_t)rintf(s1);
+                q2 = (int64_t)rintf(s2);
+            }
+        }
+    }
+    uint32_t slot = kNoSlot;
+    if (fl == 0) {
+        slot = find_or_claim(t, key[i]);
+        if (slot == kNoSlot) {
+            fl = PF_V_OVERFLOW;
+            add_u64(&t.stats[PF_STAT_OVERFLOW], 1ull);
+        }
+    }
+    if (in && fl != fl0) flags[i] = fl;
+    if (in && slot_out) slot_out[i] = slot;
+
+    if constexpr (!kAgg) {
+        if (slot != kNoSlot) accumulate(t, slot, 1, q0, q1, q2);
+    } else {
+        __shared__ uint32_t s_bucket[2 * kBlock];
+        __shared__ uint32_t s_slot[kBlock];
+        __shared__ unsigned long long s_acc[3][kBlock];
+        __shared__ uint32_t s_cnt[kBlock];
+        const uint32_t tid = threadIdx.x;
+        const uint32_t gbase = tid & ~(agg - 1);  // first lane of my group
+        const bool has = slot != kNoSlot;
+        s_slot[tid] = slot;
+        s_acc[0][tid] = 0;
+        s_acc[1][tid] = 0;
+        s_acc[2][tid] = 0;
+        s_cnt[tid] = 0;
+        // every lane with a slot writes its id into its bucket; one write wins
+        const uint32_t bk = 2 * gbase + (slot & (2 * agg - 1));
+        if (has) s_bucket[bk] = tid;
+        __syncthreads();
+        const uint32_t leader = has ? s_bucket[bk] : tid;
+        const bool member = has && s_slot[leader] == slot;
+        if (member) {
+            atomicAdd(&s_acc[0][leader], (unsigned long long)q0);
+            atomicAdd(&s_acc[1][leader], (unsigned long long)q1);
+            atomicAdd(&s_acc[2][leader], (unsigned long long)q2);
+            atomicAdd(&s_cnt[leader], 1u);
+        }
+        __syncthreads();
+        if (member && leader == tid) {
+            accumulate(t, slot, s_cnt[tid], (int64_t)s_acc[0][tid], (int64_t)s_acc[1][tid], (int64_t)s_acc[2][tid]);
+        } else if (has && !member) {
+            accumulate(t, slot, 1, q0, q1, q2);
+        }
+    }
+}
+
+hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
+                         uint8_t *flags, uint32_t *slot_out, uint32_t n, uint32_t agg_width, hipStream_t st) {
+    const uint32_t blocks = (n + kBlock - 1) / kBlock;
+    if (agg_width <= 1)
+        insert_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, 1);
+    else
+        insert_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, agg_width);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- query
+__device__ __forceinline__ uint32_t find_slot(const Tab &t, uint64_t key) {
+    const uint32_t f = fingerprint_of(key);
+    uint32_t s = home_of(key, t.mask);
+    for (uint32_t d = 0; d < t.max_probe; ++d) {
+        const uint32_t cur = t.cell[s].fp;
+        if (cur == f) return s;
+        if (cur == 0) return kNoSlot;
+        s = (s + 1) & t.mask;
+    }
+    return kNoSlot;
+}
+
+template <bool kBlend>
+__global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__restrict__ key,
+                                                       const uint32_t *__restrict__ slot_in, const float *r,
+                                                       const float *g, const float *b,
+                                                       const uint8_t *__restrict__ flags, uint32_t n, float *ro,
+                                                       float *go, float *bo, uint32_t *__restrict__ count_out,
+                                                       bool inplace) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t slot = kNoSlot;
+    if (flags[i] == 0) slot = slot_in ? slot_in[i] : find_slot(t, key[i]);
+    if (slot == kNoSlot) {
+        if (!inplace) {
+            ro[i] = r[i];
+            go[i] = g[i];
+            bo[i] = b[i];
+        }
+        if (count_out) count_out[i] = 0;
+        return;
+    }
+    float a0, a1, a2;
+    uint32_t cnt;
+    if constexpr (kBlend) {
+        const float4 v = t.blend[slot];
+        a0 = v.x;
+        a1 = v.y;
+        a2 = v.z;
+        cnt = (uint32_t)v.w;
+    } else {
+        const pf_cell c = t.cell[slot];
+        cnt = c.count;
+        a0 = cell_average(c.sum[0], cnt, t.frac_bits);
+        a1 = cell_average(c.sum[1], cnt, t.frac_bits);
+        a2 = cell_average(c.sum[2], cnt, t.frac_bits);
+    }
+    ro[i] = a0;
+    go[i] = a1;
+    bo[i] = a2;
+    if (count_out) count_out[i] = cnt;
+}
+
+hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
+                        const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
+                        float *bo, uint32_t *count_out, hipStream_t st) {
+    const uint32_t blocks = (n + kBlock - 1) / kBlock;
+    const bool inplace = (ro == r) && (go == g) && (bo == b);
+    if (use_blend)
+        query_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
+    else
+        query_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
+    return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -1,0 +1,117 @@
+"""The C ABI on a host without a GPU: the library loads, exports every entry
+point include/pf.h declares, and its host-side argument checks return the
+documented status before anything is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:pf_status|size_t|const char \*)\s*(pf_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_1902_05942_amd as pf
+    return pf
+
+
+def test_every_declared_symbol_is_exported(pf):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(pf._lib.lib, n), n
+    assert set(names) == set(pf._lib.EXPORTED)
+
+
+def test_struct_layouts_match_header(pf):
+    assert ctypes.sizeof(pf._lib.pf_table) == 5 * 8 + 4 * 4
+    assert ctypes.sizeof(pf._lib.pf_key_params) == 4 * 4 + 8 + 8
+    assert pf._lib.CELL_BYTES == 32
+
+
+def test_table_sizing_and_carving(pf):
+    L = pf._lib.lib
+    assert L.pf_table_bytes(3, 1) == 0 and L.pf_table_bytes(31, 1) == 0
+    b22 = L.pf_table_bytes(22, 1)
+    S = 1 << 22
+    assert b22 >= S * (32 + 8 + 16 + 4)
+    assert L.pf_table_bytes(22, 0) == b22 - S * 16
+    t = pf._lib.pf_table()
+    base = 0x7F0000000010                       # never dereferenced: carving is arithmetic
+    assert L.pf_table_carve(ctypes.c_void_p(base), 22, 1, 64, 24, ctypes.byref(t)) == 0
+    assert t.cell % 256 == 0 and t.cell >= base and t.stats + 80 * 8 <= base + b22
+    assert t.key - t.cell == S * 32 and t.blend - t.key == S * 8
+    for bad in [(3, 64, 24), (31, 64, 24), (10, 0, 24), (10, 1025, 24), (10, 64, 7), (10, 64, 41)]:
+        assert L.pf_table_carve(ctypes.c_void_p(base), bad[0], 1, bad[1], bad[2], ctypes.byref(t)) == pf._lib.PF_ERANGE
+    assert L.pf_table_carve(None, 10, 1, 64, 24, ctypes.byref(t)) == pf._lib.PF_EINVAL
+
+
+def test_argument_checks_return_before_launch(pf):
+    L, lp = pf._lib.lib, pf._lib
+    t = lp.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(0x7F0000000000), 10, 1, 64, 24, ctypes.byref(t)) == 0
+    kp = lp.pf_key_params()
+    kp.s = 0.01
+    fake = ctypes.c_void_p(0x7F0000100000)
+    # n == 0 is a no-op
+    assert L.pf_build_keys(*([None] * 7), 0, ctypes.byref(kp), 10, None, None, None, None, None) == lp.PF_OK
+    assert L.pf_insert_accumulate(ctypes.byref(t), None, None, None, None, None, None, 0, 0, None) == lp.PF_OK
+    assert L.pf_query_average(ctypes.byref(t), None, None, None, None, None, None, 0, 0, None, None, None, None,
+                              None) == lp.PF_OK
+    # NULL and misaligned pointers
+    assert L.pf_build_keys(*([None] * 7), 5, ctypes.byref(kp), 10, None, None, None, None, None) == lp.PF_EINVAL
+    assert L.pf_build_keys(*([fake] * 6), None, 5, None, 10, fake, None, None, fake, None) == lp.PF_EINVAL
+    odd = ctypes.c_void_p(0x7F0000100002)
+    assert L.pf_build_keys(odd, *([fake] * 5), None, 5, ctypes.byref(kp), 10, fake, None, None, fake,
+                           None) == lp.PF_EINVAL
+    assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, None, fake, None, 5, 0, None) == lp.PF_EINVAL
+    assert L.pf_query_average(ctypes.byref(t), None, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None,
+                              None) == lp.PF_EINVAL
+    # parameter ranges
+    kp.s = 0.0
+    assert L.pf_build_keys(*([fake] * 6), None, 5, ctypes.byref(kp), 10, fake, None, None, fake,
+                           None) == lp.PF_ERANGE
+    kp.s = float("nan")
+    assert L.pf_build_keys(*([fake] * 6), None, 5, ctypes.byref(kp), 10, fake, None, None, fake,
+                           None) == lp.PF_ERANGE
+    kp.s = 0.01
+    assert L.pf_build_keys(*([fake] * 6), None, 5, ctypes.byref(kp), 31, fake, None, None, fake,
+                           None) == lp.PF_ERANGE
+    assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, fake, fake, None, 5, 3, None) == lp.PF_ERANGE
+    assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, fake, fake, None, 5, 512, None) == lp.PF_ERANGE
+    assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, fake, fake, None, 1 << 32, 0,
+                                  None) == lp.PF_EINVAL
+    assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(1.5), 0, None) == lp.PF_ERANGE
+    assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(0.2), 7, None) == lp.PF_ERANGE
+    t2 = lp.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(0x7E0000000000), 11, 1, 64, 24, ctypes.byref(t2)) == 0
+    assert L.pf_temporal_update(ctypes.byref(t), ctypes.byref(t2), ctypes.c_float(0.2), 0, None) == lp.PF_ERANGE
+    t3 = lp.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(0x7D0000000000), 10, 0, 64, 24, ctypes.byref(t3)) == 0
+    assert L.pf_temporal_update(ctypes.byref(t3), None, ctypes.c_float(0.2), 0, None) == lp.PF_EINVAL
+    assert L.pf_query_average(ctypes.byref(t3), fake, None, fake, fake, fake, fake, 5, 1, fake, fake, fake, None,
+                              None) == lp.PF_EINVAL
+    # a corrupted table descriptor
+    t.log2_slots = 40
+    assert L.pf_clear(ctypes.byref(t), None) == lp.PF_ERANGE
+    assert L.pf_clear(None, None) == lp.PF_EINVAL
+    assert L.pf_read_stats(None, None, None) == lp.PF_EINVAL
+
+
+def test_product_path_has_no_fallback(pf):
+    """The package loads libpf.so and nothing else; without it, import fails."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r); import paper_1902_05942_amd._lib as L; "
+            "print(L.LIB_PATH)") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip().endswith("libpf.so")
+    src = open(os.path.join(ROOT, "paper_1902_05942_amd", "__init__.py")).read()
+    src += open(os.path.join(ROOT, "paper_1902_05942_amd", "_lib.py")).read()
+    assert "oracle" not in src

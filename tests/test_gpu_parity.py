@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for
+bit, on seeded synthetic frames (small, scaled with a ragged tail, and the
+full 1080p x3 workload in the launch configuration the benchmark times)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1902_05942_amd as pf
+import synth
+from gpu_util import assert_bits_equal, check_frame_against_oracle, gpu_frame, to_dev
+
+pytestmark = pytest.mark.gpu
+
+BENCH_AGG = 64  # aggregation width the benchmark launches with
+
+
+def _frame(name, frame=0, width=None, height=None, device="cpu"):
+    wl = synth.get(name)
+    f = synth.generate(wl, frame=frame, width=width, height=height, device=device)
+    return wl, f
+
+
+def _host(f):
+    return {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in f.items()}
+
+
+@pytest.mark.parametrize("case", ["tiny", "scaled_ragged", "hd_full"])
+def test_build_keys_bit_exact(gpu, case):
+    if case == "tiny":
+        wl, f = _frame("tiny_64x64")
+    elif case == "scaled_ragged":
+        wl, f = _frame("hd_1080p_x3", frame=5, width=333, height=187)   # 186,813 slots: ragged tail
+    else:
+        wl, f = _frame("hd_1080p_x3", frame=0, device="cuda")
+    print(f"[keys] {case}: n={f['px'].numel()}", flush=True)
+    g = to_dev(f)
+    t = pf.Table(f["log2_slots"], f["max_probe"], f["frac_bits"])
+    pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=0)
+    fh = _host(f)
+    k = oracle.build_keys(fh["px"], fh["py"], fh["pz"], fh["nx"], fh["ny"], fh["nz"], fh["valid"], f["cam"],
+                          f["s"], f["seed"], 0, f["log2_slots"])
+    assert_bits_equal(res["key"], k["key"], "key")
+    assert_bits_equal(res["fp"], k["fp"], "fingerprint")
+    assert_bits_equal(res["home"], k["home"], "home")
+    assert_bits_equal(res["flags_keys"], k["flags"], "key flags")
+
+
+def test_build_keys_edge_cases(gpu):
+    """Non-finite and masked inputs, far vertices, zero and signed-zero normal
+    components, level boundaries, generic normals, several scales."""
+    rng = np.random.default_rng(21)
+    n = 5000
+    pos = rng.uniform(-5, 5, (n, 3)).astype(np.float32)
+    nrm = rng.normal(size=(n, 3)); nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    nrm = nrm.astype(np.float32)
+    cam = np.array([0.25, 1.5, -3.0], np.float32)
+    # level boundaries: distances exactly 2^k and one ulp below
+    for j, k in enumerate(range(-8, 12)):
+        d = np.float32(2.0) ** k
+        pos[2 * j] = cam + np.array([d, 0, 0], np.float32)
+        pos[2 * j + 1] = cam + np.array([np.nextafter(d, np.float32(0)), 0, 0], np.float32)
+    pos[100] = cam                                            # zero distance
+    pos[101] = np.array([3e7, 0, 0], np.float32)              # key range
+    pos[102] = np.array([-2.5e7, 1, 0], np.float32)
+    pos[103, 0] = np.nan; pos[104, 1] = np.inf; nrm[105, 2] = -np.inf
+    nrm[106] = 0.0; nrm[107] = [-0.0, 1.0, 0.0]; nrm[108] = [0.0, -0.0, -1.0]
+    nrm[200:400] = 0; nrm[200:300, 1] = 1; nrm[300:400, 0] = -1
+    valid = np.ones(n, np.uint8); valid[109] = 0; valid[4000:4100] = 0
+    seen = set()
+    for s in (0.01, 0.003, 0.5, 7.0):
+        f = {"px": pos[:, 0].copy(), "py": pos[:, 1].copy(), "pz": pos[:, 2].copy(),
+             "nx": nrm[:, 0].copy(), "ny": nrm[:, 1].copy(), "nz": nrm[:, 2].copy(),
+             "r": np.ones(n, np.float32), "g": np.ones(n, np.float32), "b": np.ones(n, np.float32),
+             "valid": valid, "cam": tuple(float(c) for c in cam), "s": s, "seed": 0xDEADBEEF12345678,
+             "log2_slots": 16, "max_probe": 64, "frac_bits": 24}
+        g = to_dev(f)
+        t = pf.Table(16); pf.table_init(t)
+        for idx_base in (0, 123456789):
+            res = gpu_frame(f, g, t, idx_base=idx_base)
+            k = oracle.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], s,
+                                  f["seed"], idx_base, 16)
+            assert_bits_equal(res["key"], k["key"], f"key s={s}")
+            assert_bits_equal(res["fp"], k["fp"], f"fp s={s}")
+            assert_bits_equal(res["home"], k["home"], f"home s={s}")
+            assert_bits_equal(res["flags_keys"], k["flags"], f"flags s={s}")
+            seen |= {int(x) for x in np.unique(k["flags"])}
+    assert seen == {0, pf.V_INVALID, pf.V_KEYRANGE}
+
+
+@pytest.mark.parametrize("case,agg,use_slot", [
+    ("tiny", 0, True), ("tiny", 64, False), ("tiny", 256, True),
+    ("scaled_ragged", 0, False), ("scaled_ragged", 4, True), ("scaled_ragged", 64, True),
+    ("scaled_ragged", 256, False),
+    ("hd_full", BENCH_AGG, True), ("hd_full", 0, False),
+])
+def test_filter_frame_bit_exact(gpu, case, agg, use_slot):
+    if case == "tiny":
+        wl, f = _frame("tiny_64x64")
+    elif case == "scaled_ragged":
+        wl, f = _frame("hd_1080p_x3", frame=2, width=401, height=229)
+    else:
+        wl, f = _frame("hd_1080p_x3", frame=0, device="cuda")
+    print(f"[filter] {case} agg={agg} slot={use_slot} n={f['px'].numel()}", flush=True)
+    g = to_dev(f)
+    t = pf.Table(f["log2_slots"], f["max_probe"], f["frac_bits"])
+    pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=agg, use_slot=use_slot)
+    R = oracle.filter_frame(_host(f), temporal=False)
+    check_frame_against_oracle(res, R, t)
+
+
+def test_clear_reuses_table_across_frames(gpu):
+    """pf_clear empties exactly what the last frame used: a second, different
+    frame in the same table matches the oracle as if the table were new."""
+    wl = synth.get("hd_1080p_x3")
+    t = pf.Table(18); pf.table_init(t)
+    for frame in (0, 7, 3):
+        f = synth.generate(wl, frame=frame, width=320, height=180)
+        f["log2_slots"] = 18
+        res = gpu_frame(f, to_dev(f), t, agg=64)
+        check_frame_against_oracle(res, oracle.filter_frame(_host(f), temporal=False), t)
+
+
+def test_in_place_query(gpu):
+    wl, f = _frame("hd_1080p_x3", frame=1, width=300, height=200)
+    g = to_dev(f)
+    t = pf.Table(f["log2_slots"]); pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=64, in_place=True)
+    check_frame_against_oracle(res, oracle.filter_frame(_host(f), temporal=False), t)
+
+
+@pytest.mark.parametrize("agg", [0, 64])
+def test_temporal_sixteen_frames_bit_exact(gpu, agg):
+    """Exponential moving average over 16 frames of the orbiting camera with
+    double-buffered tables; every frame's output equals the oracle's."""
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(20), pf.Table(20)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(16):
+        f = synth.generate(wl, frame=frame, width=480, height=270)
+        f["log2_slots"] = 20
+        cur, prev = tabs[frame % 2], (tabs[(frame + 1) % 2] if frame else None)
+        res = gpu_frame(f, to_dev(f), cur, prev=prev, agg=agg, temporal=True, alpha=wl.alpha_old)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old)
+        check_frame_against_oracle(res, R, cur)
+        if frame:
+            assert int(res["stats"][pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, state[0]).sum())
+        state = R.state
+
+
+def test_temporal_full_hd_three_frames(gpu):
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(22), pf.Table(22)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(3):
+        f = synth.generate(wl, frame=frame, device="cuda")
+        cur, prev = tabs[frame % 2], (tabs[(frame + 1) % 2] if frame else None)
+        res = gpu_frame(f, to_dev(f), cur, prev=prev, agg=BENCH_AGG, temporal=True, alpha=wl.alpha_old)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old)
+        check_frame_against_oracle(res, R, cur)
+        state = R.state
+
+
+def test_probe_overflow_in_a_tiny_table(gpu):
+    """16 slots, 2 probe steps: which keys overflow depends on arrival order,
+    so compare what is unique: every placed cell holds exactly its key's
+    oracle group, overflowed vertices are exactly those of unplaced keys and
+    keep their own radiance, and every other vertex gets its cell's average."""
+    wl, f = _frame("tiny_64x64")
+    f["log2_slots"], f["max_probe"] = 4, 2
+    g = to_dev(f)
+    t = pf.Table(4, max_probe=2); pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=64)
+    R = oracle.filter_frame(_host(f), temporal=False, log2_slots=4, max_probe=2)
+    from gpu_util import table_contents
+    tc = table_contents(t)
+    assert 0 < len(tc["key"]) <= 16
+    gi = np.searchsorted(R.gkey, tc["key"])
+    assert np.array_equal(R.gkey[gi], tc["key"])
+    assert np.array_equal(R.gcnt[gi], tc["count"]) and np.array_equal(R.gsum[gi], tc["sum"])
+    placed = np.isin(res["key"], tc["key"])
+    base = R.flags & ~np.uint8(pf.V_OVERFLOW)
+    ok = base == 0
+    assert np.array_equal((res["flags"] & pf.V_OVERFLOW) != 0, ok & ~placed)
+    rgb = np.stack([f["r"].numpy(), f["g"].numpy(), f["b"].numpy()], 1)
+    ovf = (res["flags"] & pf.V_OVERFLOW) != 0
+    assert_bits_equal(res["out"][ovf], rgb[ovf], "overflowed vertices keep their radiance")
+    assert np.all(res["cnt"][ovf] == 0)
+    avg = oracle.average(R.gcnt, R.gsum, 24)
+    gv = R.vgroup[ok & placed]
+    assert_bits_equal(res["out"][ok & placed], avg[gv], "placed vertices get their cell average")
+
+
+def test_empty_and_single_vertex(gpu):
+    t = pf.Table(8); pf.table_init(t)
+    e = torch.empty(0, device="cuda")
+    k = torch.empty(0, dtype=torch.int64, device="cuda")
+    fl = torch.empty(0, dtype=torch.uint8, device="cuda")
+    pf.build_keys(e, e, e, e, e, e, None, (0, 0, 0), 0.01, 1, 0, 8, k, None, None, fl)
+    pf.insert_accumulate(t, k, e, e, e, fl, None, 64)
+    pf.query_average(t, k, None, e, e, e, fl, False, e, e, e, None)
+    torch.cuda.synchronize()
+    assert int(pf.read_stats(t)[pf.STAT_USED]) == 0
+    f = {"px": np.array([0.3], np.float32), "py": np.array([0.0], np.float32), "pz": np.array([0.7], np.float32),
+         "nx": np.zeros(1, np.float32), "ny": np.ones(1, np.float32), "nz": np.zeros(1, np.float32),
+         "r": np.array([0.25], np.float32), "g": np.array([0.5], np.float32), "b": np.array([2.0], np.float32),
+         "valid": np.ones(1, np.uint8), "cam": (0.0, 2.0, -6.0), "s": 0.01, "seed": 5, "log2_slots": 8,
+         "max_probe": 64, "frac_bits": 24}
+    res = gpu_frame(f, to_dev(f), t, agg=64)
+    check_frame_against_oracle(res, oracle.filter_frame(f, temporal=False), t)
+
+
+def test_nonfinite_and_out_of_range_radiance(gpu):
+    wl, f = _frame("tiny_64x64")
+    r = f["r"].clone(); r[10] = float("nan"); r[11] = float("inf"); r[12] = 3e12; r[13] = -3e12
+    f["r"] = r
+    f["g"] = f["g"].clone(); f["g"][14] = -float("inf")
+    g = to_dev(f)
+    t = pf.Table(f["log2_slots"]); pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=64)
+    R = oracle.filter_frame(_host(f), temporal=False)
+    check_frame_against_oracle(res, R, t)
+    assert set(np.unique(R.flags[10:15])) <= {0, pf.V_INVALID, pf.V_RADRANGE}

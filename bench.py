@@ -133,10 +133,10 @@ def main():
     # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
     nv = float(np.mean(n_valid))
     algo_bytes = {
-        "clear": cells * (4 + 32),
+        "clear": cells * 32 + (1 << view.log2_slots) // 8,
         "build_keys": n * (6 * 4 + 1 + 8 + 1),
         "insert_accumulate": n * (1 + 4) + nv * (8 + 12 + 4 + 28),
-        "temporal_update": cells * (4 + 32 + 8 + 4 + 8 + 16 + 16),
+        "temporal_update": cells * (32 + 8 + 4 + 8 + 16 + 16) + (1 << view.log2_slots) // 8,
         "query_average": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12,
     }
     dom = max(per, key=lambda k: per[k])

@@ -70,22 +70,28 @@ typedef struct pf_cell {
     int64_t sum[3];
 } pf_cell;
 
-/* Device statistics block: PF_STATS_LEN uint64 counters. */
+/* Statistics block: PF_STATS_LEN uint64 counters.  The kernels never update
+ * one shared counter per cell or per vertex (device atomics on one address
+ * serialise): USED, DISP and HIST are derived from the table by
+ * pf_read_stats, and OVERFLOW and TEMPORAL_HIT are gathered in spread partial
+ * counters that pf_read_stats folds in.  Read them only through
+ * pf_read_stats. */
 #define PF_STAT_USED 0        /* occupied slots (= distinct cells inserted) */
 #define PF_STAT_DISP 1        /* sum over occupied slots of (slot - home) mod 2^m */
 #define PF_STAT_OVERFLOW 2    /* vertices flagged PF_V_OVERFLOW by insert */
 #define PF_STAT_TEMPORAL_HIT 3 /* cells that found their key in the previous table */
-#define PF_STAT_DONE 4        /* internal */
 #define PF_STAT_HIST 8        /* [65]: occupied slots by displacement, bin 64 = displacement >= 64 */
-#define PF_STATS_LEN 80
+#define PF_STAT_PART_HIT 80   /* [32] internal partial counters */
+#define PF_STAT_PART_OVF 112  /* [16] internal partial counters */
+#define PF_STATS_LEN 128
 
 /* A table is a set of views into one caller-owned arena, filled in by
- * pf_table_carve().  All arrays have 2^log2_slots entries. */
+ * pf_table_carve().  cell, key and blend have 2^log2_slots entries. */
 typedef struct pf_table {
     pf_cell *cell;       /* cells (fingerprint, count, fixed-point sums) */
     uint64_t *key;       /* full key of each occupied slot, written by the slot's claimer */
     float *blend;        /* 4 floats per slot: temporal value rgb + count; may be NULL */
-    uint32_t *used;      /* list of occupied slots, PF_STAT_USED entries valid */
+    uint32_t *occ;       /* occupancy bitmap, 2^log2_slots / 32 words (bit s%32 of word s/32) */
     uint64_t *stats;     /* PF_STATS_LEN counters */
     uint32_t log2_slots; /* 4 .. 30 */
     uint32_t max_probe;  /* 1 .. 2^log2_slots: slots examined before PF_V_OVERFLOW */
@@ -102,14 +108,15 @@ size_t pf_table_bytes(uint32_t log2_slots, int with_blend);
 pf_status pf_table_carve(void *arena, uint32_t log2_slots, int with_blend, uint32_t max_probe,
                          int32_t frac_bits, pf_table *t);
 
-/* Zeroes every cell and the statistics of a freshly carved table.  Must run
- * once before the first pf_clear() or insert. */
+/* Zeroes every cell, the occupancy bitmap and the statistics of a freshly
+ * carved table.  Must run once before the first pf_clear() or insert. */
 pf_status pf_table_init(const pf_table *t, void *stream);
 
-/* Empties a table for the next frame.  Only the slots on the table's used
- * list are zeroed (work proportional to the cells of the last frame, not to
- * the table size), then the statistics.  The table must have been
- * initialised and only modified through this library since. */
+/* Empties a table for the next frame: zeroes the cells whose occupancy bit
+ * is set (work proportional to the occupancy bitmap, 2^log2_slots / 8
+ * bytes, plus the cells of the last frame, not to the cell array), the
+ * bitmap and the statistics.  The table must have been initialised and only
+ * modified through this library since. */
 pf_status pf_clear(const pf_table *t, void *stream);
 
 /* ------------------------------------------------------------------- keys */
@@ -153,8 +160,8 @@ pf_status pf_build_keys(const float *px, const float *py, const float *pz,
 /* Accumulation (Section 3.2): every vertex with vflags == 0 converts its
  * contribution (r, g, b) to fixed point q_c = rint(c * 2^frac_bits), probes
  * from home(key) for a cell whose fingerprint equals fp(key) or claims the
- * first empty cell with a compare-and-swap (recording the key, appending the
- * slot to the used list), and adds 1 to the counter and q to the sums with
+ * first empty cell with a compare-and-swap (recording the key and setting
+ * the slot's occupancy bit), and adds 1 to the counter and q to the sums with
  * device-scope integer atomics.  Integer sums make the result independent of
  * the order in which vertices arrive.
  * Vertices with non-finite contributions get PF_V_INVALID, with out-of-range
@@ -187,7 +194,8 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
                            void *stream);
 
 /* --------------------------------------------------------------- temporal */
-/* Two sets of averages (Section 3.4.1).  For every occupied cell of `cur`,
+/* Two sets of averages (Section 3.4.1).  For every occupied cell of `cur`
+ * (found through its occupancy bitmap),
  * computes c_new = sum / count as in the lookup, searches its key in `prev`
  * (fingerprint probe confirmed by the stored 64-bit key) and stores
  *   mode 0: c = alpha_old * c_old + (1 - alpha_old) * c_new  (each product
@@ -202,7 +210,8 @@ pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float al
                              void *stream);
 
 /* ------------------------------------------------------------ diagnostics */
-/* Copies the PF_STATS_LEN counters to host memory and waits for the copy.
+/* Derives USED, DISP and HIST from the table (occupancy bitmap and keys),
+ * copies the PF_STATS_LEN counters to host memory and waits for the copy.
  * The only call that blocks the host. */
 pf_status pf_read_stats(const pf_table *t, uint64_t *host_out, void *stream);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpf.so")
 
 PF_OK, PF_EINVAL, PF_ERANGE, PF_ELAUNCH = 0, -1, -2, -3
 V_INVALID, V_KEYRANGE, V_OVERFLOW, V_RADRANGE = 1, 2, 4, 8
-STAT_USED, STAT_DISP, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_HIST, STATS_LEN = 0, 1, 2, 3, 8, 80
+STAT_USED, STAT_DISP, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_HIST, STATS_LEN = 0, 1, 2, 3, 8, 128
 CELL_BYTES = 32
 
 
@@ -30,7 +30,7 @@ class PfError(RuntimeError):
 
 class pf_table(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_void_p), ("key", ctypes.c_void_p), ("blend", ctypes.c_void_p),
-                ("used", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32),
+                ("occ", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32),
                 ("max_probe", ctypes.c_uint32), ("frac_bits", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
@@ -135,9 +135,10 @@ class Table:
         S = 1 << self.log2_slots
         return self._view(self.t.blend, S * 16, torch.float32).view(S, 4)
 
-    def used(self) -> torch.Tensor:
+    def occupancy(self) -> torch.Tensor:
+        """Occupancy bitmap as int32 words (bit s % 32 of word s // 32)."""
         S = 1 << self.log2_slots
-        return self._view(self.t.used, S * 4, torch.int32)
+        return self._view(self.t.occ, (S + 31) // 32 * 4, torch.int32)
 
 
 def table_init(t: Table, stream=None):

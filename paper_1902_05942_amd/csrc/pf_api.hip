@@ -21,8 +21,8 @@ bool aligned(const T *p) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 pf_status check_table(const pf_table *t) {
-    if (!t || !t->cell || !t->key || !t->used || !t->stats) return PF_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(t->cell) % 32) || !aligned(t->key) || !aligned(t->used) ||
+    if (!t || !t->cell || !t->key || !t->occ || !t->stats) return PF_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(t->cell) % 32) || !aligned(t->key) || !aligned(t->occ) ||
         !aligned(t->stats) || (t->blend && (reinterpret_cast<uintptr_t>(t->blend) % 16)))
         return PF_EINVAL;
     if (t->log2_slots < 4 || t->log2_slots > 30) return PF_ERANGE;
@@ -36,7 +36,7 @@ Tab to_tab(const pf_table *t) {
     k.cell = t->cell;
     k.key = t->key;
     k.blend = reinterpret_cast<float4 *>(t->blend);
-    k.used = t->used;
+    k.occ = t->occ;
     k.stats = reinterpret_cast<unsigned long long *>(t->stats);
     k.mask = (uint32_t)((1ull << t->log2_slots) - 1);
     k.max_probe = t->max_probe;
@@ -59,7 +59,7 @@ size_t pf_table_bytes(uint32_t log2_slots, int with_blend) {
     b += align_up(S * sizeof(pf_cell), 256);             // cells
     b += align_up(S * sizeof(uint64_t), 256);            // keys
     b += with_blend ? align_up(S * 4 * sizeof(float), 256) : 0;
-    b += align_up(S * sizeof(uint32_t), 256);            // used list
+    b += align_up((S + 31) / 32 * sizeof(uint32_t), 256); // occupancy bitmap
     b += align_up(PF_STATS_LEN * sizeof(uint64_t), 256);  // statistics
     return b;
 }
@@ -81,8 +81,8 @@ pf_status pf_table_carve(void *arena, uint32_t log2_slots, int with_blend, uint3
         t->blend = reinterpret_cast<float *>(p);
         p += align_up(S * 4 * sizeof(float), 256);
     }
-    t->used = reinterpret_cast<uint32_t *>(p);
-    p += align_up(S * sizeof(uint32_t), 256);
+    t->occ = reinterpret_cast<uint32_t *>(p);
+    p += align_up((S + 31) / 32 * sizeof(uint32_t), 256);
     t->stats = reinterpret_cast<uint64_t *>(p);
     t->log2_slots = log2_slots;
     t->max_probe = max_probe;
@@ -179,6 +179,7 @@ pf_status pf_read_stats(const pf_table *t, uint64_t *host_out, void *stream) {
     const pf_status s = check_table(t);
     if (s != PF_OK) return s;
     if (!host_out) return PF_EINVAL;
+    if (pfk::launch_stats(to_tab(t), (hipStream_t)stream) != hipSuccess) return PF_ELAUNCH;
     if (hipMemcpyAsync(host_out, t->stats, PF_STATS_LEN * sizeof(uint64_t), hipMemcpyDeviceToHost,
                        (hipStream_t)stream) != hipSuccess)
         return PF_ELAUNCH;

@@ -109,14 +109,18 @@ struct Tab {
     pf_cell *cell;
     uint64_t *key;
     float4 *blend;
-    uint32_t *used;
+    uint32_t *occ;
     unsigned long long *stats;
     uint32_t mask;
     uint32_t max_probe;
     int32_t frac_bits;
+
+    // occupancy bitmap words (at least one; tables have >= 16 slots)
+    __host__ __device__ __forceinline__ uint32_t nwords() const { return (uint32_t)(((uint64_t)mask + 32) >> 5); }
 };
 
-__device__ __forceinline__ uint32_t load_fp_relaxed(uint32_t *p) {
+// Fingerprint read while other lanes may claim slots: a relaxed atomic load.
+__device__ __forceinline__ uint32_t load_fp_probe(uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

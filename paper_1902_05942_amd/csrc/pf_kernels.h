@@ -30,6 +30,7 @@ hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, cons
 hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
                         const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
                         float *bo, uint32_t *count_out, hipStream_t st);
+hipError_t launch_stats(const Tab &t, hipStream_t st);
 hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, hipStream_t st);
 
 }  // namespace pfk

@@ -1,56 +1,64 @@
-// Hash table kernels for gfx950: initialisation, sparse clearing,
-// accumulation with linear probing (Section 3.2) and lookup of cell averages.
+// Hash table kernels for gfx950: initialisation, clearing, accumulation with
+// linear probing (Section 3.2), lookup of cell averages, and the table
+// statistics.  Occupied slots are recorded in a bitmap (one atomicOr per
+// claimed slot, spread over 2^m/32 words) so that no kernel updates a
+// shared counter per cell.
 #include "pf_device.h"
 #include "pf_kernels.h"
 
 namespace pfk {
 
-constexpr uint32_t kListGrid = 1024;  // blocks of the grid-stride kernels over the used list
+constexpr uint32_t kScanGrid = 2048;  // blocks of the grid-stride kernels over the bitmap
 
 // ----------------------------------------------------------------- init
 __global__ __launch_bounds__(kBlock) void table_init_kernel(uint4 *__restrict__ cells16, uint64_t n16,
+                                                            uint32_t *__restrict__ occ, uint32_t nwords,
                                                             unsigned long long *__restrict__ stats) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n16; j += stride)
-        cells16[j] = make_uint4(0, 0, 0, 0);
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (uint64_t j = tid; j < n16; j += stride) cells16[j] = make_uint4(0, 0, 0, 0);
+    for (uint64_t j = tid; j < nwords; j += stride) occ[j] = 0;
     if (blockIdx.x == 0 && threadIdx.x < PF_STATS_LEN) stats[threadIdx.x] = 0;
 }
+static_assert(PF_STATS_LEN <= kBlock, "one block zeroes the statistics");
 
 hipError_t launch_table_init(const Tab &t, hipStream_t st) {
     const uint64_t n16 = ((uint64_t)t.mask + 1) * sizeof(pf_cell) / sizeof(uint4);
     uint64_t blocks = (n16 + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
-    table_init_kernel<<<(uint32_t)blocks, kBlock, 0, st>>>(reinterpret_cast<uint4 *>(t.cell), n16, t.stats);
+    table_init_kernel<<<(uint32_t)blocks, kBlock, 0, st>>>(reinterpret_cast<uint4 *>(t.cell), n16, t.occ,
+                                                           t.nwords(), t.stats);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- clear
-// Zeroes the cells on the used list, then (last block to finish) the
-// statistics, which include the list length itself.
+// Zeroes the cells whose occupancy bit is set and the bitmap words; block 0
+// zeroes the statistics (no kernel reads them here).
 __global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) {
-    const uint32_t count = (uint32_t)t.stats[PF_STAT_USED];
+    const uint32_t nwords = t.nwords();
     const uint32_t stride = gridDim.x * kBlock;
-    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < count; j += stride) {
-        uint4 *c = reinterpret_cast<uint4 *>(t.cell + t.used[j]);
-        c[0] = make_uint4(0, 0, 0, 0);
-        c[1] = make_uint4(0, 0, 0, 0);
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nwords; j += stride) {
+        uint32_t w = t.occ[j];
+        if (w == 0) continue;
+        t.occ[j] = 0;
+        while (w) {
+            const uint32_t b = __builtin_ctz(w);
+            w &= w - 1;
+            uint4 *c = reinterpret_cast<uint4 *>(t.cell + (j * 32 + b));
+            c[0] = make_uint4(0, 0, 0, 0);
+            c[1] = make_uint4(0, 0, 0, 0);
+        }
     }
-    __shared__ bool last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long done = atomicAdd(&t.stats[PF_STAT_DONE], 1ull);
-        last = (done == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        for (uint32_t k = threadIdx.x; k < PF_STATS_LEN; k += kBlock) t.stats[k] = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < PF_STATS_LEN) t.stats[threadIdx.x] = 0;
+}
+
+static uint32_t scan_blocks(uint32_t items) {
+    const uint32_t b = (items + kBlock - 1) / kBlock;
+    return b < kScanGrid ? (b ? b : 1) : kScanGrid;
 }
 
 hipError_t launch_clear(const Tab &t, hipStream_t st) {
-    clear_kernel<<<kListGrid, kBlock, 0, st>>>(t);
+    clear_kernel<<<scan_blocks(t.nwords()), kBlock, 0, st>>>(t);
     return hipGetLastError();
 }
 
@@ -65,23 +73,21 @@ __device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t
 }
 
 // Probes from home(key) for the key's fingerprint or claims the first empty
-// cell.  Returns the slot or kNoSlot after max_probe slots.
+// cell.  Returns the slot or kNoSlot after max_probe slots.  A stale read of
+// 0 only leads to a compare-and-swap that returns the current value; a
+// non-zero fingerprint never changes within the kernel.
 __device__ __forceinline__ uint32_t find_or_claim(const Tab &t, uint64_t key) {
     const uint32_t f = fingerprint_of(key);
     uint32_t s = home_of(key, t.mask);
     for (uint32_t d = 0; d < t.max_probe; ++d) {
         uint32_t *pfp = &t.cell[s].fp;
-        uint32_t cur = load_fp_relaxed(pfp);
+        uint32_t cur = load_fp_probe(pfp);
         if (cur == 0) {
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
                 t.key[s] = key;
-                const unsigned long long u =
-                    __hip_atomic_fetch_add(&t.stats[PF_STAT_USED], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                t.used[u] = s;
-                add_u64(&t.stats[PF_STAT_DISP], d);
-                add_u64(&t.stats[PF_STAT_HIST + (d < 64 ? d : 64)], 1ull);
+                __hip_atomic_fetch_or(&t.occ[s >> 5], 1u << (s & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return s;
             }
             cur = expected;  // claimed meanwhile by someone else
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *_
         slot = find_or_claim(t, key[i]);
         if (slot == kNoSlot) {
             fl = PF_V_OVERFLOW;
-            add_u64(&t.stats[PF_STAT_OVERFLOW], 1ull);
+            add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], 1ull);
         }
     }
     if (in && fl != fl0) flags[i] = fl;
@@ -243,6 +249,61 @@ hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot,
         query_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
     else
         query_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- statistics
+// Zeroes the derived counters and folds the partial counters.
+__global__ void stats_zero_kernel(unsigned long long *stats) {
+    const uint32_t k = threadIdx.x;
+    if (k == PF_STAT_USED || k == PF_STAT_DISP || (k >= PF_STAT_HIST && k < PF_STAT_HIST + 65)) stats[k] = 0;
+    if (k == PF_STAT_OVERFLOW) {
+        unsigned long long v = 0;
+        for (int j = 0; j < 16; ++j) v += stats[PF_STAT_PART_OVF + j];
+        stats[k] = v;
+    }
+    if (k == PF_STAT_TEMPORAL_HIT) {
+        unsigned long long v = 0;
+        for (int j = 0; j < 32; ++j) v += stats[PF_STAT_PART_HIT + j];
+        stats[k] = v;
+    }
+}
+
+// USED, DISP and HIST from the bitmap and the stored keys: block-local sums
+// in LDS, then one device atomic per non-zero block total.
+__global__ __launch_bounds__(kBlock) void stats_kernel(Tab t) {
+    __shared__ unsigned long long s_used, s_disp;
+    __shared__ unsigned long long s_hist[65];
+    if (threadIdx.x == 0) {
+        s_used = 0;
+        s_disp = 0;
+    }
+    if (threadIdx.x < 65) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t nwords = t.nwords();
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nwords; j += stride) {
+        uint32_t w = t.occ[j];
+        if (w) atomicAdd(&s_used, (unsigned long long)__popc(w));
+        while (w) {
+            const uint32_t s = j * 32 + __builtin_ctz(w);
+            w &= w - 1;
+            const uint32_t d = (s - home_of(t.key[s], t.mask)) & t.mask;
+            atomicAdd(&s_disp, (unsigned long long)d);
+            atomicAdd(&s_hist[d < 64 ? d : 64], 1ull);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_used) add_u64(&t.stats[PF_STAT_USED], s_used);
+        if (s_disp) add_u64(&t.stats[PF_STAT_DISP], s_disp);
+    }
+    if (threadIdx.x < 65 && s_hist[threadIdx.x]) add_u64(&t.stats[PF_STAT_HIST + threadIdx.x], s_hist[threadIdx.x]);
+}
+
+hipError_t launch_stats(const Tab &t, hipStream_t st) {
+    stats_zero_kernel<<<1, PF_STATS_LEN, 0, st>>>(t.stats);
+    stats_kernel<<<scan_blocks(t.nwords()), kBlock, 0, st>>>(t);
     return hipGetLastError();
 }
 

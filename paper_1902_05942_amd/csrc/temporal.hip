@@ -1,12 +1,13 @@
 // Temporal blend over two sets of averages (Section 3.4.1) for gfx950.
-// Work is proportional to the cells of the current frame: one lane per
-// entry of the current table's used list.
+// One lane per slot of the current table (grid-stride); lanes whose
+// occupancy bit is clear leave at once, so the work beyond a bitmap read is
+// proportional to the cells of the current frame.
 #include "pf_device.h"
 #include "pf_kernels.h"
 
 namespace pfk {
 
-constexpr uint32_t kTemporalGrid = 1024;
+constexpr uint32_t kTemporalGrid = 2048;
 
 // Searches key in a table by fingerprint, confirming with the stored key.
 __device__ __forceinline__ uint32_t find_exact(const Tab &t, uint64_t key, uint32_t f) {
@@ -22,11 +23,11 @@ __device__ __forceinline__ uint32_t find_exact(const Tab &t, uint64_t key, uint3
 
 template <bool kHasPrev>
 __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta) {
-    const uint32_t count = (uint32_t)cur.stats[PF_STAT_USED];
+    const uint32_t nslots = cur.mask + 1;
     const uint32_t stride = gridDim.x * kBlock;
     uint32_t hits = 0;
-    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < count; j += stride) {
-        const uint32_t s = cur.used[j];
+    for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < nslots; s += stride) {
+        if (((cur.occ[s >> 5] >> (s & 31)) & 1u) == 0) continue;
         const pf_cell c = cur.cell[s];
         float v0 = cell_average(c.sum[0], c.count, cur.frac_bits);
         float v1 = cell_average(c.sum[1], c.count, cur.frac_bits);
@@ -47,9 +48,13 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
         cur.blend[s] = make_float4(v0, v1, v2, (float)c.count);
     }
     if constexpr (kHasPrev) {
-        // one atomic per wavefront
-        for (int o = 32; o > 0; o >>= 1) hits += __shfl_xor(hits, o);
-        if ((threadIdx.x & 63) == 0 && hits) add_u64(&cur.stats[PF_STAT_TEMPORAL_HIT], hits);
+        // one device atomic per block, spread over 32 partial counters
+        __shared__ uint32_t s_hits;
+        if (threadIdx.x == 0) s_hits = 0;
+        __syncthreads();
+        if (hits) atomicAdd(&s_hits, hits);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_hits) add_u64(&cur.stats[PF_STAT_PART_HIT + (blockIdx.x & 31)], s_hits);
     }
 }
 

@@ -9,6 +9,14 @@ timing (inputs resident in HBM) and steps cycle through them.
 Prints one JSON line.  `value` is vertices filtered per second (valid
 vertices, i.e. those with a hit, over the whole timed region); per-kernel
 times come from HIP events on the stream the kernels run on.
+
+Other workloads (--workload):
+  hd_1080p_x3_mlp  the same frames with the learned fallback for sparse
+                   cells (4 training steps of 16384 samples and inference
+                   per frame); reports RMSE with and without it.
+  multiview_8      8 views of uneven resolution (59.5M vertex slots) in one
+                   persistent launch per frame, workgroup size and
+                   aggregation width chosen by the autotuner.
 """
 from __future__ import annotations
 
@@ -31,6 +39,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=16)
     p.add_argument("--workload", default="hd_1080p_x3")
     p.add_argument("--agg", type=int, default=64, help="aggregation width of insert (0 = none)")
+    p.add_argument("--insert", choices=("atomic", "binned"), default="atomic",
+                   help="atomic: device atomics per aggregated group; binned: LDS reduction per slot range")
     p.add_argument("--frames", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle timed on the host")
@@ -43,6 +53,8 @@ def main():
         print(f"bench.py runs on exactly one GPU (the filter has no multi-GPU path); got --gpus {a.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if a.workload == "multiview_8":
+        return main_multiview(a)
     import numpy as np
     import torch
 
@@ -59,12 +71,20 @@ def main():
     n_valid = [int(f["valid"].sum()) for f in frames]
     torch.cuda.synchronize()
 
+    use_mlp = bool(wl.extra.get("mlp"))
+    fb = None
+    if use_mlp:
+        from synth.mlp_init import init_params
+        fb = pf.MlpFallback(n, init_params(1902), batch=16384, steps=4, lr=1e-3)
     flt = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
-                         agg_width=a.agg, device=dev)
+                         agg_width=a.agg, device=dev, binned=(a.insert == "binned"))
     outs = (torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev))
+    count = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
     names = ["clear", "build_keys", "insert_accumulate", "temporal_update", "query_average"]
+    if use_mlp:
+        names.append("mlp_select_train_infer")
 
     def step(k, ev=None):
         f = frames[k % len(frames)]
@@ -79,15 +99,24 @@ def main():
                       f["seed"], 0, view.log2_slots, key, None, None, vflags)
         if ev is not None:
             ev[2].record(stream)
-        pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)
+        if flt.ws is not None:
+            pf.insert_accumulate_binned(cur, key, f["r"], f["g"], f["b"], vflags, slot, flt.ws)
+        else:
+            pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)
         if ev is not None:
             ev[3].record(stream)
         pf.temporal_update(cur, flt.prev, wl.alpha_old)
         if ev is not None:
             ev[4].record(stream)
-        pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True, outs[0], outs[1], outs[2], None)
+        pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True, outs[0], outs[1], outs[2],
+                         count if use_mlp else None)
         if ev is not None:
             ev[5].record(stream)
+        if use_mlp:
+            geo = pf.geometry(key, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["cam"])
+            fb.apply(cur, geo, vflags, count, slot, outs, f["seed"])
+            if ev is not None:
+                ev[6].record(stream)
         flt.tables.reverse()
         flt.frames += 1
 
@@ -96,7 +125,8 @@ def main():
         step(k)
     torch.cuda.synchronize()
 
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(a.steps)]
+    nev = len(names) + 1
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(a.steps)]
     print(f"[bench] timing {a.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -104,7 +134,7 @@ def main():
         step(a.warmup + k, events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = events[0][0].elapsed_time(events[-1][5])
+    gpu_ms = events[0][0].elapsed_time(events[-1][nev - 1])
     per = {nm: float(np.mean([events[k][j].elapsed_time(events[k][j + 1]) for k in range(a.steps)])) * 1e3
            for j, nm in enumerate(names)}  # microseconds
     valid_total = sum(n_valid[(a.warmup + k) % len(frames)] for k in range(a.steps))
@@ -122,6 +152,23 @@ def main():
         return float(torch.sqrt(((est - f["truth"][v]) ** 2).mean()))
     f_last = frames[(a.warmup + a.steps - 1) % len(frames)]
     q_temporal = rmse(outs, f_last)
+    mlp_info = None
+    if use_mlp:
+        sparse = (flt.vflags[:n] == 0) & (count < 4)
+        q_sparse_mlp = float(torch.sqrt(((torch.stack(outs, 1)[sparse] - f_last["truth"][sparse]) ** 2).mean()))
+        ref = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
+                             agg_width=a.agg, device=dev)
+        for k in range(a.frames):   # the moving average alone over the same frames, ending on the same one
+            fk = frames[(a.warmup + a.steps - a.frames + k) % len(frames)]
+            o_ref = ref.filter(fk["px"], fk["py"], fk["pz"], fk["nx"], fk["ny"], fk["nz"], fk["valid"], fk["r"],
+                               fk["g"], fk["b"], fk["cam"], fk["s"], fk["seed"])
+        q_sparse_ref = float(torch.sqrt(((torch.stack(o_ref, 1)[sparse] - f_last["truth"][sparse]) ** 2).mean()))
+        mlp_us = per["mlp_select_train_infer"]
+        flops = 4 * 16384 * 2 * (10240 + 15360)
+        mlp_info = {"sparse_vertices": int(sparse.sum()), "rmse_sparse_without": round(q_sparse_ref, 5),
+                    "rmse_sparse_with": round(q_sparse_mlp, 5), "rmse_all_without": round(rmse(o_ref, f_last), 5),
+                    "rmse_all_with": round(q_temporal, 5), "us_per_frame": round(mlp_us, 2),
+                    "train_flops_per_frame": flops, "loss": float(fb.net.loss().cpu()[0])}
     q_noisy = rmse((f_last["r"], f_last["g"], f_last["b"]), f_last)
     plain = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=False, agg_width=a.agg,
                            device=dev)
@@ -139,7 +186,7 @@ def main():
         "temporal_update": cells * (32 + 8 + 4 + 8 + 16 + 16) + (1 << view.log2_slots) // 8,
         "query_average": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12,
     }
-    dom = max(per, key=lambda k: per[k])
+    dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -157,15 +204,82 @@ def main():
         "config": {"workload": a.workload, "width": view.width, "height": view.height,
                    "verts_per_path": view.verts_per_path, "vertex_slots": n, "valid_vertices_mean": round(nv, 1),
                    "log2_slots": view.log2_slots, "max_probe": wl.max_probe, "frac_bits": wl.frac_bits,
-                   "frames": a.frames, "alpha_old": wl.alpha_old, "agg_width": a.agg, "parallelism": "single-gpu"},
+                   "frames": a.frames, "alpha_old": wl.alpha_old, "agg_width": a.agg, "insert": a.insert,
+                   "parallelism": "single-gpu"},
         "vertex_slots_per_s": round(n * a.steps / wall, 1),
         "gpu_ms_per_step": round(gpu_ms / a.steps, 4),
         "insert_query_vertices_per_s": round(nv / ((per["insert_accumulate"] + per["query_average"]) * 1e-6), 1),
         "kernel_us": {k: round(v, 2) for k, v in per.items()},
         "cells_last_frame": cells,
         "rmse": {"unfiltered": round(q_noisy, 5), "filtered": round(q_plain, 5), "filtered_temporal": round(q_temporal, 5)},
+        "mlp": mlp_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_multiview(a):
+    """8 views of uneven resolution, one persistent launch per frame."""
+    import numpy as np
+    import torch
+
+    import paper_1902_05942_amd as pf
+    from paper_1902_05942_amd import autotune
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = synth.get("multiview_8")
+    nfr = min(a.frames, 4)
+    shapes = [(v.width * v.height * v.verts_per_path, v.log2_slots) for v in wl.views]
+    print(f"[bench] generating {nfr} frames x {len(wl.views)} views ({sum(s for s, _ in shapes)} slots)",
+          file=sys.stderr, flush=True)
+    frames = [[synth.generate(wl, view=v, frame=i, device=dev) for v in range(len(wl.views))] for i in range(nfr)]
+    n_valid = [sum(int(f["valid"].sum()) for f in fr) for fr in frames]
+    mvf = pf.MultiViewFilter(shapes, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old, device=dev)
+    block, agg, table = autotune.tune(mvf, frames[0], reps=3, use_cache=False, verbose=True)
+    print(f"[bench] autotuned workgroup {block}, aggregation {agg}", file=sys.stderr, flush=True)
+    for k in range(a.warmup):
+        mvf.filter(frames[k % nfr], block, agg)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(a.steps):
+        mvf.filter(frames[(a.warmup + k) % nfr], block, agg)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert mvf.status() == 0
+    launch_us = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)])) * 1e3
+    valid_total = sum(n_valid[(a.warmup + k) % nfr] for k in range(a.steps))
+    n_total = sum(s for s, _ in shapes)
+    nv = float(np.mean(n_valid))
+    cells = 0
+    for pair in mvf.tables:
+        cells += int(pf.read_stats(pair[1])[pf.STAT_USED])
+    words = sum((1 << l) // 8 for _, l in shapes)
+    # per slot: position/normal/valid 25 read, key/flags/slot 13 written, lookup flags+slot 5 read, output 12
+    # written; per valid vertex: contribution 12, probe 4, cell update 28, temporal value 16; per invalid slot:
+    # own contribution 12; per cell: clear 32, temporal 84; the occupancy bitmaps read twice
+    algo = n_total * 55 + nv * 60 + (n_total - nv) * 12 + cells * 116 + 2 * words
+    achieved = algo / (launch_us * 1e-6) / 1e9
+    line = {
+        "metric": "vertices/s filtered (insert+query), 8 views in one persistent launch",
+        "value": round(valid_total / wall, 1), "unit": "vertices/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(wall * 1e3 / a.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
+        "config": {"workload": "multiview_8", "views": [[v.width, v.height, v.verts_per_path] for v in wl.views],
+                   "vertex_slots": n_total, "valid_vertices_mean": round(nv, 1), "table_slots":
+                   sum(1 << l for _, l in shapes), "block": block, "agg_width": agg, "frames": nfr,
+                   "parallelism": "single-gpu"},
+        "launch_us": round(launch_us, 2),
+        "autotune_ms": {f"{b}/{g}": round(v, 4) for (b, g), v in sorted(table.items())},
+        "roofline": {"bound": "hbm", "kernel": "views_kernel", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(algo)},
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

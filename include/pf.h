@@ -178,6 +178,26 @@ pf_status pf_insert_accumulate(const pf_table *t, const uint64_t *key, const flo
                                const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
                                uint32_t agg_width, void *stream);
 
+/* [host] Workspace bytes of pf_insert_accumulate_binned for n vertices and a
+ * table of 2^log2_slots slots; 0 when log2_slots > 25 (use
+ * pf_insert_accumulate then). */
+size_t pf_insert_workspace_bytes(uint64_t n, uint32_t log2_slots);
+
+/* The same accumulation as pf_insert_accumulate (identical table, flags and
+ * slots up to the order-dependent placement of probe collisions), without
+ * device atomics on the cell sums: vertices are binned by the slot they
+ * claim (a counting sort over tile histograms) and each bin -- a contiguous
+ * slot range -- is summed in LDS by one workgroup, which then adds count and
+ * sums to its cells with plain loads and stores and sets their occupancy
+ * bits.  Compare-and-swap remains only for claiming new cells.
+ * slot_out is required.  workspace: pf_insert_workspace_bytes(n, log2_slots)
+ * device bytes (caller-owned, no alignment needed).
+ * Errors: PF_EINVAL (NULL, misaligned, workspace too small), PF_ERANGE
+ * (log2_slots > 25). */
+pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, const float *r, const float *g,
+                                      const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
+                                      void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------ query */
 /* Lookup (Sections 3.2, 3.3.1): for each vertex with vflags == 0, finds its
  * cell (from slot[i] when slot is non-NULL, else by probing with key[i]) and
@@ -208,6 +228,160 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
  * unknown mode, differing sizes). */
 pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode,
                              void *stream);
+
+
+/* ------------------------------------------------------- learned fallback */
+/* A small BF16 network that predicts the contribution of vertices whose
+ * cell holds few samples, trained online on the averages of well-populated
+ * cells.  It is not part of the paper; it stands where Section 3.3 puts its
+ * fallbacks for voxels with a low number of vertices.
+ *
+ * Network: x [80] -> 64 (ReLU) -> 64 (ReLU) -> 3, i.e.
+ *   z1 = W1 x + b1, a1 = relu(z1), z2 = W2 a1 + b2, a2 = relu(z2),
+ *   y = W3 a2 + b3.
+ * Parameters, FP32, packed in this order (PF_MLP_NPARAM floats):
+ *   W1 [64][80], b1 [64], W2 [64][64], b2 [64], W3 [16][64], b3 [16];
+ *   rows 3..15 of W3 and entries 3..15 of b3 are padding and must be 0.
+ * Features of a vertex with key k (cell index x~, level l'), position x,
+ * normal n and camera p_cam:
+ *   p_c = (x~_c + 1/2) * 2^(l' - 10)   (the cell centre in units of s, exact)
+ *   x[6j + c] = sin(pi 2^j p_c), x[6j + 3 + c] = cos(pi 2^j p_c), j = 0..11
+ *   x[72 + c] = n_c, x[75 + c] = (x - p_cam)_c / |x - p_cam|, x[78..79] = 0
+ * evaluated in FP64 and rounded FP64 -> FP32 -> BF16 (nearest even), with
+ * zero results taken as +0.
+ * Arithmetic: BF16 operands (features, a BF16 copy of the weights, a1, a2 and
+ * the back-propagated gradients gy, gz2, gz1) on MFMA with FP32
+ * accumulation; biases, loss and gradient sums in FP32.  Loss: mean over the
+ * batch and the 3 channels of (y - target)^2.  Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) on the FP32 weights. */
+#define PF_MLP_IN 80
+#define PF_MLP_HIDDEN 64
+#define PF_MLP_NPARAM 10384
+#define PF_MLP_BLOCK_SAMPLES 64   /* training batch granularity */
+
+typedef struct pf_mlp {
+    float *w;            /* [PF_MLP_NPARAM] FP32 weights (caller fills before pf_mlp_init) */
+    uint16_t *wb;        /* [PF_MLP_NPARAM] BF16 copy used by the products */
+    float *m;            /* [PF_MLP_NPARAM] Adam first moment */
+    float *v;            /* [PF_MLP_NPARAM] Adam second moment */
+    float *partial;      /* [max_batch / 64][PF_MLP_NPARAM + 1] per-workgroup gradient and loss sums */
+    float *loss;         /* [1] mean loss of the last training step */
+    uint32_t max_batch;  /* multiple of 64 */
+    uint32_t reserved;
+} pf_mlp;
+
+/* Per-view geometry the features are computed from (device pointers, n
+ * vertices each; cam by value). */
+typedef struct pf_geometry {
+    const uint64_t *key;
+    const float *px, *py, *pz;
+    const float *nx, *ny, *nz;
+    float cam[3];
+    float reserved;
+} pf_geometry;
+
+/* [host] Arena bytes for a network trained with batches up to max_batch. */
+size_t pf_mlp_bytes(uint32_t max_batch);
+
+/* [host] Carves *m out of `arena` (pf_mlp_bytes(max_batch) bytes).
+ * Errors: PF_EINVAL (NULL), PF_ERANGE (max_batch 0, not a multiple of 64,
+ * or above 2^20). */
+pf_status pf_mlp_carve(void *arena, uint32_t max_batch, pf_mlp *m);
+
+/* Zeroes the Adam moments and the loss and rounds the FP32 weights (already
+ * written to m->w by the caller) into the BF16 copy. */
+pf_status pf_mlp_init(const pf_mlp *m, void *stream);
+
+/* [host] Workspace bytes of pf_mlp_select for n vertices. */
+size_t pf_mlp_select_workspace_bytes(uint64_t n);
+
+/* Lists, in ascending vertex order, the vertices with vflags == 0 whose
+ * cell count (from pf_query_average's count_out) is >= train_from
+ * (train_idx) and those whose count is < sparse_below (sparse_idx); writes
+ * the two list lengths to counts[0] and counts[1] (device).  Lists hold up to
+ * n entries each.  Workspace: pf_mlp_select_workspace_bytes(n) device bytes.
+ * Errors: PF_EINVAL (NULL, misaligned, n too large). */
+pf_status pf_mlp_select(const uint8_t *vflags, const uint32_t *count, uint64_t n, uint32_t sparse_below,
+                        uint32_t train_from, uint32_t *train_idx, uint32_t *sparse_idx, uint32_t *counts,
+                        void *workspace, void *stream);
+
+/* One training step on `batch` samples (a multiple of 64, <= max_batch).
+ * Sample j is vertex train_idx[(u * counts[0]) >> 32] with u the first
+ * output of PCG32 seeded with (seed, j); its target is the plain average
+ * (sum / count, as in the lookup) of its cell in table t at slot[vertex]
+ * (pf_insert_accumulate's slot_out).  Computes the loss gradient in fixed
+ * order (deterministic), then one Adam step with bias corrections for step
+ * number `step` (>= 1) and learning rate lr, and refreshes the BF16 copy.
+ * A step with counts[0] == 0 changes nothing.
+ * Errors: PF_EINVAL (NULL), PF_ERANGE (batch, step, lr). */
+pf_status pf_mlp_train_step(const pf_mlp *m, const pf_table *t, const pf_geometry *g, const uint32_t *slot,
+                            const uint32_t *train_idx, const uint32_t *counts, uint32_t batch, uint64_t seed,
+                            uint32_t step, float lr, void *stream);
+
+/* The network's input features (BF16 bit patterns, [n][PF_MLP_IN]) of the
+ * n vertices listed in idx, as the training and inference kernels compute
+ * them.  For inspection and tests.
+ * Errors: PF_EINVAL (NULL, misaligned), PF_ERANGE (n * PF_MLP_IN >= 2^32). */
+pf_status pf_mlp_features(const pf_geometry *g, const uint32_t *idx, uint64_t n, uint16_t *out, void *stream);
+
+/* Inference for the counts[1] vertices listed in sparse_idx (n_max bounds
+ * the list): y = network(features); when all three outputs are finite the
+ * vertex's r, g, b become max(0, y_c), otherwise they are left unchanged.
+ * Errors: PF_EINVAL (NULL, misaligned), PF_ERANGE (n_max too large). */
+pf_status pf_mlp_infer(const pf_mlp *m, const pf_geometry *g, const uint32_t *sparse_idx, const uint32_t *counts,
+                       uint64_t n_max, float *r, float *gch, float *b, void *stream);
+
+
+/* ----------------------------------------------------------- many views */
+/* One view of a batched launch: its vertex streams (SoA, n each), its
+ * outputs, its key parameters and its tables.  Tables of all views may be
+ * carved from one arena. */
+typedef struct pf_view {
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    const uint8_t *valid;     /* nullable */
+    const float *r, *g, *b;   /* contributions */
+    uint64_t *key;            /* [n] out */
+    uint8_t *vflags;          /* [n] out */
+    uint32_t *slot;           /* [n] out: cell of each vertex, 0xffffffff if unfiltered */
+    float *r_out, *g_out, *b_out;  /* [n] out; must not alias r, g, b */
+    uint32_t *count_out;      /* [n] out, nullable */
+    pf_table cur;             /* cleared, then filled by this launch */
+    pf_table prev;            /* previous frame (read only); prev.cell == NULL: none */
+    pf_key_params kp;
+    uint32_t n;               /* vertices (< 2^32) */
+    float alpha_old;          /* moving-average weight of the previous value */
+    int32_t temporal;         /* 1: lookup returns the moving average (cur needs a blend array) */
+    uint32_t reserved;
+} pf_view;
+
+#define PF_MAX_VIEWS 64
+
+/* [host] Device workspace bytes of pf_filter_views for nviews views (barrier
+ * counters and the device copy of the descriptors). */
+size_t pf_views_workspace_bytes(uint32_t nviews);
+
+/* Filters nviews views in ONE persistent launch (a cooperative grid of
+ * resident workgroups of `block` threads): per view it clears `cur`, builds
+ * the keys and inserts every vertex (as pf_build_keys + pf_insert_accumulate
+ * with aggregation width agg_width), computes the temporal values when
+ * temporal is set (as pf_temporal_update, mode 0), and looks up every vertex
+ * (as pf_query_average with the slots).  Phases are separated by grid-wide
+ * barriers; the work items of all views are spread over all workgroups.
+ * Results equal those of the single-view calls.
+ * views: [host] array of nviews descriptors, validated on the host and
+ * copied into the workspace before the call returns.  block in
+ * {64, 128, 256, 512, 1024}; agg_width 0 or a power of two <= block;
+ * grid_per_cu: workgroups per compute unit (0 = as many as fit).
+ * workspace: pf_views_workspace_bytes(nviews) device bytes, 256-byte
+ * aligned; its first uint32 is a status word, non-zero if a barrier wait
+ * ever exceeded its bound (every workgroup then stops; with a cooperative
+ * launch all workgroups are resident, so it stays 0); the next words hold
+ * the grid size and, after a timed-out wait, the arrivals that were seen.
+ * Errors: PF_EINVAL (NULL, misaligned, inconsistent descriptor), PF_ERANGE
+ * (nviews 0 or above PF_MAX_VIEWS, block, agg_width, parameters),
+ * PF_ELAUNCH. */
+pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
+                          uint32_t grid_per_cu, void *workspace, void *stream);
 
 /* ------------------------------------------------------------ diagnostics */
 /* Derives USED, DISP and HIST from the table (occupancy bitmap and keys),

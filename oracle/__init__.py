@@ -46,6 +46,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         u64, u32, i32, f32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
         L.orc_pcg32_outputs.argtypes = [u64, u64, u32, vp]
+        L.orc_pcg32_first.argtypes = [u64, u64, vp]
         L.orc_fmix64.argtypes = [u64]; L.orc_fmix64.restype = u64
         L.orc_splitmix64.argtypes = [u64]; L.orc_splitmix64.restype = u64
         L.orc_level_of_detail.argtypes = [vp, f32, f32, f32]; L.orc_level_of_detail.restype = ctypes.c_int
@@ -73,6 +74,13 @@ def pcg32_outputs(initstate: int, initseq: int, count: int) -> np.ndarray:
     out = np.zeros(count, np.uint32)
     lib().orc_pcg32_outputs(initstate, initseq, count, _p(out))
     return out
+
+
+def pcg32_first(initstate: int, n: int) -> np.ndarray:
+    """First PCG32 output for streams 0..n-1 under one initial state."""
+    out = np.zeros(max(n, 1), np.uint32)
+    lib().orc_pcg32_first(initstate, n, _p(out))
+    return out[:n].copy()
 
 
 def fmix64(k: int) -> int:

@@ -24,7 +24,8 @@ units of s is (x~ + 1/2) 2^l'; p = (x~ + 1/2) 2^(l' - 10) is exact in binary32;
 features are sin(pi 2^k p) and cos(pi 2^k p) for k = 0..11 (feature
 6k + c is the sine of axis c, 6k + 3 + c its cosine), evaluated in float64
 after exact argument reduction (exact at integer and half-integer phases),
-and rounded float64 -> float32 -> bfloat16.  The view direction is
+and rounded float64 -> float32 -> bfloat16, zeros taken as +0.  The view
+direction is
 (x - cam) / |x - cam| in float64, rounded the same way.
 """
 from __future__ import annotations
@@ -98,8 +99,9 @@ def features(key, pos, nrm, cam) -> np.ndarray:
         x[:, 6 * k + 3: 6 * k + 6] = cospi(t)
     x[:, 72:75] = np.asarray(nrm, np.float32).astype(np.float64)
     d = np.asarray(pos, np.float32).astype(np.float64) - np.asarray(cam, np.float32).astype(np.float64)[None, :]
-    x[:, 75:78] = d / np.sqrt((d * d).sum(1, keepdims=True))
-    return to_bf16_via_f32(x)
+    ss = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    x[:, 75:78] = d / np.sqrt(ss)[:, None]
+    return to_bf16_via_f32(x + 0.0)              # zeros are +0 (IEEE: -0 + 0 = +0)
 
 
 # ------------------------------------------------------------------ parameters

@@ -87,6 +87,16 @@ void orc_pcg32_outputs(uint64_t initstate, uint64_t initseq, uint32_t count, uin
     for (uint32_t i = 0; i < count; ++i) out[i] = orc_pcg32_next(&g);
 }
 
+/* first output of the generator seeded with (initstate, stream j), j = 0..n-1 */
+void orc_pcg32_first(uint64_t initstate, uint64_t n, uint32_t *out)
+{
+    for (uint64_t j = 0; j < n; ++j) {
+        orc_pcg32 g;
+        orc_pcg32_seed(&g, initstate, j);
+        out[j] = orc_pcg32_next(&g);
+    }
+}
+
 /* MurmurHash3's 64-bit finaliser (Appleby, public domain). */
 uint64_t orc_fmix64(uint64_t k)
 {

@@ -11,8 +11,37 @@ import torch
 
 from . import _lib
 from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_USED, V_INVALID, V_KEYRANGE,  # noqa
-                   V_OVERFLOW, V_RADRANGE, PfError, Table, build_keys, clear, insert_accumulate, query_average,
-                   read_stats, table_init, temporal_update, version)
+                   V_OVERFLOW, V_RADRANGE, Mlp, PfError, Table, build_keys, clear, geometry, insert_accumulate,
+                   mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
+                   query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
+                   filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned)
+
+
+class MlpFallback:
+    """Online-trained network for vertices in sparse cells: per frame, list
+    the vertices of well-populated cells (count >= train_from) and of sparse
+    cells (count < sparse_below), run `steps` training steps of `batch`
+    samples, then replace the sparse vertices' output by the prediction."""
+
+    def __init__(self, n_max: int, weights, batch: int = 16384, steps: int = 4, lr: float = 1e-3,
+                 sparse_below: int = 4, train_from: int = 16, device="cuda"):
+        self.net = Mlp(batch, device)
+        mlp_init(self.net, weights)
+        self.batch, self.steps, self.lr = batch, steps, lr
+        self.sparse_below, self.train_from = sparse_below, train_from
+        self.train_idx = torch.empty(max(n_max, 1), dtype=torch.int32, device=device)
+        self.sparse_idx = torch.empty(max(n_max, 1), dtype=torch.int32, device=device)
+        self.counts = torch.zeros(2, dtype=torch.int32, device=device)
+        self.ws = torch.empty(max(mlp_select_workspace_bytes(n_max), 4), dtype=torch.uint8, device=device)
+
+    def apply(self, table, geo, vflags, count, slot, out, seed):
+        n = vflags.numel()
+        mlp_select(vflags, count, self.sparse_below, self.train_from, self.train_idx[:n], self.sparse_idx[:n],
+                   self.counts, self.ws)
+        for k in range(self.steps):
+            mlp_train_step(self.net, table, geo, slot, self.train_idx[:n], self.counts, self.batch,
+                           (int(seed) ^ ((k + 1) * 0x9E3779B97F4A7C15)) & 0xFFFFFFFFFFFFFFFF, self.lr)
+        mlp_infer(self.net, geo, self.sparse_idx[:n], self.counts, out[0], out[1], out[2])
 
 
 class FrameFilter:
@@ -25,7 +54,8 @@ class FrameFilter:
     """
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
-                 temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda"):
+                 temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
+                 mlp: "MlpFallback | None" = None, binned: bool = False):
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device) for _ in range(2 if temporal else 1)]
         for t in self.tables:
             table_init(t)
@@ -38,6 +68,13 @@ class FrameFilter:
         self.slot = torch.empty(n_max, dtype=torch.int32, device=device)
         self.count = torch.empty(n_max, dtype=torch.int32, device=device)
         self.frames = 0
+        self.mlp = mlp
+        self.ws = None
+        if binned:
+            nb = insert_workspace_bytes(n_max, log2_slots)
+            if nb == 0:
+                raise PfError("pf_insert_workspace_bytes", _lib.PF_ERANGE)
+            self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
 
     @property
     def cur(self) -> Table:
@@ -52,17 +89,92 @@ class FrameFilter:
         """Filters one frame; returns (r_out, g_out, b_out) (in place if out is (r, g, b))."""
         n = px.numel()
         key, vflags, slot = self.key[:n], self.vflags[:n], self.slot[:n]
-        cnt = self.count[:n] if with_count else None
+        cnt = self.count[:n] if (with_count or self.mlp is not None) else None
         cur = self.cur
         clear(cur)
         build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, self.log2_slots, key, None, None, vflags)
-        insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
+        if self.ws is not None:
+            insert_accumulate_binned(cur, key, r, g, b, vflags, slot, self.ws)
+        else:
+            insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
         if self.temporal:
             temporal_update(cur, self.prev, self.alpha_old)
         if out is None:
             out = (torch.empty_like(r), torch.empty_like(g), torch.empty_like(b))
         query_average(cur, key, slot, r, g, b, vflags, self.temporal, out[0], out[1], out[2], cnt)
+        if self.mlp is not None:
+            geo = geometry(key, px, py, pz, nx, ny, nz, cam)
+            self.mlp.apply(cur, geo, vflags, cnt, slot, out, seed)
         if self.temporal:
             self.tables.reverse()
         self.frames += 1
         return out
+
+
+class MultiViewFilter:
+    """Many views filtered by one persistent launch per frame.
+
+    Each view has two tables (current, previous) carved from ONE arena, and
+    its own key/flag/slot/count/output buffers.  filter() takes one frame dict
+    per view (device streams px..nz, valid, r, g, b and cam, s, seed) and runs
+    pf_filter_views with the given workgroup size and aggregation width, then
+    swaps every view's tables.
+    """
+
+    def __init__(self, views, max_probe: int = 64, frac_bits: int = 24, temporal: bool = True,
+                 alpha_old: float = 0.2, device="cuda"):
+        # views: list of (n_max, log2_slots)
+        self.temporal, self.alpha_old = temporal, alpha_old
+        sizes = [table_bytes(l, True) for _, l in views]
+        ntab = 2 if temporal else 1
+        total = sum(sizes) * ntab
+        self.arena = torch.empty(total, dtype=torch.uint8, device=device)
+        self.tables, off = [], 0
+        for (n, l), sz in zip(views, sizes):
+            pair = []
+            for _ in range(ntab):
+                pair.append(Table(l, max_probe, frac_bits, True, device, arena=self.arena[off:off + sz]))
+                table_init(pair[-1])
+                off += sz
+            self.tables.append(pair)
+        self.bufs = []
+        for n, _ in views:
+            self.bufs.append({
+                "key": torch.empty(n, dtype=torch.int64, device=device),
+                "vflags": torch.empty(n, dtype=torch.uint8, device=device),
+                "slot": torch.empty(n, dtype=torch.int32, device=device),
+                "count": torch.empty(n, dtype=torch.int32, device=device),
+                "out": tuple(torch.empty(n, dtype=torch.float32, device=device) for _ in range(3)),
+            })
+        ws = views_workspace_bytes(len(views))
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self.ws = self.workspace[(-base) % 256:][:ws]
+        self.frames = 0
+
+    def descriptors(self, frames, with_count=False):
+        descs = []
+        for v, f in enumerate(frames):
+            b = self.bufs[v]
+            n = f["px"].numel()
+            pair = self.tables[v]
+            prev = pair[1] if (self.temporal and self.frames > 0) else None
+            descs.append(make_view(f, b["key"][:n], b["vflags"][:n], b["slot"][:n],
+                                   tuple(o[:n] for o in b["out"]), pair[0], prev,
+                                   b["count"][:n] if with_count else None, self.temporal, self.alpha_old))
+        return descs
+
+    def filter(self, frames, block=256, agg_width=64, with_count=False, grid_per_cu=0):
+        filter_views(self.descriptors(frames, with_count), block, agg_width, self.ws, grid_per_cu)
+        if self.temporal:
+            for pair in self.tables:
+                pair.reverse()
+        self.frames += 1
+        return [tuple(o[:f["px"].numel()] for o in b["out"]) for b, f in zip(self.bufs, frames)]
+
+    def status(self) -> int:
+        return int(self.ws[:4].view(torch.int32).cpu()[0])
+
+    def status_words(self):
+        """status, grid size, arrivals seen by a timed-out wait, its barrier number."""
+        return [int(x) for x in self.ws[:16].view(torch.int32).cpu()]

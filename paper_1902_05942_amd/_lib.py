@@ -39,6 +39,31 @@ class pf_key_params(ctypes.Structure):
                 ("idx_base", ctypes.c_uint64)]
 
 
+class pf_mlp(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("wb", ctypes.c_void_p), ("m", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("partial", ctypes.c_void_p), ("loss", ctypes.c_void_p), ("max_batch", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class pf_geometry(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
+                ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p), ("nz", ctypes.c_void_p),
+                ("cam", ctypes.c_float * 3), ("reserved", ctypes.c_float)]
+
+
+MLP_NPARAM, MLP_IN, MLP_BLOCK_SAMPLES = 10384, 80, 64
+
+
+class pf_view(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("px", "py", "pz", "nx", "ny", "nz", "valid", "r", "g", "b", "key",
+                                                "vflags", "slot", "r_out", "g_out", "b_out", "count_out")] + [
+        ("cur", pf_table), ("prev", pf_table), ("kp", pf_key_params), ("n", ctypes.c_uint32),
+        ("alpha_old", ctypes.c_float), ("temporal", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+MAX_VIEWS = 64
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
@@ -55,9 +80,22 @@ def _load():
         "pf_clear": ([T, vp], i),
         "pf_build_keys": ([vp] * 7 + [u64, ctypes.POINTER(pf_key_params), u32, vp, vp, vp, vp, vp], i),
         "pf_insert_accumulate": ([T, vp, vp, vp, vp, vp, vp, u64, u32, vp], i),
+        "pf_insert_workspace_bytes": ([u64, u32], ctypes.c_size_t),
+        "pf_insert_accumulate_binned": ([T, vp, vp, vp, vp, vp, vp, u64, vp, ctypes.c_size_t, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
+        "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
+        "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, vp], i),
+        "pf_mlp_bytes": ([u32], ctypes.c_size_t),
+        "pf_mlp_carve": ([vp, u32, ctypes.POINTER(pf_mlp)], i),
+        "pf_mlp_init": ([ctypes.POINTER(pf_mlp), vp], i),
+        "pf_mlp_select_workspace_bytes": ([u64], ctypes.c_size_t),
+        "pf_mlp_select": ([vp, vp, u64, u32, u32, vp, vp, vp, vp, vp], i),
+        "pf_mlp_train_step": ([ctypes.POINTER(pf_mlp), T, ctypes.POINTER(pf_geometry), vp, vp, vp, u32, u64, u32, f32,
+                               vp], i),
+        "pf_mlp_features": ([ctypes.POINTER(pf_geometry), vp, u64, vp, vp], i),
+        "pf_mlp_infer": ([ctypes.POINTER(pf_mlp), ctypes.POINTER(pf_geometry), vp, vp, u64, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -69,7 +107,10 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "pf_clear", "pf_build_keys",
-            "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats")
+            "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats", "pf_mlp_bytes",
+            "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
+            "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
+            "pf_insert_workspace_bytes", "pf_insert_accumulate_binned")
 
 
 def _ptr(t):
@@ -169,6 +210,16 @@ def insert_accumulate(t: Table, key, r, g, b, vflags, slot_out=None, agg_width=0
                                                             _stream(stream)))
 
 
+def insert_workspace_bytes(n: int, log2_slots: int) -> int:
+    return int(lib.pf_insert_workspace_bytes(n, log2_slots))
+
+
+def insert_accumulate_binned(t: Table, key, r, g, b, vflags, slot_out, workspace, stream=None):
+    _check("pf_insert_accumulate_binned", lib.pf_insert_accumulate_binned(
+        t.ref, _ptr(key), _ptr(r), _ptr(g), _ptr(b), _ptr(vflags), _ptr(slot_out), key.numel(), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_out, g_out, b_out, count_out=None,
                   stream=None):
     n = vflags.numel()
@@ -187,3 +238,123 @@ def read_stats(t: Table, stream=None):
     out = np.zeros(STATS_LEN, np.uint64)
     _check("pf_read_stats", lib.pf_read_stats(t.ref, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- learned fallback
+def geometry(key, px, py, pz, nx, ny, nz, cam):
+    g = pf_geometry()
+    g.key, g.px, g.py, g.pz = key.data_ptr(), px.data_ptr(), py.data_ptr(), pz.data_ptr()
+    g.nx, g.ny, g.nz = nx.data_ptr(), ny.data_ptr(), nz.data_ptr()
+    for c in range(3):
+        g.cam[c] = float(cam[c])
+    g._keep = (key, px, py, pz, nx, ny, nz)
+    return g
+
+
+class Mlp:
+    """One network arena (a torch uint8 tensor) carved into the pf_mlp views."""
+
+    def __init__(self, max_batch: int = 16384, device="cuda"):
+        nbytes = int(lib.pf_mlp_bytes(max_batch))
+        if nbytes == 0:
+            raise PfError("pf_mlp_bytes", PF_ERANGE)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.m = pf_mlp()
+        _check("pf_mlp_carve", lib.pf_mlp_carve(_ptr(self.arena), max_batch, ctypes.byref(self.m)))
+        self.max_batch = max_batch
+        self.steps = 0
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.m)
+
+    def _view(self, addr, n, dtype, itemsize):
+        off = addr - self.arena.data_ptr()
+        return self.arena[off:off + n * itemsize].view(dtype)
+
+    def weights(self) -> torch.Tensor:
+        return self._view(self.m.w, MLP_NPARAM, torch.float32, 4)
+
+    def weights_bf16(self) -> torch.Tensor:
+        return self._view(self.m.wb, MLP_NPARAM, torch.int16, 2)
+
+    def moments(self):
+        return self._view(self.m.m, MLP_NPARAM, torch.float32, 4), self._view(self.m.v, MLP_NPARAM, torch.float32, 4)
+
+    def partials(self, nblocks) -> torch.Tensor:
+        return self._view(self.m.partial, nblocks * (MLP_NPARAM + 1), torch.float32, 4).view(nblocks, MLP_NPARAM + 1)
+
+    def loss(self) -> torch.Tensor:
+        return self._view(self.m.loss, 1, torch.float32, 4)
+
+
+def mlp_init(m: Mlp, weights, stream=None):
+    """Copies the FP32 weights in, then pf_mlp_init (moments to zero, BF16 copy)."""
+    w = torch.as_tensor(weights, dtype=torch.float32).reshape(-1)
+    m.weights().copy_(w.to(m.arena.device))
+    m.steps = 0
+    _check("pf_mlp_init", lib.pf_mlp_init(m.ref, _stream(stream)))
+
+
+def mlp_select_workspace_bytes(n: int) -> int:
+    return int(lib.pf_mlp_select_workspace_bytes(n))
+
+
+def mlp_select(vflags, count, sparse_below, train_from, train_idx, sparse_idx, counts, workspace, stream=None):
+    n = vflags.numel()
+    _check("pf_mlp_select", lib.pf_mlp_select(_ptr(vflags), _ptr(count), n, sparse_below, train_from, _ptr(train_idx),
+                                              _ptr(sparse_idx), _ptr(counts), _ptr(workspace), _stream(stream)))
+
+
+def mlp_train_step(m: Mlp, t: Table, geo, slot, train_idx, counts, batch, seed, lr, step=None, stream=None):
+    if step is None:
+        m.steps += 1
+        step = m.steps
+    _check("pf_mlp_train_step", lib.pf_mlp_train_step(m.ref, t.ref, ctypes.byref(geo), _ptr(slot), _ptr(train_idx),
+                                                      _ptr(counts), batch, int(seed) & 0xFFFFFFFFFFFFFFFF, step,
+                                                      float(lr), _stream(stream)))
+
+
+def mlp_features(geo, idx, out, stream=None):
+    _check("pf_mlp_features", lib.pf_mlp_features(ctypes.byref(geo), _ptr(idx), idx.numel(), _ptr(out),
+                                                  _stream(stream)))
+
+
+def mlp_infer(m: Mlp, geo, sparse_idx, counts, r, g, b, stream=None):
+    _check("pf_mlp_infer", lib.pf_mlp_infer(m.ref, ctypes.byref(geo), _ptr(sparse_idx), _ptr(counts),
+                                            sparse_idx.numel(), _ptr(r), _ptr(g), _ptr(b), _stream(stream)))
+
+
+# ---------------------------------------------------------------- many views
+def views_workspace_bytes(nviews: int) -> int:
+    return int(lib.pf_views_workspace_bytes(nviews))
+
+
+def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, temporal=True, alpha_old=0.2,
+              idx_base=0):
+    """Descriptor of one view; f holds px..nz, valid, r, g, b (device) and cam, s, seed."""
+    d = pf_view()
+    for name in ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b"):
+        setattr(d, name, f[name].data_ptr())
+    d.valid = f["valid"].data_ptr() if f.get("valid") is not None else None
+    d.key, d.vflags, d.slot = key.data_ptr(), vflags.data_ptr(), slot.data_ptr()
+    d.r_out, d.g_out, d.b_out = out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr()
+    d.count_out = count_out.data_ptr() if count_out is not None else None
+    d.cur = cur.t
+    if prev is not None:
+        d.prev = prev.t
+    for c in range(3):
+        d.kp.cam[c] = float(f["cam"][c])
+    d.kp.s = float(f["s"])
+    d.kp.seed = int(f["seed"]) & 0xFFFFFFFFFFFFFFFF
+    d.kp.idx_base = int(idx_base)
+    d.n = key.numel()
+    d.alpha_old = float(alpha_old)
+    d.temporal = int(bool(temporal))
+    return d
+
+
+def filter_views(descs, block, agg_width, workspace, grid_per_cu=0, stream=None):
+    arr = (pf_view * len(descs))(*descs)
+    _check("pf_filter_views", lib.pf_filter_views(arr, len(descs), block, agg_width, grid_per_cu, _ptr(workspace),
+                                                  _stream(stream)))

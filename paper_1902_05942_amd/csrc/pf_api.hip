@@ -142,6 +142,26 @@ pf_status pf_insert_accumulate(const pf_table *t, const uint64_t *key, const flo
                                        (hipStream_t)stream));
 }
 
+size_t pf_insert_workspace_bytes(uint64_t n, uint32_t log2_slots) {
+    if (n > kMaxN || log2_slots < 4) return 0;
+    return pfk::binned_workspace_bytes((uint32_t)n, log2_slots);
+}
+
+pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, const float *r, const float *g,
+                                      const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
+                                      void *workspace, size_t workspace_bytes, void *stream) {
+    const pf_status s = check_table(t);
+    if (s != PF_OK) return s;
+    if (n > kMaxN) return PF_EINVAL;
+    const size_t need = pf_insert_workspace_bytes(n, t->log2_slots);
+    if (need == 0) return PF_ERANGE;
+    if (n == 0) return PF_OK;
+    if (!key || !r || !g || !b || !vflags || !slot_out || !workspace || workspace_bytes < need) return PF_EINVAL;
+    if (!aligned(key) || !aligned(r) || !aligned(g) || !aligned(b) || !aligned(slot_out)) return PF_EINVAL;
+    return launched(pfk::launch_insert_binned(to_tab(t), key, r, g, b, vflags, slot_out, (uint32_t)n, workspace,
+                                              (hipStream_t)stream));
+}
+
 pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_t *slot, const float *r_in,
                            const float *g_in, const float *b_in, const uint8_t *vflags, uint64_t n, int use_blend,
                            float *r_out, float *g_out, float *b_out, uint32_t *count_out, void *stream) {
@@ -173,6 +193,193 @@ pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float al
     Tab p;
     if (prev) p = to_tab(prev);
     return launched(pfk::launch_temporal(to_tab(cur), prev ? &p : nullptr, alpha_old, mode, (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ learned fallback
+namespace {
+size_t mlp_partial_floats(uint32_t max_batch) { return (size_t)(max_batch / PF_MLP_BLOCK_SAMPLES) * (PF_MLP_NPARAM + 1); }
+
+bool mlp_ok(const pf_mlp *m) {
+    return m && m->w && m->wb && m->m && m->v && m->partial && m->loss && m->max_batch &&
+           m->max_batch % PF_MLP_BLOCK_SAMPLES == 0 && aligned(m->w) && aligned(m->wb) && aligned(m->m) &&
+           aligned(m->v) && aligned(m->partial) && aligned(m->loss);
+}
+
+pfk::MlpArgs to_mlp(const pf_mlp *m) {
+    pfk::MlpArgs a;
+    a.w = m->w;
+    a.wb = m->wb;
+    a.m = m->m;
+    a.v = m->v;
+    a.partial = m->partial;
+    a.loss = m->loss;
+    a.max_batch = m->max_batch;
+    return a;
+}
+
+bool geo_ok(const pf_geometry *g) {
+    return g && g->key && g->px && g->py && g->pz && g->nx && g->ny && g->nz && aligned(g->key) && aligned(g->px) &&
+           aligned(g->py) && aligned(g->pz) && aligned(g->nx) && aligned(g->ny) && aligned(g->nz) &&
+           isfinite(g->cam[0]) && isfinite(g->cam[1]) && isfinite(g->cam[2]);
+}
+
+pfk::GeoArgs to_geo(const pf_geometry *g) {
+    pfk::GeoArgs a;
+    a.key = g->key;
+    a.px = g->px;
+    a.py = g->py;
+    a.pz = g->pz;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.nz = g->nz;
+    for (int c = 0; c < 3; ++c) a.cam[c] = g->cam[c];
+    return a;
+}
+}  // namespace
+
+size_t pf_mlp_bytes(uint32_t max_batch) {
+    if (max_batch == 0 || max_batch % PF_MLP_BLOCK_SAMPLES || max_batch > (1u << 20)) return 0;
+    size_t b = 256;
+    b += align_up(PF_MLP_NPARAM * sizeof(float), 256) * 3;   // w, m, v
+    b += align_up(PF_MLP_NPARAM * sizeof(uint16_t), 256);    // wb
+    b += align_up(mlp_partial_floats(max_batch) * sizeof(float), 256);
+    b += 256;                                                // loss
+    return b;
+}
+
+pf_status pf_mlp_carve(void *arena, uint32_t max_batch, pf_mlp *m) {
+    if (!arena || !m) return PF_EINVAL;
+    if (pf_mlp_bytes(max_batch) == 0) return PF_ERANGE;
+    uintptr_t p = align_up(reinterpret_cast<uintptr_t>(arena), 256);
+    memset(m, 0, sizeof(*m));
+    m->w = reinterpret_cast<float *>(p);
+    p += align_up(PF_MLP_NPARAM * sizeof(float), 256);
+    m->m = reinterpret_cast<float *>(p);
+    p += align_up(PF_MLP_NPARAM * sizeof(float), 256);
+    m->v = reinterpret_cast<float *>(p);
+    p += align_up(PF_MLP_NPARAM * sizeof(float), 256);
+    m->wb = reinterpret_cast<uint16_t *>(p);
+    p += align_up(PF_MLP_NPARAM * sizeof(uint16_t), 256);
+    m->partial = reinterpret_cast<float *>(p);
+    p += align_up(mlp_partial_floats(max_batch) * sizeof(float), 256);
+    m->loss = reinterpret_cast<float *>(p);
+    m->max_batch = max_batch;
+    return PF_OK;
+}
+
+pf_status pf_mlp_init(const pf_mlp *m, void *stream) {
+    if (!mlp_ok(m)) return PF_EINVAL;
+    return launched(pfk::launch_mlp_init(to_mlp(m), (hipStream_t)stream));
+}
+
+size_t pf_mlp_select_workspace_bytes(uint64_t n) {
+    if (n > kMaxN) return 0;
+    return (size_t)2 * pfk::mlp_select_blocks((uint32_t)n) * sizeof(uint32_t) + 4;
+}
+
+pf_status pf_mlp_select(const uint8_t *vflags, const uint32_t *count, uint64_t n, uint32_t sparse_below,
+                        uint32_t train_from, uint32_t *train_idx, uint32_t *sparse_idx, uint32_t *counts,
+                        void *workspace, void *stream) {
+    if (n > kMaxN) return PF_EINVAL;
+    if (!counts || !aligned(counts)) return PF_EINVAL;
+    if (n > 0 && (!vflags || !count || !train_idx || !sparse_idx || !workspace)) return PF_EINVAL;
+    if ((count && !aligned(count)) || (train_idx && !aligned(train_idx)) || (sparse_idx && !aligned(sparse_idx)) ||
+        (workspace && !aligned(reinterpret_cast<uint32_t *>(workspace))))
+        return PF_EINVAL;
+    return launched(pfk::launch_mlp_select(vflags, count, (uint32_t)n, sparse_below, train_from, train_idx,
+                                           sparse_idx, counts, reinterpret_cast<uint32_t *>(workspace),
+                                           (hipStream_t)stream));
+}
+
+pf_status pf_mlp_train_step(const pf_mlp *m, const pf_table *t, const pf_geometry *g, const uint32_t *slot,
+                            const uint32_t *train_idx, const uint32_t *counts, uint32_t batch, uint64_t seed,
+                            uint32_t step, float lr, void *stream) {
+    if (!mlp_ok(m)) return PF_EINVAL;
+    pf_status s = check_table(t);
+    if (s != PF_OK) return s;
+    if (!geo_ok(g) || !slot || !train_idx || !counts || !aligned(slot) || !aligned(train_idx) || !aligned(counts))
+        return PF_EINVAL;
+    if (batch == 0 || batch % PF_MLP_BLOCK_SAMPLES || batch > m->max_batch) return PF_ERANGE;
+    if (step == 0 || !(lr > 0.0f) || !isfinite(lr)) return PF_ERANGE;
+    return launched(pfk::launch_mlp_train(to_mlp(m), to_tab(t), to_geo(g), slot, train_idx, counts, batch, seed,
+                                          step, lr, (hipStream_t)stream));
+}
+
+pf_status pf_mlp_features(const pf_geometry *g, const uint32_t *idx, uint64_t n, uint16_t *out, void *stream) {
+    if (n > kMaxN / PF_MLP_IN) return PF_ERANGE;
+    if (n == 0) return PF_OK;
+    if (!geo_ok(g) || !idx || !out || !aligned(idx) || !aligned(out)) return PF_EINVAL;
+    return launched(pfk::launch_mlp_features(to_geo(g), idx, (uint32_t)n, out, (hipStream_t)stream));
+}
+
+pf_status pf_mlp_infer(const pf_mlp *m, const pf_geometry *g, const uint32_t *sparse_idx, const uint32_t *counts,
+                       uint64_t n_max, float *r, float *gch, float *b, void *stream) {
+    if (!mlp_ok(m)) return PF_EINVAL;
+    if (n_max > kMaxN) return PF_ERANGE;
+    if (!geo_ok(g) || !sparse_idx || !counts || !r || !gch || !b || !aligned(sparse_idx) || !aligned(counts) ||
+        !aligned(r) || !aligned(gch) || !aligned(b))
+        return PF_EINVAL;
+    if (n_max == 0) return PF_OK;
+    return launched(pfk::launch_mlp_infer(to_mlp(m), to_geo(g), sparse_idx, counts, (uint32_t)n_max, r, gch, b,
+                                          (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ many views
+static_assert(sizeof(pf_view) == 296, "pf_view layout is part of the ABI");
+static_assert(sizeof(pf_table) == 56, "pf_table layout is part of the ABI");
+
+size_t pf_views_workspace_bytes(uint32_t nviews) {
+    if (nviews == 0 || nviews > PF_MAX_VIEWS) return 0;
+    return align_up(pfk::views_counter_bytes(), 256) + align_up(nviews * sizeof(pf_view), 256);
+}
+
+namespace {
+pf_status check_view(const pf_view &d) {
+    if (!d.px || !d.py || !d.pz || !d.nx || !d.ny || !d.nz || !d.r || !d.g || !d.b || !d.key || !d.vflags ||
+        !d.slot || !d.r_out || !d.g_out || !d.b_out)
+        return PF_EINVAL;
+    if (!aligned(d.px) || !aligned(d.py) || !aligned(d.pz) || !aligned(d.nx) || !aligned(d.ny) || !aligned(d.nz) ||
+        !aligned(d.r) || !aligned(d.g) || !aligned(d.b) || !aligned(d.key) || !aligned(d.slot) ||
+        !aligned(d.r_out) || !aligned(d.g_out) || !aligned(d.b_out) || (d.count_out && !aligned(d.count_out)))
+        return PF_EINVAL;
+    if (d.r_out == d.r || d.g_out == d.g || d.b_out == d.b) return PF_EINVAL;
+    pf_status s = check_table(&d.cur);
+    if (s != PF_OK) return s;
+    if (d.temporal && !d.cur.blend) return PF_EINVAL;
+    if (d.prev.cell) {
+        s = check_table(&d.prev);
+        if (s != PF_OK) return s;
+        if (!d.prev.blend || d.prev.log2_slots != d.cur.log2_slots || d.prev.cell == d.cur.cell) return PF_EINVAL;
+    }
+    if (!(d.kp.s > 0.0f) || !isfinite(d.kp.s) || !isfinite(d.kp.cam[0]) || !isfinite(d.kp.cam[1]) ||
+        !isfinite(d.kp.cam[2]))
+        return PF_ERANGE;
+    if (!(d.alpha_old >= 0.0f && d.alpha_old <= 1.0f)) return PF_ERANGE;
+    return PF_OK;
+}
+}  // namespace
+
+pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
+                          uint32_t grid_per_cu, void *workspace, void *stream) {
+    if (!views || !workspace || (reinterpret_cast<uintptr_t>(workspace) % 256)) return PF_EINVAL;
+    if (nviews == 0 || nviews > PF_MAX_VIEWS) return PF_ERANGE;
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return PF_ERANGE;
+    if (agg_width > block || (agg_width > 1 && (agg_width & (agg_width - 1)))) return PF_ERANGE;
+    for (uint32_t v = 0; v < nviews; ++v) {
+        const pf_status s = check_view(views[v]);
+        if (s != PF_OK) return s;
+        for (uint32_t u = 0; u < v; ++u)  // every view owns its tables
+            if (views[u].cur.cell == views[v].cur.cell || views[u].cur.cell == views[v].prev.cell ||
+                views[u].prev.cell == views[v].cur.cell)
+                return PF_EINVAL;
+    }
+    uint32_t *ws = reinterpret_cast<uint32_t *>(workspace);
+    pf_view *dev_views = reinterpret_cast<pf_view *>(reinterpret_cast<char *>(workspace) +
+                                                     align_up(pfk::views_counter_bytes(), 256));
+    if (hipMemcpyAsync(dev_views, views, nviews * sizeof(pf_view), hipMemcpyHostToDevice, (hipStream_t)stream) !=
+        hipSuccess)
+        return PF_ELAUNCH;
+    return launched(pfk::launch_views(dev_views, nviews, block, agg_width, grid_per_cu, ws, (hipStream_t)stream));
 }
 
 pf_status pf_read_stats(const pf_table *t, uint64_t *host_out, void *stream) {

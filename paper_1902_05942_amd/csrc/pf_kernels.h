@@ -23,6 +23,9 @@ hipError_t launch_build_keys(const float *px, const float *py, const float *pz, 
                              const float *nz, const uint8_t *valid, uint32_t n, const KeyArgs &a, uint64_t *key,
                              uint32_t *fp, uint32_t *home, uint8_t *flags, hipStream_t st);
 
+size_t binned_workspace_bytes(uint32_t n, uint32_t log2_slots);
+hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
+                                uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, hipStream_t st);
 hipError_t launch_table_init(const Tab &t, hipStream_t st);
 hipError_t launch_clear(const Tab &t, hipStream_t st);
 hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
@@ -31,6 +34,36 @@ hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot,
                         const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
                         float *bo, uint32_t *count_out, hipStream_t st);
 hipError_t launch_stats(const Tab &t, hipStream_t st);
+
+struct MlpArgs {
+    float *w;
+    uint16_t *wb;
+    float *m;
+    float *v;
+    float *partial;
+    float *loss;
+    uint32_t max_batch;
+};
+
+struct GeoArgs {
+    const uint64_t *key;
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    float cam[3];
+};
+
+size_t views_counter_bytes();
+hipError_t launch_views(const pf_view *views_dev, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,
+                        uint32_t *ws, hipStream_t st);
+hipError_t launch_mlp_init(const MlpArgs &a, hipStream_t st);
+uint32_t mlp_select_blocks(uint32_t n);
+hipError_t launch_mlp_select(const uint8_t *flags, const uint32_t *count, uint32_t n, uint32_t lo, uint32_t hi,
+                             uint32_t *tr_idx, uint32_t *sp_idx, uint32_t *counts, uint32_t *ws, hipStream_t st);
+hipError_t launch_mlp_train(const MlpArgs &a, const Tab &t, const GeoArgs &g, const uint32_t *slot,
+                            const uint32_t *train_idx, const uint32_t *counts, uint32_t batch, uint64_t seed,
+                            uint32_t step, float lr, hipStream_t st);
+hipError_t launch_mlp_features(const GeoArgs &g, const uint32_t *idx, uint32_t n, uint16_t *out, hipStream_t st);
+hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *idx, const uint32_t *counts,
+                            uint32_t n_max, float *r, float *gc, float *b, hipStream_t st);
 hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, hipStream_t st);
 
 }  // namespace pfk

@@ -1,0 +1,254 @@
+// Per-vertex and per-cell operations of the filter, shared by the single-view
+// kernels (keys.hip, table.hip, temporal.hip) and the batched multi-view
+// kernel (views.hip), so every launch shape runs the same arithmetic.
+#pragma once
+
+#include "pf_device.h"
+
+#pragma clang fp contract(off)
+
+namespace pfk {
+
+// Key construction of Algorithm 1 for one vertex.  Returns the vertex flags
+// (0, PF_V_INVALID or PF_V_KEYRANGE); key/fp/home are 0 for flagged vertices.
+__device__ __forceinline__ uint8_t vertex_key(const float x[3], const float nr[3], bool valid, const float cam[3],
+                                              float s, uint64_t seed, uint64_t stream, uint32_t mask, uint64_t &key,
+                                              uint32_t &fp, uint32_t &home) {
+    key = 0;
+    fp = 0;
+    home = 0;
+    const bool ok_in = valid && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(nr[0]) &&
+                       isfinite(nr[1]) && isfinite(nr[2]);
+    if (!ok_in) return PF_V_INVALID;
+    // l <- level_of_detail(|p_cam - x|)
+    const int l = level_of_detail(cam[0], cam[1], cam[2], x[0], x[1], x[2]);
+    // jitter(n): cube sample projected onto the tangent plane
+    Pcg32 g(seed, stream);
+    float r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = ldexpf((float)(g.next() >> 8), -24) - 0.5f;
+    const float t0 = r[0] * nr[0];
+    const float t1 = r[1] * nr[1];
+    const float t2 = r[2] * nr[2];
+    const float t = (t0 + t1) + t2;
+    // x' <- x + jitter(n) * s * 2^l
+    const float h = ldexpf(s, l);
+    float xp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float tn = t * nr[c];
+        const float j = r[c] - tn;
+        const float jh = j * h;
+        xp[c] = x[c] + jh;
+    }
+    // l' <- level_of_detail(|p_cam - x'|); x~ <- floor(x' / (s * 2^l'))
+    const int lp = level_of_detail(cam[0], cam[1], cam[2], xp[0], xp[1], xp[2]);
+    const float hp = ldexpf(s, lp);
+    bool inrange = true;
+    int32_t q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float f = floorf(xp[c] / hp);
+        inrange = inrange && (f >= -kCellIndexLimit) && (f < kCellIndexLimit);
+        q[c] = inrange ? (int32_t)f : 0;
+    }
+    if (!inrange) return PF_V_KEYRANGE;
+    const uint32_t code = normal_class(nr[0]) | (normal_class(nr[1]) << 2) | (normal_class(nr[2]) << 4);
+    key = (uint64_t)(uint32_t)(q[0] + 65536) | ((uint64_t)(uint32_t)(q[1] + 65536) << 17) |
+          ((uint64_t)(uint32_t)(q[2] + 65536) << 34) | ((uint64_t)(uint32_t)(lp + 16) << 51) | ((uint64_t)code << 56);
+    home = home_of(key, mask);
+    fp = fingerprint_of(key);
+    return 0;
+}
+
+// Fixed-point contribution q_c = rint(c * 2^F).  Returns 0, PF_V_INVALID
+// (non-finite) or PF_V_RADRANGE (|c 2^F| >= 2^62).
+__device__ __forceinline__ uint8_t fixed_point(float c0, float c1, float c2, int frac_bits, int64_t &q0, int64_t &q1,
+                                               int64_t &q2) {
+    q0 = q1 = q2 = 0;
+    if (!(isfinite(c0) && isfinite(c1) && isfinite(c2))) return PF_V_INVALID;
+    const float s0 = ldexpf(c0, frac_bits), s1 = ldexpf(c1, frac_bits), s2 = ldexpf(c2, frac_bits);
+    const float lim = 4611686018427387904.0f;  // 2^62
+    if (!(fabsf(s0) < lim && fabsf(s1) < lim && fabsf(s2) < lim)) return PF_V_RADRANGE;
+    q0 = (int64_t)rintf(s0);
+    q1 = (int64_t)rintf(s1);
+    q2 = (int64_t)rintf(s2);
+    return 0;
+}
+
+__device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, int64_t q0, int64_t q1,
+                                           int64_t q2) {
+    pf_cell *c = t.cell + slot;
+    add_u32(&c->count, cnt);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[0]), (unsigned long long)q0);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[1]), (unsigned long long)q1);
+    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[2]), (unsigned long long)q2);
+}
+
+// Probes from home(key) for the key's fingerprint or claims the first empty
+// cell.  Returns the slot or kNoSlot after max_probe slots.  A stale read of
+// 0 only leads to a compare-and-swap that returns the current value; a
+// non-zero fingerprint never changes within a kernel.
+__device__ __forceinline__ uint32_t find_or_claim(const Tab &t, uint64_t key) {
+    const uint32_t f = fingerprint_of(key);
+    uint32_t s = home_of(key, t.mask);
+    for (uint32_t d = 0; d < t.max_probe; ++d) {
+        uint32_t *pfp = &t.cell[s].fp;
+        uint32_t cur = load_fp_probe(pfp);
+        if (cur == 0) {
+            uint32_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                t.key[s] = key;
+                __hip_atomic_fetch_or(&t.occ[s >> 5], 1u << (s & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return s;
+            }
+            cur = expected;  // claimed meanwhile by someone else
+        }
+        if (cur == f) return s;
+        s = (s + 1) & t.mask;
+    }
+    return kNoSlot;
+}
+
+// Probe without claiming (lookup after insertion).
+__device__ __forceinline__ uint32_t find_slot(const Tab &t, uint64_t key) {
+    const uint32_t f = fingerprint_of(key);
+    uint32_t s = home_of(key, t.mask);
+    for (uint32_t d = 0; d < t.max_probe; ++d) {
+        const uint32_t cur = t.cell[s].fp;
+        if (cur == f) return s;
+        if (cur == 0) return kNoSlot;
+        s = (s + 1) & t.mask;
+    }
+    return kNoSlot;
+}
+
+// Search by fingerprint confirmed with the stored 64-bit key.
+__device__ __forceinline__ uint32_t find_exact(const Tab &t, uint64_t key, uint32_t f) {
+    uint32_t s = home_of(key, t.mask);
+    for (uint32_t d = 0; d < t.max_probe; ++d) {
+        const uint32_t cur = t.cell[s].fp;
+        if (cur == 0) return kNoSlot;
+        if (cur == f && t.key[s] == key) return s;
+        s = (s + 1) & t.mask;
+    }
+    return kNoSlot;
+}
+
+// LDS scratch of the workgroup aggregation (kBlockT threads).
+template <int kBlockT>
+struct AggLds {
+    uint32_t bucket[2 * kBlockT];
+    uint32_t slot[kBlockT];
+    unsigned long long acc[3][kBlockT];
+    uint32_t cnt[kBlockT];
+};
+
+// Accumulates every lane's contribution into its slot.  agg <= 1: one set of
+// device atomics per lane.  agg > 1 (power of two <= kBlockT): lanes of an
+// aggregation group (agg consecutive threads) that reach the same slot first
+// add their contributions in LDS; one lane per (group, slot) then issues the
+// device atomics.  Groups meet through a bucket array indexed by the slot's
+// low bits; a lane whose bucket was taken by another slot goes direct.  Must
+// be reached by every thread of the workgroup when agg > 1.
+template <int kBlockT>
+__device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &L, uint32_t agg, uint32_t slot,
+                                                 int64_t q0, int64_t q1, int64_t q2) {
+    const bool has = slot != kNoSlot;
+    if (agg <= 1) {
+        if (has) accumulate(t, slot, 1, q0, q1, q2);
+        return;
+    }
+    const uint32_t tid = threadIdx.x;
+    const uint32_t gbase = tid & ~(agg - 1);  // first lane of my group
+    L.slot[tid] = slot;
+    L.acc[0][tid] = 0;
+    L.acc[1][tid] = 0;
+    L.acc[2][tid] = 0;
+    L.cnt[tid] = 0;
+    // every lane with a slot writes its id into its bucket; one write wins
+    const uint32_t bk = 2 * gbase + (slot & (2 * agg - 1));
+    if (has) L.bucket[bk] = tid;
+    __syncthreads();
+    const uint32_t leader = has ? L.bucket[bk] : tid;
+    const bool member = has && L.slot[leader] == slot;
+    if (member) {
+        atomicAdd(&L.acc[0][leader], (unsigned long long)q0);
+        atomicAdd(&L.acc[1][leader], (unsigned long long)q1);
+        atomicAdd(&L.acc[2][leader], (unsigned long long)q2);
+        atomicAdd(&L.cnt[leader], 1u);
+    }
+    __syncthreads();
+    if (member && leader == tid) {
+        accumulate(t, slot, L.cnt[tid], (int64_t)L.acc[0][tid], (int64_t)L.acc[1][tid], (int64_t)L.acc[2][tid]);
+    } else if (has && !member) {
+        accumulate(t, slot, 1, q0, q1, q2);
+    }
+    __syncthreads();  // the scratch may be reused right after
+}
+
+// Temporal value of one occupied cell: the current average blended with the
+// previous frame's value when the key is found there.  Returns whether it
+// was found.
+template <bool kHasPrev>
+__device__ __forceinline__ bool temporal_cell(const Tab &cur, const Tab &prev, uint32_t s, float alpha, float beta) {
+    const pf_cell c = cur.cell[s];
+    float v0 = cell_average(c.sum[0], c.count, cur.frac_bits);
+    float v1 = cell_average(c.sum[1], c.count, cur.frac_bits);
+    float v2 = cell_average(c.sum[2], c.count, cur.frac_bits);
+    bool hit = false;
+    if constexpr (kHasPrev) {
+        const uint64_t key = cur.key[s];
+        const uint32_t p = find_exact(prev, key, c.fp);
+        if (p != kNoSlot) {
+            const float4 old = prev.blend[p];
+            const float a0 = alpha * old.x, a1 = alpha * old.y, a2 = alpha * old.z;
+            const float b0 = beta * v0, b1 = beta * v1, b2 = beta * v2;
+            v0 = a0 + b0;
+            v1 = a1 + b1;
+            v2 = a2 + b2;
+            hit = true;
+        }
+    }
+    cur.blend[s] = make_float4(v0, v1, v2, (float)c.count);
+    return hit;
+}
+
+// Lookup for one vertex: writes its filtered contribution (or its own when
+// unfiltered) and count.
+template <bool kBlend>
+__device__ __forceinline__ void query_vertex(const Tab &t, uint32_t slot, uint32_t i, const float *r, const float *g,
+                                             const float *b, float *ro, float *go, float *bo, uint32_t *count_out,
+                                             bool inplace) {
+    if (slot == kNoSlot) {
+        if (!inplace) {
+            ro[i] = r[i];
+            go[i] = g[i];
+            bo[i] = b[i];
+        }
+        if (count_out) count_out[i] = 0;
+        return;
+    }
+    float a0, a1, a2;
+    uint32_t cnt;
+    if constexpr (kBlend) {
+        const float4 v = t.blend[slot];
+        a0 = v.x;
+        a1 = v.y;
+        a2 = v.z;
+        cnt = (uint32_t)v.w;
+    } else {
+        const pf_cell c = t.cell[slot];
+        cnt = c.count;
+        a0 = cell_average(c.sum[0], cnt, t.frac_bits);
+        a1 = cell_average(c.sum[1], cnt, t.frac_bits);
+        a2 = cell_average(c.sum[2], cnt, t.frac_bits);
+    }
+    ro[i] = a0;
+    go[i] = a1;
+    bo[i] = a2;
+    if (count_out) count_out[i] = cnt;
+}
+
+}  // namespace pfk

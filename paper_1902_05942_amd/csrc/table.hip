@@ -3,8 +3,8 @@
 // statistics.  Occupied slots are recorded in a bitmap (one atomicOr per
 // claimed slot, spread over 2^m/32 words) so that no kernel updates a
 // shared counter per cell.
-#include "pf_device.h"
 #include "pf_kernels.h"
+#include "pf_ops.h"
 
 namespace pfk {
 
@@ -63,46 +63,6 @@ hipError_t launch_clear(const Tab &t, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------- insert
-__device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, int64_t q0, int64_t q1,
-                                           int64_t q2) {
-    pf_cell *c = t.cell + slot;
-    add_u32(&c->count, cnt);
-    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[0]), (unsigned long long)q0);
-    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[1]), (unsigned long long)q1);
-    add_u64(reinterpret_cast<unsigned long long *>(&c->sum[2]), (unsigned long long)q2);
-}
-
-// Probes from home(key) for the key's fingerprint or claims the first empty
-// cell.  Returns the slot or kNoSlot after max_probe slots.  A stale read of
-// 0 only leads to a compare-and-swap that returns the current value; a
-// non-zero fingerprint never changes within the kernel.
-__device__ __forceinline__ uint32_t find_or_claim(const Tab &t, uint64_t key) {
-    const uint32_t f = fingerprint_of(key);
-    uint32_t s = home_of(key, t.mask);
-    for (uint32_t d = 0; d < t.max_probe; ++d) {
-        uint32_t *pfp = &t.cell[s].fp;
-        uint32_t cur = load_fp_probe(pfp);
-        if (cur == 0) {
-            uint32_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) {
-                t.key[s] = key;
-                __hip_atomic_fetch_or(&t.occ[s >> 5], 1u << (s & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return s;
-            }
-            cur = expected;  // claimed meanwhile by someone else
-        }
-        if (cur == f) return s;
-        s = (s + 1) & t.mask;
-    }
-    return kNoSlot;
-}
-
-// kAgg: lanes of one aggregation group (agg consecutive lanes of a block)
-// that reach the same slot add their contributions in LDS first; one lane
-// per (group, slot) then issues the device atomics.  Groups meet through a
-// bucket array indexed by the slot's low bits; a lane whose bucket was taken
-// by a different slot falls back to its own atomics.
 template <bool kAgg>
 __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *__restrict__ key,
                                                         const float *__restrict__ r, const float *__restrict__ g,
@@ -113,22 +73,7 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *_
     uint8_t fl = in ? flags[i] : (uint8_t)PF_V_INVALID;
     const uint8_t fl0 = fl;
     int64_t q0 = 0, q1 = 0, q2 = 0;
-    if (fl == 0) {
-        const float c0 = r[i], c1 = g[i], c2 = b[i];
-        if (!(isfinite(c0) && isfinite(c1) && isfinite(c2))) {
-            fl = PF_V_INVALID;
-        } else {
-            const float s0 = ldexpf(c0, t.frac_bits), s1 = ldexpf(c1, t.frac_bits), s2 = ldexpf(c2, t.frac_bits);
-            const float lim = 4611686018427387904.0f;  // 2^62
-            if (!(fabsf(s0) < lim && fabsf(s1) < lim && fabsf(s2) < lim)) {
-                fl = PF_V_RADRANGE;
-            } else {
-                q0 = (int64_t)rintf(s0);
-                q1 = (int64_t)rintf(s1);
-                q2 = (int64_t)rintf(s2);
-            }
-        }
-    }
+    if (fl == 0) fl = fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
     uint32_t slot = kNoSlot;
     if (fl == 0) {
         slot = find_or_claim(t, key[i]);
@@ -139,40 +84,11 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *_
     }
     if (in && fl != fl0) flags[i] = fl;
     if (in && slot_out) slot_out[i] = slot;
-
     if constexpr (!kAgg) {
         if (slot != kNoSlot) accumulate(t, slot, 1, q0, q1, q2);
     } else {
-        __shared__ uint32_t s_bucket[2 * kBlock];
-        __shared__ uint32_t s_slot[kBlock];
-        __shared__ unsigned long long s_acc[3][kBlock];
-        __shared__ uint32_t s_cnt[kBlock];
-        const uint32_t tid = threadIdx.x;
-        const uint32_t gbase = tid & ~(agg - 1);  // first lane of my group
-        const bool has = slot != kNoSlot;
-        s_slot[tid] = slot;
-        s_acc[0][tid] = 0;
-        s_acc[1][tid] = 0;
-        s_acc[2][tid] = 0;
-        s_cnt[tid] = 0;
-        // every lane with a slot writes its id into its bucket; one write wins
-        const uint32_t bk = 2 * gbase + (slot & (2 * agg - 1));
-        if (has) s_bucket[bk] = tid;
-        __syncthreads();
-        const uint32_t leader = has ? s_bucket[bk] : tid;
-        const bool member = has && s_slot[leader] == slot;
-        if (member) {
-            atomicAdd(&s_acc[0][leader], (unsigned long long)q0);
-            atomicAdd(&s_acc[1][leader], (unsigned long long)q1);
-            atomicAdd(&s_acc[2][leader], (unsigned long long)q2);
-            atomicAdd(&s_cnt[leader], 1u);
-        }
-        __syncthreads();
-        if (member && leader == tid) {
-            accumulate(t, slot, s_cnt[tid], (int64_t)s_acc[0][tid], (int64_t)s_acc[1][tid], (int64_t)s_acc[2][tid]);
-        } else if (has && !member) {
-            accumulate(t, slot, 1, q0, q1, q2);
-        }
+        __shared__ AggLds<kBlock> L;
+        accumulate_group<kBlock>(t, L, agg, slot, q0, q1, q2);
     }
 }
 
@@ -187,18 +103,6 @@ hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, cons
 }
 
 // ----------------------------------------------------------------- query
-__device__ __forceinline__ uint32_t find_slot(const Tab &t, uint64_t key) {
-    const uint32_t f = fingerprint_of(key);
-    uint32_t s = home_of(key, t.mask);
-    for (uint32_t d = 0; d < t.max_probe; ++d) {
-        const uint32_t cur = t.cell[s].fp;
-        if (cur == f) return s;
-        if (cur == 0) return kNoSlot;
-        s = (s + 1) & t.mask;
-    }
-    return kNoSlot;
-}
-
 template <bool kBlend>
 __global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__restrict__ key,
                                                        const uint32_t *__restrict__ slot_in, const float *r,
@@ -210,34 +114,7 @@ __global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__
     if (i >= n) return;
     uint32_t slot = kNoSlot;
     if (flags[i] == 0) slot = slot_in ? slot_in[i] : find_slot(t, key[i]);
-    if (slot == kNoSlot) {
-        if (!inplace) {
-            ro[i] = r[i];
-            go[i] = g[i];
-            bo[i] = b[i];
-        }
-        if (count_out) count_out[i] = 0;
-        return;
-    }
-    float a0, a1, a2;
-    uint32_t cnt;
-    if constexpr (kBlend) {
-        const float4 v = t.blend[slot];
-        a0 = v.x;
-        a1 = v.y;
-        a2 = v.z;
-        cnt = (uint32_t)v.w;
-    } else {
-        const pf_cell c = t.cell[slot];
-        cnt = c.count;
-        a0 = cell_average(c.sum[0], cnt, t.frac_bits);
-        a1 = cell_average(c.sum[1], cnt, t.frac_bits);
-        a2 = cell_average(c.sum[2], cnt, t.frac_bits);
-    }
-    ro[i] = a0;
-    go[i] = a1;
-    bo[i] = a2;
-    if (count_out) count_out[i] = cnt;
+    query_vertex<kBlend>(t, slot, i, r, g, b, ro, go, bo, count_out, inplace);
 }
 
 hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,

@@ -1,0 +1,321 @@
+// Many views in one persistent launch on gfx950.  A cooperative grid of
+// resident workgroups walks four phases -- clear, keys + insert, temporal,
+// lookup -- separated by grid-wide barriers.  Within a phase the work items
+// of all views (chunks of bitmap words, vertices or slots) are dealt to the
+// workgroups round-robin, so small and large views share the whole chip.
+// The per-vertex and per-cell arithmetic is that of the single-view kernels
+// (pf_ops.h).
+#include "pf_kernels.h"
+#include "pf_ops.h"
+
+namespace pfk {
+
+namespace views {
+
+constexpr int kIters = 8;            // block-sized steps per work item
+constexpr int kSubCounters = 64;     // first level of the grid barrier
+constexpr int kCounterStride = 16;   // uint32 words between counters (64 B)
+
+struct Barrier {
+    uint32_t *status;   // [0] non-zero once a wait has timed out
+    uint32_t *sub;      // kSubCounters arrival counters, kCounterStride apart
+    uint32_t *rel;      // kSubCounters release flags, kCounterStride apart
+    uint32_t *top;      // sub-groups arrived
+    uint64_t limit;     // wall-clock ticks a wait may last
+};
+
+// Reads a counter at the coherence point with a read-modify-write that adds
+// 0: loads may be served by an XCD's L2, which does not see atomics made
+// elsewhere.  The zero is hidden from the optimiser, which would otherwise
+// turn the idempotent read-modify-write back into a plain load.
+__device__ __forceinline__ uint32_t poll(uint32_t *p) {
+    uint32_t zero = 0;
+    asm volatile("" : "+v"(zero));
+    return __hip_atomic_fetch_add(p, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ Tab to_tab(const pf_table &t) {
+    Tab k;
+    k.cell = t.cell;
+    k.key = t.key;
+    k.blend = reinterpret_cast<float4 *>(t.blend);
+    k.occ = t.occ;
+    k.stats = reinterpret_cast<unsigned long long *>(t.stats);
+    k.mask = (uint32_t)((1ull << t.log2_slots) - 1);
+    k.max_probe = t.max_probe;
+    k.frac_bits = t.frac_bits;
+    return k;
+}
+
+// Grid-wide barrier number `epoch` (1, 2, 3 ...).  A workgroup arrives at
+// one of 64 sub-counters; the last arrival of a sub-group advances the top
+// counter, waits for all sub-groups, then raises its sub-group's release
+// flag, on which the other members wait.  So at most ~64 workgroups poll any
+// one address.  Release/acquire fences make the phase's writes visible
+// across XCDs.  Every wait is bounded in wall-clock time; a timed-out wait
+// sets the status word and returns false (the workgroup then leaves).
+__device__ bool grid_barrier(const Barrier &bar, uint32_t epoch) {
+    __shared__ uint32_t s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t G = gridDim.x;
+        const uint32_t nsub = G < (uint32_t)kSubCounters ? G : (uint32_t)kSubCounters;
+        const uint32_t sub = blockIdx.x % nsub;
+        const uint32_t in_sub = (G - sub + nsub - 1) / nsub;  // workgroups of this sub-group
+        const uint32_t old = __hip_atomic_fetch_add(bar.sub + sub * kCounterStride, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        uint32_t ok = 1;
+        if (old + 1 == epoch * in_sub) {
+            __hip_atomic_fetch_add(bar.top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (poll(bar.top) < epoch * nsub) {
+                if (wall_clock64() - t0 > bar.limit) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            __hip_atomic_fetch_max(bar.rel + sub * kCounterStride, ok ? epoch : 0xffffffffu, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            for (;;) {
+                const uint32_t r = poll(bar.rel + sub * kCounterStride);
+                if (r == 0xffffffffu) {
+                    ok = 0;
+                    break;
+                }
+                if (r >= epoch) break;
+                if (wall_clock64() - t0 > bar.limit) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        if (!ok) {
+            __hip_atomic_fetch_or(bar.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(bar.status + 2, poll(bar.top), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(bar.status + 3, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <int B>
+struct Lds {
+    AggLds<B> agg;
+    uint32_t first[4][PF_MAX_VIEWS + 1];  // per phase: first global item of each view
+    uint32_t hits;
+};
+
+template <int B>
+__device__ __forceinline__ void item_of(const Lds<B> &L, int phase, uint32_t nviews, uint32_t it, uint32_t &v,
+                                        uint32_t &local) {
+    v = 0;
+    while (v + 1 < nviews && it >= L.first[phase][v + 1]) ++v;
+    local = it - L.first[phase][v];
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ views, uint32_t nviews, uint32_t agg,
+                                                  Barrier bar) {
+    __shared__ Lds<B> L;
+    constexpr uint32_t kItem = (uint32_t)B * kIters;
+    // work items per view and phase: 0 clear (bitmap words), 1 keys + insert
+    // (vertices), 2 temporal (slots), 3 lookup (vertices)
+    if (threadIdx.x == 0) {
+        uint32_t acc[4] = {0, 0, 0, 0};
+        for (uint32_t v = 0; v < nviews; ++v) {
+            const pf_view &d = views[v];
+            const uint32_t slots = 1u << d.cur.log2_slots;
+            const uint32_t words = (slots + 31) / 32;
+            const uint32_t items[4] = {(words + kItem - 1) / kItem, (d.n + kItem - 1) / kItem,
+                                       d.temporal ? (slots + kItem - 1) / kItem : 0u, (d.n + kItem - 1) / kItem};
+            for (int p = 0; p < 4; ++p) {
+                L.first[p][v] = acc[p];
+                acc[p] += items[p];
+            }
+        }
+        for (int p = 0; p < 4; ++p) L.first[p][nviews] = acc[p];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) bar.status[1] = gridDim.x;
+    __syncthreads();
+    const uint32_t G = gridDim.x;
+
+    // ---- phase 0: clear the current tables
+    for (uint32_t it = blockIdx.x; it < L.first[0][nviews]; it += G) {
+        uint32_t v, local;
+        item_of(L, 0, nviews, it, v, local);
+        const Tab t = to_tab(views[v].cur);
+        const uint32_t nwords = t.nwords();
+        for (int k = 0; k < kIters; ++k) {
+            const uint32_t j = local * kItem + k * B + threadIdx.x;
+            if (j >= nwords) break;
+            uint32_t w = t.occ[j];
+            if (w == 0) continue;
+            t.occ[j] = 0;
+            while (w) {
+                const uint32_t b = __builtin_ctz(w);
+                w &= w - 1;
+                uint4 *c = reinterpret_cast<uint4 *>(t.cell + (j * 32 + b));
+                c[0] = make_uint4(0, 0, 0, 0);
+                c[1] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (local == 0)
+            for (uint32_t k = threadIdx.x; k < PF_STATS_LEN; k += B) t.stats[k] = 0;
+    }
+    if (!grid_barrier(bar, 1)) return;
+
+    // ---- phase 1: keys and insertion
+    for (uint32_t it = blockIdx.x; it < L.first[1][nviews]; it += G) {
+        uint32_t v, local;
+        item_of(L, 1, nviews, it, v, local);
+        const pf_view &d = views[v];
+        const Tab t = to_tab(d.cur);
+        for (int k = 0; k < kIters; ++k) {
+            const uint32_t i = local * kItem + k * B + threadIdx.x;
+            const bool in = i < d.n;
+            uint32_t slot = kNoSlot;
+            int64_t q0 = 0, q1 = 0, q2 = 0;
+            if (in) {
+                const float x[3] = {d.px[i], d.py[i], d.pz[i]};
+                const float nr[3] = {d.nx[i], d.ny[i], d.nz[i]};
+                uint64_t key;
+                uint32_t fp, home;
+                uint8_t fl = vertex_key(x, nr, d.valid == nullptr || d.valid[i] != 0, d.kp.cam, d.kp.s, d.kp.seed,
+                                        d.kp.idx_base + i, t.mask, key, fp, home);
+                if (fl == 0) fl = fixed_point(d.r[i], d.g[i], d.b[i], t.frac_bits, q0, q1, q2);
+                if (fl == 0) {
+                    slot = find_or_claim(t, key);
+                    if (slot == kNoSlot) {
+                        fl = PF_V_OVERFLOW;
+                        add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], 1ull);
+                    }
+                }
+                d.key[i] = key;
+                d.vflags[i] = fl;
+                d.slot[i] = slot;
+            }
+            if (k * B + local * kItem >= d.n) {
+                // whole step beyond the view: uniform across the workgroup
+                break;
+            }
+            accumulate_group<B>(t, L.agg, agg, slot, q0, q1, q2);
+        }
+    }
+    if (!grid_barrier(bar, 2)) return;
+
+    // ---- phase 2: temporal values
+    for (uint32_t it = blockIdx.x; it < L.first[2][nviews]; it += G) {
+        uint32_t v, local;
+        item_of(L, 2, nviews, it, v, local);
+        const pf_view &d = views[v];
+        const Tab cur = to_tab(d.cur);
+        const bool has_prev = d.prev.cell != nullptr;
+        const Tab prev = has_prev ? to_tab(d.prev) : cur;
+        const float alpha = d.alpha_old, beta = 1.0f - d.alpha_old;
+        const uint32_t nslots = cur.mask + 1;
+        uint32_t hits = 0;
+        for (int k = 0; k < kIters; ++k) {
+            const uint32_t s = local * kItem + k * B + threadIdx.x;
+            if (s >= nslots) break;
+            if (((cur.occ[s >> 5] >> (s & 31)) & 1u) == 0) continue;
+            if (has_prev)
+                hits += temporal_cell<true>(cur, prev, s, alpha, beta) ? 1u : 0u;
+            else
+                temporal_cell<false>(cur, prev, s, alpha, beta);
+        }
+        if (has_prev) {
+            if (threadIdx.x == 0) L.hits = 0;
+            __syncthreads();
+            if (hits) atomicAdd(&L.hits, hits);
+            __syncthreads();
+            if (threadIdx.x == 0 && L.hits) add_u64(&cur.stats[PF_STAT_PART_HIT + (blockIdx.x & 31)], L.hits);
+            __syncthreads();
+        }
+    }
+    if (!grid_barrier(bar, 3)) return;
+
+    // ---- phase 3: lookup
+    for (uint32_t it = blockIdx.x; it < L.first[3][nviews]; it += G) {
+        uint32_t v, local;
+        item_of(L, 3, nviews, it, v, local);
+        const pf_view &d = views[v];
+        const Tab t = to_tab(d.cur);
+        for (int k = 0; k < kIters; ++k) {
+            const uint32_t i = local * kItem + k * B + threadIdx.x;
+            if (i >= d.n) break;
+            const uint32_t slot = d.vflags[i] == 0 ? d.slot[i] : kNoSlot;
+            if (d.temporal)
+                query_vertex<true>(t, slot, i, d.r, d.g, d.b, d.r_out, d.g_out, d.b_out, d.count_out, false);
+            else
+                query_vertex<false>(t, slot, i, d.r, d.g, d.b, d.r_out, d.g_out, d.b_out, d.count_out, false);
+        }
+    }
+}
+
+__global__ void views_reset_kernel(uint32_t *ws, uint32_t words) {
+    for (uint32_t j = threadIdx.x; j < words; j += blockDim.x) ws[j] = 0;
+}
+
+template <int B>
+hipError_t launch_b(const pf_view *views, uint32_t nviews, uint32_t agg, uint32_t per_cu, uint32_t *ws,
+                    hipStream_t st) {
+    static int resident = 0;  // workgroups per CU for this block size (queried once)
+    static int cus = 0;
+    if (resident == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(views_kernel<B>), B,
+                                                         0);
+        if (e != hipSuccess) return e;
+        if (resident < 1) return hipErrorInvalidConfiguration;
+    }
+    static uint64_t ticks_per_s = 0;
+    if (ticks_per_s == 0) {
+        int dev = 0, khz = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess) return e;
+        ticks_per_s = (uint64_t)(khz > 0 ? khz : 100000) * 1000ull;
+    }
+    Barrier bar;
+    bar.status = ws;
+    bar.sub = ws + kCounterStride;
+    bar.rel = ws + kCounterStride * (1 + kSubCounters);
+    bar.top = ws + kCounterStride * (1 + 2 * kSubCounters);
+    bar.limit = 2 * ticks_per_s;  // a phase never takes seconds
+    const uint32_t words = kCounterStride * (2 + 2 * kSubCounters);
+    views_reset_kernel<<<1, 256, 0, st>>>(ws, words);
+    const uint32_t per = (per_cu == 0 || per_cu > (uint32_t)resident) ? (uint32_t)resident : per_cu;
+    uint32_t grid = per * (uint32_t)cus;
+    void *args[] = {(void *)&views, (void *)&nviews, (void *)&agg, (void *)&bar};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(views_kernel<B>), dim3(grid), dim3(B), args, 0,
+                                      st);
+}
+
+}  // namespace views
+
+size_t views_counter_bytes() { return sizeof(uint32_t) * views::kCounterStride * (2 * views::kSubCounters + 2); }
+
+hipError_t launch_views(const pf_view *views_dev, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,
+                        uint32_t *ws, hipStream_t st) {
+    switch (block) {
+        case 64: return views::launch_b<64>(views_dev, nviews, agg, per_cu, ws, st);
+        case 128: return views::launch_b<128>(views_dev, nviews, agg, per_cu, ws, st);
+        case 256: return views::launch_b<256>(views_dev, nviews, agg, per_cu, ws, st);
+        case 512: return views::launch_b<512>(views_dev, nviews, agg, per_cu, ws, st);
+        case 1024: return views::launch_b<1024>(views_dev, nviews, agg, per_cu, ws, st);
+        default: return hipErrorInvalidConfiguration;
+    }
+}
+
+}  // namespace pfk

@@ -47,7 +47,11 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
     pf.build_keys(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"], f["s"], f["seed"],
                   idx_base, cur.log2_slots, key, fp, home, vflags)
     flags_keys = vflags.clone()
-    pf.insert_accumulate(cur, key, g["r"], g["g"], g["b"], vflags, slot if use_slot else None, agg)
+    if agg == "binned":
+        ws = torch.empty(pf.insert_workspace_bytes(n, cur.log2_slots), dtype=torch.uint8, device=dev)
+        pf.insert_accumulate_binned(cur, key, g["r"], g["g"], g["b"], vflags, slot, ws)
+    else:
+        pf.insert_accumulate(cur, key, g["r"], g["g"], g["b"], vflags, slot if use_slot else None, agg)
     if temporal:
         pf.temporal_update(cur, prev, alpha)
     if in_place:

@@ -32,6 +32,9 @@ def test_every_declared_symbol_is_exported(pf):
 def test_struct_layouts_match_header(pf):
     assert ctypes.sizeof(pf._lib.pf_table) == 5 * 8 + 4 * 4
     assert ctypes.sizeof(pf._lib.pf_key_params) == 4 * 4 + 8 + 8
+    assert ctypes.sizeof(pf._lib.pf_view) == 296
+    assert ctypes.sizeof(pf._lib.pf_mlp) == 6 * 8 + 8
+    assert ctypes.sizeof(pf._lib.pf_geometry) == 7 * 8 + 16
     assert pf._lib.CELL_BYTES == 32
 
 

@@ -94,6 +94,7 @@ def test_build_keys_edge_cases(gpu):
     ("scaled_ragged", 0, False), ("scaled_ragged", 4, True), ("scaled_ragged", 64, True),
     ("scaled_ragged", 256, False),
     ("hd_full", BENCH_AGG, True), ("hd_full", 0, False),
+    ("tiny", "binned", True), ("scaled_ragged", "binned", True), ("hd_full", "binned", True),
 ])
 def test_filter_frame_bit_exact(gpu, case, agg, use_slot):
     if case == "tiny":
@@ -131,7 +132,7 @@ def test_in_place_query(gpu):
     check_frame_against_oracle(res, oracle.filter_frame(_host(f), temporal=False), t)
 
 
-@pytest.mark.parametrize("agg", [0, 64])
+@pytest.mark.parametrize("agg", [0, 64, "binned"])
 def test_temporal_sixteen_frames_bit_exact(gpu, agg):
     """Exponential moving average over 16 frames of the orbiting camera with
     double-buffered tables; every frame's output equals the oracle's."""
@@ -165,6 +166,36 @@ def test_temporal_full_hd_three_frames(gpu):
         R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old)
         check_frame_against_oracle(res, R, cur)
         state = R.state
+
+
+def test_binned_insert_accumulates_several_batches(gpu):
+    """Two batches inserted into one table before one lookup equal one batch
+    of both (integer sums), for the binned path as for the atomic one."""
+    wl, f = _frame("hd_1080p_x3", frame=4, width=256, height=144)
+    g = to_dev(f)
+    n = g["px"].numel()
+    h = n // 2 + 123
+    for mode in ("binned", 64):
+        t = pf.Table(f["log2_slots"]); pf.table_init(t)
+        key = torch.empty(n, dtype=torch.int64, device="cuda")
+        fl = torch.empty(n, dtype=torch.uint8, device="cuda")
+        slot = torch.empty(n, dtype=torch.int32, device="cuda")
+        pf.build_keys(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"], f["s"], f["seed"],
+                      0, f["log2_slots"], key, None, None, fl)
+        for a, b in ((0, h), (h, n)):
+            if mode == "binned":
+                ws = torch.empty(pf.insert_workspace_bytes(b - a, f["log2_slots"]), dtype=torch.uint8, device="cuda")
+                pf.insert_accumulate_binned(t, key[a:b], g["r"][a:b], g["g"][a:b], g["b"][a:b], fl[a:b], slot[a:b],
+                                            ws)
+            else:
+                pf.insert_accumulate(t, key[a:b], g["r"][a:b], g["g"][a:b], g["b"][a:b], fl[a:b], slot[a:b], mode)
+        out = [torch.empty(n, device="cuda") for _ in range(3)]
+        cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        pf.query_average(t, key, slot, g["r"], g["g"], g["b"], fl, False, out[0], out[1], out[2], cnt)
+        torch.cuda.synchronize()
+        R = oracle.filter_frame(_host(f), temporal=False)
+        assert_bits_equal(np.stack([o.cpu().numpy() for o in out], 1), R.out, f"{mode} radiance")
+        assert_bits_equal(cnt.cpu().numpy().view(np.uint32), R.cnt, f"{mode} counts")
 
 
 def test_probe_overflow_in_a_tiny_table(gpu):

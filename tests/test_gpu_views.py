@@ -1,0 +1,79 @@
+"""GPU parity of the persistent multi-view launch: every view of every frame
+equals the oracle bit for bit, for every (workgroup size, aggregation width)
+the autotuner can pick."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1902_05942_amd as pf
+import synth
+from gpu_util import assert_bits_equal, table_contents
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(160, 90, 3, 16), (64, 64, 1, 14), (301, 167, 3, 18), (97, 55, 2, 15)]
+
+
+def _views(frame):
+    wl = synth.get("multiview_8")
+    out = []
+    for v, (w, h, vpp, m) in enumerate(SHAPES):
+        spec = synth.ViewSpec(w, h, vpp, m, synth.workloads.CONFIG_SEED + v)
+        wl_v = synth.Workload(f"view{v}", [spec], frames=3)
+        f = synth.generate(wl_v, frame=frame)
+        f["s"] = 0.01 if v != 3 else 0.03
+        out.append(f)
+    return wl, out
+
+
+@pytest.mark.parametrize("block,agg", [(64, 0), (256, 64), (1024, 256), (512, 4), (128, 128)])
+def test_views_bit_exact_over_frames(gpu, block, agg):
+    mvf = pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=True, alpha_old=0.2)
+    states = [None] * len(SHAPES)
+    for frame in range(3):
+        wl, fs = _views(frame)
+        dev = [{k: (v.cuda() if torch.is_tensor(v) else v) for k, v in f.items()} for f in fs]
+        outs = mvf.filter(dev, block, agg, with_count=True)
+        torch.cuda.synchronize()
+        assert mvf.status() == 0
+        for v, f in enumerate(fs):
+            R = oracle.filter_frame(f, prev_state=states[v], temporal=True, alpha_old=0.2)
+            b = mvf.bufs[v]
+            n = f["px"].numel()
+            assert_bits_equal(b["key"][:n].cpu().numpy().view(np.uint64), R.key, f"view {v} keys")
+            assert_bits_equal(b["vflags"][:n].cpu().numpy(), R.flags, f"view {v} flags")
+            assert_bits_equal(b["count"][:n].cpu().numpy().view(np.uint32), R.cnt, f"view {v} counts")
+            got = np.stack([o.cpu().numpy() for o in outs[v]], 1)
+            assert_bits_equal(got, R.out, f"view {v} frame {frame} radiance")
+            t = mvf.tables[v][1]            # this frame's table after the swap
+            tc = table_contents(t)
+            order = np.argsort(tc["key"])
+            assert R.table.order_free
+            assert_bits_equal(tc["key"][order], R.gkey, f"view {v} table keys")
+            assert_bits_equal(tc["sum"][order], R.gsum, f"view {v} table sums")
+            assert_bits_equal(tc["occupied"], R.table.occupied, f"view {v} occupancy")
+            st = pf.read_stats(t)
+            assert int(st[pf.STAT_USED]) == len(R.gkey) and int(st[pf.STAT_DISP]) == R.table.total_disp
+            if frame:
+                assert int(st[pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, states[v][0]).sum())
+            states[v] = R.state
+
+
+def test_views_argument_checks(gpu):
+    mvf = pf.MultiViewFilter([(100, 10)], temporal=True)
+    wl, fs = _views(0)
+    f = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in fs[1].items()}
+    n = f["px"].numel()
+    mvf2 = pf.MultiViewFilter([(n, 14)], temporal=True)
+    d = mvf2.descriptors([f])
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d, 96, 0, mvf2.ws)                 # unsupported workgroup size
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d, 256, 3, mvf2.ws)                # aggregation width not a power of two
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d + d, 256, 0, mvf2.ws)            # two views sharing tables
+    d[0].r_out = d[0].r
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d, 256, 0, mvf2.ws)                # output aliasing the input
+    del mvf

@@ -254,3 +254,62 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     state = (gkey[placed].copy(), gval[placed].copy())
     return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,
                        sim, out, cnt, state)
+
+
+# ---------------------------------------------------- binary32 sums (variant)
+@dataclass
+class FloatFrameResult:
+    key: np.ndarray
+    flags: np.ndarray        # key flags, INVALID for non-finite contributions, OVERFLOW
+    vgroup: np.ndarray
+    gkey: np.ndarray
+    gcnt: np.ndarray
+    gsum: np.ndarray         # [G,3] float64 sums of the binary32 contributions
+    gabs: np.ndarray         # [G,3] float64 sums of their magnitudes
+    gmean: np.ndarray        # [G,3] float64 gsum / gcnt
+    table: TableSim
+
+
+def float_filter_frame(f: dict, cam=None, idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None):
+    """The accumulation as the paper performs it (Section 3.3.1: one
+    floating-point atomic add per component of each vertex), reduced to what
+    every arrival order shares: the partition of Eq. (7) is the same as
+    filter_frame's, and each cell's mean (Eq. (8), w = 1) is taken over the
+    binary32 contributions in float64 (rounding error at most n 2^-53 of
+    the summed magnitudes, far below binary32's).  A GPU result in binary32
+    may differ from gmean by the rounding of one float summation in some
+    order plus one float division; the tests bound that from gabs.  No
+    RADRANGE here: contributions are not scaled."""
+    A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
+         ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
+    cam = f["cam"] if cam is None else cam
+    s = f["s"] if s is None else s
+    seed = f["seed"] if seed is None else seed
+    m = f["log2_slots"] if log2_slots is None else log2_slots
+    P = f["max_probe"] if max_probe is None else max_probe
+    k = build_keys(A["px"], A["py"], A["pz"], A["nx"], A["ny"], A["nz"], A["valid"], cam, s, seed, idx_base, m)
+    flags = k["flags"].copy()
+    rgb = [_f32(A[c]) for c in ("r", "g", "b")]
+    finite = np.isfinite(rgb[0]) & np.isfinite(rgb[1]) & np.isfinite(rgb[2])
+    flags[(flags == 0) & ~finite] = INVALID
+    n = flags.shape[0]
+    gkey, gcnt, _, vgroup = group_by(k["key"], flags, np.zeros((n, 3), np.int64))
+    G = gkey.shape[0]
+    first = np.full(G, -1, np.int64)
+    idx = np.nonzero(vgroup >= 0)[0]
+    first[vgroup[idx][::-1]] = idx[::-1]
+    gfp = k["fp"][first] if G else np.zeros(0, np.uint32)
+    ghome = k["home"][first] if G else np.zeros(0, np.uint32)
+    sim = simulate_table(gkey, gfp, ghome, m, P)
+    sel = vgroup >= 0
+    gsum = np.zeros((G, 3)); gabs = np.zeros((G, 3))
+    for c in range(3):
+        x = rgb[c][sel].astype(np.float64)
+        gsum[:, c] = np.bincount(vgroup[sel], weights=x, minlength=G)
+        gabs[:, c] = np.bincount(vgroup[sel], weights=np.abs(x), minlength=G)
+    gmean = gsum / np.maximum(gcnt, 1)[:, None].astype(np.float64)
+    # vertices of keys the table could not place keep their own contribution
+    lost = sel.copy()
+    lost[sel] = sim.gslot[vgroup[sel]] < 0
+    flags[lost] = OVERFLOW
+    return FloatFrameResult(k["key"], flags, vgroup, gkey, gcnt, gsum, gabs, gmean, sim)

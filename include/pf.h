@@ -62,6 +62,8 @@ typedef int pf_status;
  *                  sentinel of Section 3.2.1)
  *   uint32 count   vertices accumulated in this cell
  *   int64  sum[3]  contributions in fixed point, sum of rint(c * 2^frac_bits)
+ *                  (PF_SUMS_FIXED64); with PF_SUMS_FLOAT32 the low 4 bytes of
+ *                  each word hold a binary32 sum instead, the high 4 are 0
  * The fingerprint sits in the cell so that probing and accumulating touch
  * one memory line. */
 typedef struct pf_cell {
@@ -96,8 +98,21 @@ typedef struct pf_table {
     uint32_t log2_slots; /* 4 .. 30 */
     uint32_t max_probe;  /* 1 .. 2^log2_slots: slots examined before PF_V_OVERFLOW */
     int32_t frac_bits;   /* 8 .. 40: fixed-point fraction bits of the sums */
-    uint32_t reserved;
+    uint32_t sum_format; /* PF_SUMS_FIXED64 (set by pf_table_carve) or PF_SUMS_FLOAT32 */
 } pf_table;
+
+/* Sum formats.  PF_SUMS_FIXED64: exact int64 fixed-point sums; every
+ * insertion order gives the same bits.  PF_SUMS_FLOAT32: the paper's own
+ * accumulation (Section 3.3.1: one floating-point atomic add per component
+ * of each vertex), binary32 sums whose rounding depends on the order in
+ * which atomics arrive; each sum of n non-negative contributions is within
+ * (n-1) 2^-24 / (1 - (n-1) 2^-24) of the exact sum, relative.  Float tables
+ * are accepted by pf_insert_accumulate, pf_query_average,
+ * pf_temporal_update and pf_mlp_train_step (frac_bits is then unused), and
+ * rejected with PF_EINVAL by pf_insert_accumulate_binned and
+ * pf_filter_views. */
+#define PF_SUMS_FIXED64 0u
+#define PF_SUMS_FLOAT32 1u
 
 /* [host] Bytes of one table arena (including 256 bytes of alignment slack). */
 size_t pf_table_bytes(uint32_t log2_slots, int with_blend);
@@ -167,6 +182,9 @@ pf_status pf_build_keys(const float *px, const float *py, const float *pz,
  * Vertices with non-finite contributions get PF_V_INVALID, with out-of-range
  * ones PF_V_RADRANGE, those finding neither within max_probe slots
  * PF_V_OVERFLOW; vertices already flagged are skipped.
+ * On a PF_SUMS_FLOAT32 table the contribution is added as it is, with one
+ * binary32 atomic add per component (no RADRANGE; a sum may overflow to
+ * infinity), and combined lanes add in LDS first, in binary32 as well.
  * agg_width: 0 = one set of atomics per vertex; k > 0 = lanes of a wavefront
  * that reach the same slot combine their contributions first (at most k
  * distinct slots per wavefront are combined, the rest go directly).
@@ -192,8 +210,8 @@ size_t pf_insert_workspace_bytes(uint64_t n, uint32_t log2_slots);
  * bits.  Compare-and-swap remains only for claiming new cells.
  * slot_out is required.  workspace: pf_insert_workspace_bytes(n, log2_slots)
  * device bytes (caller-owned, no alignment needed).
- * Errors: PF_EINVAL (NULL, misaligned, workspace too small), PF_ERANGE
- * (log2_slots > 25). */
+ * Errors: PF_EINVAL (NULL, misaligned, workspace too small, a
+ * PF_SUMS_FLOAT32 table), PF_ERANGE (log2_slots > 25). */
 pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, const float *r, const float *g,
                                       const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
                                       void *workspace, size_t workspace_bytes, void *stream);
@@ -201,7 +219,8 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
 /* ------------------------------------------------------------------ query */
 /* Lookup (Sections 3.2, 3.3.1): for each vertex with vflags == 0, finds its
  * cell (from slot[i] when slot is non-NULL, else by probing with key[i]) and
- * writes avg_c = (float)((double)sum_c * 2^-frac_bits / (double)count), or
+ * writes avg_c = (float)((double)sum_c * 2^-frac_bits / (double)count)
+ * (PF_SUMS_FLOAT32: sum_c / (float)count, one binary32 division), or
  * the cell's temporal value when use_blend != 0 (after pf_temporal_update).
  * Flagged vertices, and vertices whose key is not found, write their own
  * contribution and count 0.  r_out.. may alias r_in.. (in-place update);
@@ -377,9 +396,9 @@ size_t pf_views_workspace_bytes(uint32_t nviews);
  * ever exceeded its bound (every workgroup then stops; with a cooperative
  * launch all workgroups are resident, so it stays 0); the next words hold
  * the grid size and, after a timed-out wait, the arrivals that were seen.
- * Errors: PF_EINVAL (NULL, misaligned, inconsistent descriptor), PF_ERANGE
- * (nviews 0 or above PF_MAX_VIEWS, block, agg_width, parameters),
- * PF_ELAUNCH. */
+ * Errors: PF_EINVAL (NULL, misaligned, inconsistent descriptor, a
+ * PF_SUMS_FLOAT32 table), PF_ERANGE (nviews 0 or above PF_MAX_VIEWS,
+ * block, agg_width, parameters), PF_ELAUNCH. */
 pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
                           uint32_t grid_per_cu, void *workspace, void *stream);
 

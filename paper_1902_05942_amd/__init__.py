@@ -10,7 +10,8 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_USED, V_INVALID, V_KEYRANGE,  # noqa
+from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_USED, SUMS_FIXED64,  # noqa
+                   SUMS_FLOAT32, V_INVALID, V_KEYRANGE,
                    V_OVERFLOW, V_RADRANGE, Mlp, PfError, Table, build_keys, clear, geometry, insert_accumulate,
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
@@ -55,8 +56,10 @@ class FrameFilter:
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
-                 mlp: "MlpFallback | None" = None, binned: bool = False):
-        self.tables = [Table(log2_slots, max_probe, frac_bits, True, device) for _ in range(2 if temporal else 1)]
+                 mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False):
+        fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
+        self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
+                       for _ in range(2 if temporal else 1)]
         for t in self.tables:
             table_init(t)
         self.log2_slots = log2_slots

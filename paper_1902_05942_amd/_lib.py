@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpf.so")
 PF_OK, PF_EINVAL, PF_ERANGE, PF_ELAUNCH = 0, -1, -2, -3
 V_INVALID, V_KEYRANGE, V_OVERFLOW, V_RADRANGE = 1, 2, 4, 8
 STAT_USED, STAT_DISP, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_HIST, STATS_LEN = 0, 1, 2, 3, 8, 128
+SUMS_FIXED64, SUMS_FLOAT32 = 0, 1
 CELL_BYTES = 32
 
 
@@ -31,7 +32,7 @@ class PfError(RuntimeError):
 class pf_table(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_void_p), ("key", ctypes.c_void_p), ("blend", ctypes.c_void_p),
                 ("occ", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32),
-                ("max_probe", ctypes.c_uint32), ("frac_bits", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+                ("max_probe", ctypes.c_uint32), ("frac_bits", ctypes.c_int32), ("sum_format", ctypes.c_uint32)]
 
 
 class pf_key_params(ctypes.Structure):
@@ -143,7 +144,7 @@ class Table:
     """One table arena (a torch uint8 tensor) carved into the pf_table views."""
 
     def __init__(self, log2_slots: int, max_probe: int = 64, frac_bits: int = 24, with_blend: bool = True,
-                 device="cuda", arena=None):
+                 device="cuda", arena=None, sum_format: int = 0):
         nbytes = table_bytes(log2_slots, with_blend)
         if nbytes == 0:
             raise PfError("pf_table_bytes", PF_ERANGE)
@@ -151,6 +152,7 @@ class Table:
         self.t = pf_table()
         _check("pf_table_carve", lib.pf_table_carve(_ptr(self.arena), log2_slots, int(with_blend), max_probe,
                                                     frac_bits, ctypes.byref(self.t)))
+        self.t.sum_format = sum_format
         self.log2_slots = log2_slots
         self.with_blend = with_blend
 

@@ -1,17 +1,24 @@
-// Insert-accumulate without device atomics on the cells, for gfx950.
+// Insert-accumulate without device atomics on the cell sums, for gfx950.
 //
-// Device atomics run at ~24 G/s on MI355X whatever the footprint, so the
-// per-vertex atomic adds of the cell update bound the atomic insert.  Here
-// the vertices are binned by the slot they were given and every bin (a
-// contiguous slot range) is reduced by one workgroup in LDS, which then owns
-// its cells and updates them with plain loads and stores:
-//   claim    per vertex: fixed point, probe / claim (CAS on new cells only),
-//            slot out, and a per-tile histogram of bins in LDS
-//   colscan  per bin: running offsets over the tiles, bin totals
-//   binscan  bin start offsets (one workgroup)
-//   scatter  per vertex: record {slot, r, g, b} into its bin's range
-//   reduce   per bin: LDS sums over the bin's records, then count and sums
-//            added to the cells and the occupancy bits set (exclusive owner)
+// Device atomics run at ~24 G/s on MI355X whatever the footprint, and a
+// random access of any kind moves a whole cache line, so the cost of the
+// insert is the number of per-cell operations it sends to memory.  This path
+// sends one per group of vertices that share a key within a chunk of 4096
+// consecutive vertices, and no atomic at all for the sums:
+//   aggregate  per tile (every ntiles-th chunk): each chunk's vertices are
+//              merged by key, first along runs of equal keys within a
+//              wavefront, then in an LDS hash table (count and fixed-point
+//              sums added with LDS atomics); each group then probes / claims its cell
+//              once (compare-and-swap on new cells only), writes one record
+//              {slot, count, sums} to the tile's staging area and counts it
+//              in the tile's histogram of slot bins; every vertex receives
+//              its group's slot
+//   colscan    per bin: running record offsets over the tiles, bin totals
+//   binscan    start offset of every bin (one workgroup)
+//   scatter    per tile: staged records moved to their bin's range
+//   reduce     per bin (a contiguous slot range): records summed in LDS, then
+//              count and sums added to the cells with plain loads and stores
+//              by the workgroup that owns them, occupancy bits set
 // Integer sums make the result identical to the atomic insert.
 #include "pf_kernels.h"
 #include "pf_ops.h"
@@ -20,49 +27,73 @@ namespace pfk {
 
 namespace binned {
 
-constexpr int kT = 1024;                 // threads of the tile kernels
-constexpr uint32_t kLog2MinBinSlots = 10;
-constexpr uint32_t kLog2MaxBins = 13;    // LDS histogram of 8192 bins
-constexpr uint32_t kMaxLog2Slots = 25;   // reduce LDS: 4096 slots x 28 B
-constexpr uint32_t kTileMin = 8192;
-constexpr uint32_t kMaxTiles = 1024;
-constexpr int kReduceThreads = 256;
+constexpr int kT = 1024;                     // threads of the tile kernels
+constexpr uint32_t kPer = 4;                 // vertices per thread and chunk
+constexpr uint32_t kChunk = kT * kPer;       // vertices merged in one LDS table
+constexpr uint32_t kMaxTiles = 512;          // two workgroups on each of 256 CUs
+constexpr uint32_t kLdsBudget = 80 * 1024;   // two 1024-thread workgroups per CU
+constexpr uint32_t kLdsProbe = 32;           // LDS probes before a vertex goes alone
+constexpr uint32_t kFlush = 2;               // LDS entries per thread (entries <= kFlush * kT)
+constexpr uint32_t kMaxLog2Slots = 25;
+constexpr int kReduceThreads = 512;
+constexpr uint64_t kEmpty = ~0ull;           // no key has bit 63 set
+
+// One staged group: the cell layout with the slot in place of the fingerprint.
+struct __align__(16) Rec {
+    uint32_t slot, count;
+    int64_t s[3];
+};
+static_assert(sizeof(Rec) == 32, "record is two 16-byte words");
 
 struct Plan {
-    uint32_t log2_bins, nbins, bin_shift, bin_slots, ntiles, tile;
-    size_t off_h, off_tot, off_start, off_rec, bytes;
+    uint32_t log2_bins, nbins, bin_shift, bin_slots, ntiles, tile, cap;
+    size_t lds_aggregate, lds_reduce;
+    size_t off_h, off_tot, off_start, off_ntr, off_trec, off_rec, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 Plan make_plan(uint32_t n, uint32_t log2_slots) {
     Plan p;
-    p.log2_bins = log2_slots > kLog2MinBinSlots ? log2_slots - kLog2MinBinSlots : 0;
-    if (p.log2_bins > kLog2MaxBins) p.log2_bins = kLog2MaxBins;
+    // bins of 2048 slots (4096 above 2^24 slots, keeping the histogram small)
+    uint32_t lbs = log2_slots > 24 ? 12 : 11;
+    if (lbs > log2_slots) lbs = log2_slots;
+    p.bin_shift = lbs;
+    p.bin_slots = 1u << lbs;
+    p.log2_bins = log2_slots - lbs;
     p.nbins = 1u << p.log2_bins;
-    p.bin_shift = log2_slots - p.log2_bins;
-    p.bin_slots = 1u << p.bin_shift;
-    uint32_t nt = (n + kTileMin - 1) / kTileMin;
-    if (nt > kMaxTiles) nt = kMaxTiles;
-    if (nt == 0) nt = 1;
-    p.ntiles = nt;
-    p.tile = ((n + nt - 1) / nt + kT - 1) / kT * kT;
+    // a tile is the set of chunks one workgroup takes (every ntiles-th);
+    // its staging area holds a record per vertex at most
+    const uint32_t nchunks = (n + kChunk - 1) / kChunk;
+    p.ntiles = nchunks < kMaxTiles ? (nchunks ? nchunks : 1) : kMaxTiles;
+    p.tile = (nchunks + p.ntiles - 1) / p.ntiles * kChunk;
+    if (p.tile == 0) p.tile = kChunk;
+    // LDS of aggregate: key 8 B, sums 24 B and count 4 B per entry, the bin
+    // histogram and two counters; entries take what the budget leaves
+    const size_t fixed = (size_t)p.nbins * 4 + 16;
+    uint32_t cap = (uint32_t)((kLdsBudget - fixed) / 36) / 64 * 64;
+    if (cap < 512) cap = 512;
+    if (cap > kFlush * kT) cap = kFlush * kT;
+    p.cap = cap;
+    p.lds_aggregate = (size_t)cap * 36 + fixed;
+    p.lds_reduce = (size_t)p.bin_slots * 28;
     p.off_h = 0;
     p.off_tot = align256((size_t)p.ntiles * p.nbins * 4);
     p.off_start = p.off_tot + align256((size_t)p.nbins * 4);
-    p.off_rec = p.off_start + align256((size_t)p.nbins * 4);
-    p.bytes = p.off_rec + align256((size_t)n * 16) + 256;
+    p.off_ntr = p.off_start + align256((size_t)p.nbins * 4);
+    p.off_trec = p.off_ntr + align256((size_t)p.ntiles * 4);
+    p.off_rec = p.off_trec + align256((size_t)p.ntiles * p.tile * sizeof(Rec));
+    p.bytes = p.off_rec + align256((size_t)(n ? n : 1) * sizeof(Rec)) + 256;
     return p;
 }
 
 // Probe / claim like find_or_claim, without the occupancy bit (set by the
-// reduce pass, which owns the bitmap words of its bin).
-__device__ __forceinline__ uint32_t claim(const Tab &t, uint64_t key) {
-    const uint32_t f = fingerprint_of(key);
-    uint32_t s = home_of(key, t.mask);
+// reduce pass, which owns the bitmap words of its bin), continuing from slot
+// s whose fingerprint word was already read as cur.
+__device__ __forceinline__ uint32_t claim_from(const Tab &t, uint64_t key, uint32_t f, uint32_t s, uint32_t cur) {
     for (uint32_t d = 0; d < t.max_probe; ++d) {
         uint32_t *pfp = &t.cell[s].fp;
-        uint32_t cur = load_fp_probe(pfp);
+        if (d) cur = load_fp_probe(pfp);
         if (cur == 0) {
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -78,58 +109,302 @@ __device__ __forceinline__ uint32_t claim(const Tab &t, uint64_t key) {
     return kNoSlot;
 }
 
-__global__ __launch_bounds__(kT) void claim_kernel(Tab t, const uint64_t *__restrict__ key,
-                                                   const float *__restrict__ r, const float *__restrict__ g,
-                                                   const float *__restrict__ b, uint8_t *__restrict__ flags,
-                                                   uint32_t *__restrict__ slot_out, uint32_t n, uint32_t tile,
-                                                   uint32_t nbins, uint32_t bin_shift, uint32_t *__restrict__ H) {
-    extern __shared__ uint32_t hist[];
-    for (uint32_t k = threadIdx.x; k < nbins; k += kT) hist[k] = 0;
-    __syncthreads();
-    const uint32_t i0 = blockIdx.x * tile;
-    const uint32_t i1 = min(n, i0 + tile);
-    uint32_t ovf = 0;
-    for (uint32_t i = i0 + threadIdx.x; i < i1; i += kT) {
-        uint8_t fl = flags[i];
-        const uint8_t fl0 = fl;
-        uint32_t slot = kNoSlot;
-        if (fl == 0) {
-            int64_t q0, q1, q2;
-            fl = fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
+__device__ __forceinline__ uint32_t claim(const Tab &t, uint64_t key) {
+    const uint32_t s = home_of(key, t.mask);
+    return claim_from(t, key, fingerprint_of(key), s, load_fp_probe(&t.cell[s].fp));
+}
+
+// Index of this lane among the lanes of its wavefront that pass want=true,
+// the lowest of them reserving the whole range on *ctr.  Every lane of the
+// wavefront must call.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t *ctr, bool want) {
+    const uint64_t m = __ballot(want);
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    uint32_t base = 0;
+    if (m != 0) {
+        const int leader = __builtin_ctzll(m);
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+    }
+    return base + rank;
+}
+
+__device__ __forceinline__ void store_rec(Rec *p, uint32_t slot, uint32_t count, uint64_t s0, uint64_t s1,
+                                          uint64_t s2) {
+    uint4 *w = reinterpret_cast<uint4 *>(p);
+    w[0] = make_uint4(slot, count, (uint32_t)s0, (uint32_t)(s0 >> 32));
+    w[1] = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
+}
+
+// LDS entry of `key` in the chunk's table (inserted if absent), or -1 when
+// kLdsProbe entries in a row hold other keys.
+__device__ __forceinline__ int lds_insert(unsigned long long *lkey, uint32_t cap, uint64_t key) {
+    uint32_t j = (uint32_t)(((uint64_t)(uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32) * cap) >> 32);
+#pragma unroll 1
+    for (uint32_t d = 0; d < kLdsProbe; ++d) {
+        const unsigned long long old = atomicCAS(&lkey[j], (unsigned long long)kEmpty, (unsigned long long)key);
+        if (old == kEmpty || old == key) return (int)j;
+        j = j + 1 == cap ? 0 : j + 1;
+    }
+    return -1;
+}
+
+// Value of another lane through the DPP crossbar (a VALU operation, no LDS
+// round trip): lanes whose source is outside the pattern, or whose row is
+// masked off, read 0.
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, false);
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+    return (uint64_t)dpp<kCtrl, kRowMask>((uint32_t)v) | (uint64_t)dpp<kCtrl, kRowMask>((uint32_t)(v >> 32)) << 32;
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ void dpp_add(uint32_t &c, uint64_t &a0, uint64_t &a1, uint64_t &a2) {
+    const uint32_t dc = dpp<kCtrl, kRowMask>(c);
+    const uint64_t d0 = dpp<kCtrl, kRowMask>(a0), d1 = dpp<kCtrl, kRowMask>(a1), d2 = dpp<kCtrl, kRowMask>(a2);
+    c += dc;
+    a0 += d0;
+    a1 += d1;
+    a2 += d2;
+}
+
+// Adds one vertex per lane (lanes with ok) to the chunk's LDS table and
+// returns its entry (-1: no room).  The lanes of a wavefront hold
+// consecutive vertices, so runs of lanes with equal keys (coherent primary
+// hits) are summed across the wavefront first and only the last lane of a
+// run touches the LDS table: a run's total is the wavefront's inclusive
+// prefix sum at its last lane minus the exclusive prefix sum at its first
+// (integer sums, exact modulo 2^64).  Every lane of the wavefront must call.
+__device__ __forceinline__ int merge_into_lds(unsigned long long *lkey, unsigned long long *ls0,
+                                              unsigned long long *ls1, unsigned long long *ls2, uint32_t *lcnt,
+                                              uint32_t cap, bool ok, uint64_t k, int64_t q0, int64_t q1,
+                                              int64_t q2) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t kv = ok ? k : kEmpty;
+    const uint64_t prev = dpp<0x138>(kv);  // wave_shr:1, the previous lane's key
+    const bool head = lane == 0 || prev != kv;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = (2ull << lane) - 1;  // lanes 0 .. lane
+    const uint64_t later = heads & ~upto;
+    const uint32_t tail = later ? (uint32_t)__builtin_ctzll(later) - 1 : 63u;  // last lane of my run
+    uint32_t cnt = ok ? 1u : 0u;
+    uint64_t a0 = (uint64_t)q0, a1 = (uint64_t)q1, a2 = (uint64_t)q2;
+    if (__ballot(ok && !head)) {  // some run spans several lanes
+        const uint32_t first = 63u - (uint32_t)__builtin_clzll(heads & upto);
+        uint32_t pc = cnt;
+        uint64_t p0 = a0, p1 = a1, p2 = a2;
+        dpp_add<0x111>(pc, p0, p1, p2);  // row_shr:1
+        dpp_add<0x112>(pc, p0, p1, p2);  // row_shr:2
+        dpp_add<0x114>(pc, p0, p1, p2);  // row_shr:4
+        dpp_add<0x118>(pc, p0, p1, p2);  // row_shr:8
+        dpp_add<0x142, 0xa>(pc, p0, p1, p2);  // row_bcast:15 into rows 1 and 3
+        dpp_add<0x143, 0xc>(pc, p0, p1, p2);  // row_bcast:31 into rows 2 and 3
+        // exclusive prefix at the run's first lane
+        const uint32_t ec = __shfl(pc - cnt, (int)first);
+        const uint64_t e0 = __shfl((unsigned long long)(p0 - a0), (int)first);
+        const uint64_t e1 = __shfl((unsigned long long)(p1 - a1), (int)first);
+        const uint64_t e2 = __shfl((unsigned long long)(p2 - a2), (int)first);
+        cnt = pc - ec;
+        a0 = p0 - e0;
+        a1 = p1 - e1;
+        a2 = p2 - e2;
+    }
+    int e = -1;
+    if (ok && lane == tail) {
+        e = lds_insert(lkey, cap, kv);
+        if (e >= 0) {
+            atomicAdd(&lcnt[e], cnt);
+            atomicAdd(&ls0[e], (unsigned long long)a0);
+            atomicAdd(&ls1[e], (unsigned long long)a1);
+            atomicAdd(&ls2[e], (unsigned long long)a2);
         }
-        if (fl == 0) {
-            slot = claim(t, key[i]);
-            if (slot == kNoSlot) {
-                fl = PF_V_OVERFLOW;
-                ++ovf;
-            } else {
-                atomicAdd(&hist[slot >> bin_shift], 1u);
+    }
+    e = __shfl(e, (int)tail);
+    return ok ? e : -1;
+}
+
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void aggregate_kernel(Tab t, const uint64_t *__restrict__ key,
+                                                       const float *__restrict__ r, const float *__restrict__ g,
+                                                       const float *__restrict__ b, uint8_t *__restrict__ flags,
+                                                       uint32_t *__restrict__ slot_out, uint32_t n, uint32_t tile,
+                                                       uint32_t cap, uint32_t nbins, uint32_t bin_shift,
+                                                       uint32_t *__restrict__ H, uint32_t *__restrict__ ntr,
+                                                       Rec *__restrict__ trec) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *lkey = reinterpret_cast<unsigned long long *>(lds);
+    unsigned long long *ls0 = lkey + cap, *ls1 = ls0 + cap, *ls2 = ls1 + cap;
+    uint32_t *lcnt = reinterpret_cast<uint32_t *>(ls2 + cap);  // count, then the group's slot
+    uint32_t *hist = lcnt + cap;
+    uint32_t *misc = hist + nbins;                              // [0] staged records, [1] overflowed vertices
+    for (uint32_t k = threadIdx.x; k < nbins; k += kT) hist[k] = 0;
+    if (threadIdx.x < 2) misc[threadIdx.x] = 0;
+    // chunks are dealt out with a stride so that every workgroup gets a mix
+    // of coherent and incoherent (or empty) parts of the stream
+    const uint32_t nchunks = (n + kChunk - 1) / kChunk;
+    Rec *out = trec + (size_t)blockIdx.x * tile;
+    for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+        const uint32_t c0 = ci * kChunk;
+        const uint32_t i1 = min(n, c0 + kChunk);
+        for (uint32_t j = threadIdx.x; j < cap; j += kT) {
+            lkey[j] = kEmpty;
+            ls0[j] = 0;
+            ls1[j] = 0;
+            ls2[j] = 0;
+            lcnt[j] = 0;
+        }
+        __syncthreads();
+        // only the flags (8 bits per vertex) and the LDS entries (16 bits,
+        // 0xffff = none) stay live across the barriers, packed; the rare
+        // vertex that finds no room reloads its key and contribution
+        uint32_t flp0 = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kPer; ++u) {
+            const uint32_t i = c0 + u * kT + threadIdx.x;
+            flp0 |= (uint32_t)(i < i1 ? flags[i] : (uint8_t)PF_V_INVALID) << (8 * u);
+        }
+        uint32_t flp = flp0;
+        uint64_t ep = 0;
+        // software pipeline: the contribution and key of vertex u + 1 are in
+        // flight while vertex u is merged
+        float nr = 0.0f, ng = 0.0f, nb = 0.0f;
+        uint64_t nk = 0;
+        if ((flp0 & 0xffu) == 0) {
+            const uint32_t i = c0 + threadIdx.x;
+            nr = r[i];
+            ng = g[i];
+            nb = b[i];
+            nk = key[i];
+        }
+#pragma unroll 1
+        for (uint32_t u = 0; u < kPer; ++u) {
+            const float cr = nr, cg = ng, cb = nb;
+            const uint64_t k = nk;
+            if (u + 1 < kPer && ((flp0 >> (8 * (u + 1))) & 0xffu) == 0) {
+                const uint32_t i = c0 + (u + 1) * kT + threadIdx.x;
+                nr = r[i];
+                ng = g[i];
+                nb = b[i];
+                nk = key[i];
+            }
+            uint32_t f = (flp0 >> (8 * u)) & 0xffu;
+            int64_t q0 = 0, q1 = 0, q2 = 0;
+            if (f == 0) f = fixed_point(cr, cg, cb, t.frac_bits, q0, q1, q2);
+            flp |= f << (8 * u);  // bits change only where they were 0
+            const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
+            ep |= (uint64_t)(uint16_t)e << (16 * u);
+        }
+        __syncthreads();
+        // one probe / claim and one staged record per group; the first probes
+        // of a thread's entries are issued before either is resolved
+        uint64_t fk[kFlush];
+        uint32_t fs[kFlush], fcur[kFlush];
+#pragma unroll
+        for (uint32_t v = 0; v < kFlush; ++v) {
+            const uint32_t j = v * kT + threadIdx.x;
+            fk[v] = j < cap ? lkey[j] : kEmpty;
+            fs[v] = 0;
+            fcur[v] = 0;
+            if (fk[v] != kEmpty) {
+                fs[v] = home_of(fk[v], t.mask);
+                fcur[v] = load_fp_probe(&t.cell[fs[v]].fp);
             }
         }
-        if (fl != fl0) flags[i] = fl;
-        slot_out[i] = slot;
+#pragma unroll
+        for (uint32_t v = 0; v < kFlush; ++v) {
+            const uint32_t j = v * kT + threadIdx.x;
+            uint32_t s = kNoSlot;
+            if (fk[v] != kEmpty) {
+                s = claim_from(t, fk[v], fingerprint_of(fk[v]), fs[v], fcur[v]);
+                if (s == kNoSlot) atomicAdd(&misc[1], lcnt[j]);
+            }
+            const bool stage = fk[v] != kEmpty && s != kNoSlot;
+            const uint32_t pos = wave_reserve(&misc[0], stage);
+            if (stage) {
+                store_rec(out + pos, s, lcnt[j], ls0[j], ls1[j], ls2[j]);
+                atomicAdd(&hist[s >> bin_shift], 1u);
+            }
+            if (fk[v] != kEmpty) lcnt[j] = s;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (uint32_t u = 0; u < kPer; ++u) {
+            const uint32_t i = c0 + u * kT + threadIdx.x;
+            uint32_t f = (flp >> (8 * u)) & 0xffu;
+            const uint32_t e = (uint32_t)(ep >> (16 * u)) & 0xffffu;
+            uint32_t s = kNoSlot;
+            bool alone = false;
+            int64_t q0 = 0, q1 = 0, q2 = 0;
+            if (f == 0) {
+                if (e != 0xffffu) {
+                    s = lcnt[e];
+                } else {  // no room in the LDS table: a group of its own
+                    fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
+                    s = claim(t, key[i]);
+                    alone = s != kNoSlot;
+                    if (!alone) atomicAdd(&misc[1], 1u);
+                }
+                if (s == kNoSlot) f = PF_V_OVERFLOW;
+            }
+            const uint32_t pos = wave_reserve(&misc[0], alone);
+            if (alone) {
+                store_rec(out + pos, s, 1u, (uint64_t)q0, (uint64_t)q1, (uint64_t)q2);
+                atomicAdd(&hist[s >> bin_shift], 1u);
+            }
+            if (i < i1) {
+                if (f != ((flp0 >> (8 * u)) & 0xffu)) flags[i] = (uint8_t)f;
+                slot_out[i] = s;
+            }
+        }
+        __syncthreads();  // the table is cleared for the next chunk
     }
-    if (ovf) add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], ovf);
     __syncthreads();
     uint32_t *row = H + (size_t)blockIdx.x * nbins;
     for (uint32_t k = threadIdx.x; k < nbins; k += kT) row[k] = hist[k];
+    if (threadIdx.x == 0) {
+        ntr[blockIdx.x] = misc[0];
+        if (misc[1]) add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], misc[1]);
+    }
 }
 
 // Per bin: exclusive running offset over the tiles (in place), bin total.
-__global__ __launch_bounds__(256) void colscan_kernel(uint32_t *__restrict__ H, uint32_t ntiles, uint32_t nbins,
-                                                      uint32_t *__restrict__ total) {
-    const uint32_t bin = blockIdx.x * 256 + threadIdx.x;
-    if (bin >= nbins) return;
-    uint32_t run = 0;
-    for (uint32_t t = 0; t < ntiles; ++t) {
-        const uint32_t c = H[(size_t)t * nbins + bin];
-        H[(size_t)t * nbins + bin] = run;
-        run += c;
+// A workgroup takes 16 bins; each of its 64 rows of lanes holds the counts of
+// 8 consecutive tiles in registers, so a column is loaded once, summed in
+// parallel and rewritten without a second read.
+constexpr int kScanBins = 16, kScanRows = 64, kScanPer = 8;
+static_assert(kScanRows * kScanPer >= kMaxTiles, "one register batch covers every tile");
+__global__ __launch_bounds__(kScanBins *kScanRows) void colscan_kernel(uint32_t *__restrict__ H, uint32_t ntiles,
+                                                                       uint32_t nbins,
+                                                                       uint32_t *__restrict__ total) {
+    __shared__ uint32_t part[kScanRows][kScanBins + 1];
+    const uint32_t bx = threadIdx.x % kScanBins, cy = threadIdx.x / kScanBins;
+    const uint32_t bin = blockIdx.x * kScanBins + bx;
+    const uint32_t t0 = cy * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t t = t0 + k;
+        v[k] = (bin < nbins && t < ntiles) ? H[(size_t)t * nbins + bin] : 0u;
     }
-    total[bin] = run;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    part[cy][bx] = s;
+    __syncthreads();
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < cy; ++c) run += part[c][bx];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t t = t0 + k;
+        if (bin < nbins && t < ntiles) H[(size_t)t * nbins + bin] = run;
+        run += v[k];
+    }
+    if (cy == kScanRows - 1 && bin < nbins) total[bin] = run;
 }
 
-// Exclusive scan of the bin totals (one workgroup, nbins <= 8192).
+// Exclusive scan of the bin totals (one workgroup).
 __global__ __launch_bounds__(1024) void binscan_kernel(const uint32_t *__restrict__ total, uint32_t nbins,
                                                        uint32_t *__restrict__ start) {
     __shared__ uint32_t part[1024];
@@ -155,35 +430,60 @@ __global__ __launch_bounds__(1024) void binscan_kernel(const uint32_t *__restric
         }
 }
 
-__global__ __launch_bounds__(kT) void scatter_kernel(const float *__restrict__ r, const float *__restrict__ g,
-                                                     const float *__restrict__ b, const uint8_t *__restrict__ flags,
-                                                     const uint32_t *__restrict__ slot, uint32_t n, uint32_t tile,
-                                                     uint32_t nbins, uint32_t bin_shift,
+constexpr uint32_t kBatch = 4;  // records per thread loaded before any is moved
+
+__global__ __launch_bounds__(kT) void scatter_kernel(const Rec *__restrict__ trec, const uint32_t *__restrict__ ntr,
+                                                     uint32_t tile, uint32_t nbins, uint32_t bin_shift,
                                                      const uint32_t *__restrict__ H,
-                                                     const uint32_t *__restrict__ start, uint4 *__restrict__ rec) {
+                                                     const uint32_t *__restrict__ start, Rec *__restrict__ rec) {
     extern __shared__ uint32_t cursor[];
+    const uint4 *in = reinterpret_cast<const uint4 *>(trec + (size_t)blockIdx.x * tile);
+    const uint32_t m = ntr[blockIdx.x];
+    uint4 lo[kBatch], hi[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {  // first batch in flight while the cursors are set up
+        const uint32_t j = u * kT + threadIdx.x;
+        if (j < m) {
+            lo[u] = in[2 * j];
+            hi[u] = in[2 * j + 1];
+        }
+    }
     const uint32_t *row = H + (size_t)blockIdx.x * nbins;
     for (uint32_t k = threadIdx.x; k < nbins; k += kT) cursor[k] = start[k] + row[k];
     __syncthreads();
-    const uint32_t i0 = blockIdx.x * tile;
-    const uint32_t i1 = min(n, i0 + tile);
-    for (uint32_t i = i0 + threadIdx.x; i < i1; i += kT) {
-        if (flags[i] != 0) continue;
-        const uint32_t s = slot[i];
-        const uint32_t pos = atomicAdd(&cursor[s >> bin_shift], 1u);
-        rec[pos] = make_uint4(s, __float_as_uint(r[i]), __float_as_uint(g[i]), __float_as_uint(b[i]));
+    for (uint32_t j0 = 0; j0 < m; j0 += kBatch * kT) {
+        if (j0) {
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) {
+                const uint32_t j = j0 + u * kT + threadIdx.x;
+                if (j < m) {
+                    lo[u] = in[2 * j];
+                    hi[u] = in[2 * j + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t j = j0 + u * kT + threadIdx.x;
+            if (j < m) {
+                const uint32_t pos = atomicAdd(&cursor[lo[u].x >> bin_shift], 1u);
+                uint4 *o = reinterpret_cast<uint4 *>(rec + pos);
+                o[0] = lo[u];
+                o[1] = hi[u];
+            }
+        }
     }
 }
 
 // One workgroup per bin: LDS sums over its records, then the exclusive
 // owner adds them to the cells and sets the occupancy bits of its words.
-__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const uint4 *__restrict__ rec,
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec *__restrict__ rec,
                                                                 const uint32_t *__restrict__ start,
                                                                 const uint32_t *__restrict__ total,
                                                                 uint32_t bin_slots) {
-    extern __shared__ unsigned long long lds[];
-    unsigned long long *sum0 = lds, *sum1 = lds + bin_slots, *sum2 = lds + 2 * bin_slots;
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(lds + 3 * bin_slots);
+    extern __shared__ unsigned long long lred[];
+    unsigned long long *sum0 = lred, *sum1 = lred + bin_slots, *sum2 = lred + 2 * bin_slots;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(lred + 3 * bin_slots);
     const uint32_t bin = blockIdx.x;
     const uint32_t base = bin * bin_slots;
     for (uint32_t k = threadIdx.x; k < bin_slots; k += kReduceThreads) {
@@ -193,26 +493,56 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const uin
         cnt[k] = 0;
     }
     __syncthreads();
+    const uint4 *in = reinterpret_cast<const uint4 *>(rec);
     const uint32_t j0 = start[bin], j1 = j0 + total[bin];
-    for (uint32_t j = j0 + threadIdx.x; j < j1; j += kReduceThreads) {
-        const uint4 e = rec[j];
-        const uint32_t loc = e.x - base;
-        int64_t q0, q1, q2;
-        fixed_point(__uint_as_float(e.y), __uint_as_float(e.z), __uint_as_float(e.w), t.frac_bits, q0, q1, q2);
-        atomicAdd(&sum0[loc], (unsigned long long)q0);
-        atomicAdd(&sum1[loc], (unsigned long long)q1);
-        atomicAdd(&sum2[loc], (unsigned long long)q2);
-        atomicAdd(&cnt[loc], 1u);
+    for (uint32_t jb = j0; jb < j1; jb += kBatch * kReduceThreads) {
+        uint4 lo[kBatch], hi[kBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t j = jb + u * kReduceThreads + threadIdx.x;
+            if (j < j1) {
+                lo[u] = in[2 * (size_t)j];
+                hi[u] = in[2 * (size_t)j + 1];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t j = jb + u * kReduceThreads + threadIdx.x;
+            if (j < j1) {
+                const uint32_t loc = lo[u].x - base;
+                atomicAdd(&cnt[loc], lo[u].y);
+                atomicAdd(&sum0[loc], (unsigned long long)lo[u].z | (unsigned long long)lo[u].w << 32);
+                atomicAdd(&sum1[loc], (unsigned long long)hi[u].x | (unsigned long long)hi[u].y << 32);
+                atomicAdd(&sum2[loc], (unsigned long long)hi[u].z | (unsigned long long)hi[u].w << 32);
+            }
+        }
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < bin_slots; k += kReduceThreads) {
-        const uint32_t c = cnt[k];
-        if (c == 0) continue;
-        pf_cell *cell = t.cell + base + k;
-        cell->count += c;
-        cell->sum[0] = (int64_t)((uint64_t)cell->sum[0] + sum0[k]);
-        cell->sum[1] = (int64_t)((uint64_t)cell->sum[1] + sum1[k]);
-        cell->sum[2] = (int64_t)((uint64_t)cell->sum[2] + sum2[k]);
+    // the cells of a thread's slots are all loaded before any is updated
+    uint4 *cells = reinterpret_cast<uint4 *>(t.cell + base);
+    for (uint32_t kb = 0; kb < bin_slots; kb += kBatch * kReduceThreads) {
+        uint32_t c[kBatch];
+        uint4 lo[kBatch], hi[kBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t k = kb + u * kReduceThreads + threadIdx.x;
+            c[u] = k < bin_slots ? cnt[k] : 0u;
+            if (c[u]) {
+                lo[u] = cells[2 * k];
+                hi[u] = cells[2 * k + 1];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t k = kb + u * kReduceThreads + threadIdx.x;
+            if (c[u]) {
+                const uint64_t s0 = ((uint64_t)lo[u].z | (uint64_t)lo[u].w << 32) + sum0[k];
+                const uint64_t s1 = ((uint64_t)hi[u].x | (uint64_t)hi[u].y << 32) + sum1[k];
+                const uint64_t s2 = ((uint64_t)hi[u].z | (uint64_t)hi[u].w << 32) + sum2[k];
+                cells[2 * k] = make_uint4(lo[u].x, lo[u].y + c[u], (uint32_t)s0, (uint32_t)(s0 >> 32));
+                cells[2 * k + 1] = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
+            }
+        }
     }
     // occupancy words of this bin (bins hold >= 32 slots, or the whole table)
     const uint32_t words = (bin_slots + 31) / 32;
@@ -239,23 +569,27 @@ hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *
     uint32_t *H = reinterpret_cast<uint32_t *>(base + p.off_h);
     uint32_t *tot = reinterpret_cast<uint32_t *>(base + p.off_tot);
     uint32_t *start = reinterpret_cast<uint32_t *>(base + p.off_start);
-    uint4 *rec = reinterpret_cast<uint4 *>(base + p.off_rec);
-    const size_t hist_lds = (size_t)p.nbins * 4;
-    const size_t red_lds = (size_t)p.bin_slots * 28;
+    uint32_t *ntr = reinterpret_cast<uint32_t *>(base + p.off_ntr);
+    Rec *trec = reinterpret_cast<Rec *>(base + p.off_trec);
+    Rec *rec = reinterpret_cast<Rec *>(base + p.off_rec);
     static bool attrs = false;  // dynamic LDS above 64 KB needs the attribute, set once per function
     if (!attrs) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(reduce_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4096 * 28));
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(aggregate_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(reduce_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4096 * 28));
         if (e != hipSuccess) return e;
         attrs = true;
     }
-    claim_kernel<<<p.ntiles, kT, hist_lds, st>>>(t, key, r, g, b, flags, slot_out, n, p.tile, p.nbins, p.bin_shift,
-                                                 H);
-    colscan_kernel<<<(p.nbins + 255) / 256, 256, 0, st>>>(H, p.ntiles, p.nbins, tot);
+    aggregate_kernel<<<p.ntiles, kT, p.lds_aggregate, st>>>(t, key, r, g, b, flags, slot_out, n, p.tile, p.cap,
+                                                            p.nbins, p.bin_shift, H, ntr, trec);
+    colscan_kernel<<<(p.nbins + kScanBins - 1) / kScanBins, kScanBins * kScanRows, 0, st>>>(H, p.ntiles, p.nbins,
+                                                                                          tot);
     binscan_kernel<<<1, 1024, 0, st>>>(tot, p.nbins, start);
-    scatter_kernel<<<p.ntiles, kT, hist_lds, st>>>(r, g, b, flags, slot_out, n, p.tile, p.nbins, p.bin_shift, H,
-                                                   start, rec);
-    reduce_kernel<<<p.nbins, kReduceThreads, red_lds, st>>>(t, rec, start, tot, p.bin_slots);
+    scatter_kernel<<<p.ntiles, kT, (size_t)p.nbins * 4, st>>>(trec, ntr, p.tile, p.nbins, p.bin_shift, H, start,
+                                                              rec);
+    reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot, p.bin_slots);
     return hipGetLastError();
 }
 

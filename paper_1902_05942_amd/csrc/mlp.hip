@@ -253,9 +253,9 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         }
         if (lg == 0) {
             const pf_cell c = A.t.cell[A.slot[v]];
-            L.target[(r0 + lr) * 4 + 0] = cell_average(c.sum[0], c.count, A.t.frac_bits);
-            L.target[(r0 + lr) * 4 + 1] = cell_average(c.sum[1], c.count, A.t.frac_bits);
-            L.target[(r0 + lr) * 4 + 2] = cell_average(c.sum[2], c.count, A.t.frac_bits);
+            L.target[(r0 + lr) * 4 + 0] = A.t.average(c, 0);
+            L.target[(r0 + lr) * 4 + 1] = A.t.average(c, 1);
+            L.target[(r0 + lr) * 4 + 2] = A.t.average(c, 2);
         }
     }
     __syncthreads();

@@ -28,6 +28,7 @@ pf_status check_table(const pf_table *t) {
     if (t->log2_slots < 4 || t->log2_slots > 30) return PF_ERANGE;
     if (t->max_probe < 1 || (uint64_t)t->max_probe > (1ull << t->log2_slots)) return PF_ERANGE;
     if (t->frac_bits < 8 || t->frac_bits > 40) return PF_ERANGE;
+    if (t->sum_format != PF_SUMS_FIXED64 && t->sum_format != PF_SUMS_FLOAT32) return PF_EINVAL;
     return PF_OK;
 }
 
@@ -41,6 +42,7 @@ Tab to_tab(const pf_table *t) {
     k.mask = (uint32_t)((1ull << t->log2_slots) - 1);
     k.max_probe = t->max_probe;
     k.frac_bits = t->frac_bits;
+    k.fsum = t->sum_format == PF_SUMS_FLOAT32 ? 1u : 0u;
     return k;
 }
 
@@ -153,6 +155,7 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
     const pf_status s = check_table(t);
     if (s != PF_OK) return s;
     if (n > kMaxN) return PF_EINVAL;
+    if (t->sum_format != PF_SUMS_FIXED64) return PF_EINVAL;
     const size_t need = pf_insert_workspace_bytes(n, t->log2_slots);
     if (need == 0) return PF_ERANGE;
     if (n == 0) return PF_OK;
@@ -345,6 +348,7 @@ pf_status check_view(const pf_view &d) {
     if (d.r_out == d.r || d.g_out == d.g || d.b_out == d.b) return PF_EINVAL;
     pf_status s = check_table(&d.cur);
     if (s != PF_OK) return s;
+    if (d.cur.sum_format != PF_SUMS_FIXED64) return PF_EINVAL;
     if (d.temporal && !d.cur.blend) return PF_EINVAL;
     if (d.prev.cell) {
         s = check_table(&d.prev);

@@ -104,6 +104,10 @@ __device__ __forceinline__ float cell_average(int64_t sum, uint32_t count, int f
     return (float)(s / (double)count);
 }
 
+// binary32 sum held in the low word of a cell's sum (PF_SUMS_FLOAT32)
+__device__ __forceinline__ float *float_sum(pf_cell *c, int k) { return reinterpret_cast<float *>(&c->sum[k]); }
+__device__ __forceinline__ float float_sum_value(int64_t word) { return __uint_as_float((uint32_t)(uint64_t)word); }
+
 // Table handle passed to kernels by value.
 struct Tab {
     pf_cell *cell;
@@ -114,9 +118,16 @@ struct Tab {
     uint32_t mask;
     uint32_t max_probe;
     int32_t frac_bits;
+    uint32_t fsum;  // 1: binary32 sums in the low word of each sum (PF_SUMS_FLOAT32)
 
     // occupancy bitmap words (at least one; tables have >= 16 slots)
     __host__ __device__ __forceinline__ uint32_t nwords() const { return (uint32_t)(((uint64_t)mask + 32) >> 5); }
+
+    // average of component k of a cell in this table's sum format
+    __device__ __forceinline__ float average(const pf_cell &c, int k) const {
+        if (fsum) return float_sum_value(c.sum[k]) / (float)c.count;
+        return cell_average(c.sum[k], c.count, frac_bits);
+    }
 };
 
 // Fingerprint read while other lanes may claim slots: a relaxed atomic load.

@@ -76,6 +76,25 @@ __device__ __forceinline__ uint8_t fixed_point(float c0, float c1, float c2, int
     return 0;
 }
 
+// Contribution kept as binary32 (PF_SUMS_FLOAT32): 0 or PF_V_INVALID.
+__device__ __forceinline__ uint8_t float_contribution(float c0, float c1, float c2, float &v0, float &v1, float &v2) {
+    v0 = v1 = v2 = 0.0f;
+    if (!(isfinite(c0) && isfinite(c1) && isfinite(c2))) return PF_V_INVALID;
+    v0 = c0;
+    v1 = c1;
+    v2 = c2;
+    return 0;
+}
+
+// One binary32 atomic add per component (the hardware's global_atomic_add_f32).
+__device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, float v0, float v1, float v2) {
+    pf_cell *c = t.cell + slot;
+    add_u32(&c->count, cnt);
+    unsafeAtomicAdd(float_sum(c, 0), v0);
+    unsafeAtomicAdd(float_sum(c, 1), v1);
+    unsafeAtomicAdd(float_sum(c, 2), v2);
+}
+
 __device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, int64_t q0, int64_t q1,
                                            int64_t q2) {
     pf_cell *c = t.cell + slot;
@@ -152,9 +171,18 @@ struct AggLds {
 // device atomics.  Groups meet through a bucket array indexed by the slot's
 // low bits; a lane whose bucket was taken by another slot goes direct.  Must
 // be reached by every thread of the workgroup when agg > 1.
-template <int kBlockT>
+__device__ __forceinline__ void lds_add(unsigned long long *p, int64_t v) { atomicAdd(p, (unsigned long long)v); }
+__device__ __forceinline__ void lds_add(unsigned long long *p, float v) { atomicAdd(reinterpret_cast<float *>(p), v); }
+__device__ __forceinline__ int64_t lds_value(const unsigned long long *p, int64_t) { return (int64_t)*p; }
+__device__ __forceinline__ float lds_value(const unsigned long long *p, float) {
+    return *reinterpret_cast<const float *>(p);
+}
+
+// V is int64_t (fixed-point sums) or float (binary32 sums, in the low word
+// of each LDS accumulator).
+template <int kBlockT, typename V>
 __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &L, uint32_t agg, uint32_t slot,
-                                                 int64_t q0, int64_t q1, int64_t q2) {
+                                                 V q0, V q1, V q2) {
     const bool has = slot != kNoSlot;
     if (agg <= 1) {
         if (has) accumulate(t, slot, 1, q0, q1, q2);
@@ -174,14 +202,15 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
     const uint32_t leader = has ? L.bucket[bk] : tid;
     const bool member = has && L.slot[leader] == slot;
     if (member) {
-        atomicAdd(&L.acc[0][leader], (unsigned long long)q0);
-        atomicAdd(&L.acc[1][leader], (unsigned long long)q1);
-        atomicAdd(&L.acc[2][leader], (unsigned long long)q2);
+        lds_add(&L.acc[0][leader], q0);
+        lds_add(&L.acc[1][leader], q1);
+        lds_add(&L.acc[2][leader], q2);
         atomicAdd(&L.cnt[leader], 1u);
     }
     __syncthreads();
     if (member && leader == tid) {
-        accumulate(t, slot, L.cnt[tid], (int64_t)L.acc[0][tid], (int64_t)L.acc[1][tid], (int64_t)L.acc[2][tid]);
+        accumulate(t, slot, L.cnt[tid], lds_value(&L.acc[0][tid], q0), lds_value(&L.acc[1][tid], q0),
+                   lds_value(&L.acc[2][tid], q0));
     } else if (has && !member) {
         accumulate(t, slot, 1, q0, q1, q2);
     }
@@ -194,9 +223,9 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 template <bool kHasPrev>
 __device__ __forceinline__ bool temporal_cell(const Tab &cur, const Tab &prev, uint32_t s, float alpha, float beta) {
     const pf_cell c = cur.cell[s];
-    float v0 = cell_average(c.sum[0], c.count, cur.frac_bits);
-    float v1 = cell_average(c.sum[1], c.count, cur.frac_bits);
-    float v2 = cell_average(c.sum[2], c.count, cur.frac_bits);
+    float v0 = cur.average(c, 0);
+    float v1 = cur.average(c, 1);
+    float v2 = cur.average(c, 2);
     bool hit = false;
     if constexpr (kHasPrev) {
         const uint64_t key = cur.key[s];
@@ -241,9 +270,9 @@ __device__ __forceinline__ void query_vertex(const Tab &t, uint32_t slot, uint32
     } else {
         const pf_cell c = t.cell[slot];
         cnt = c.count;
-        a0 = cell_average(c.sum[0], cnt, t.frac_bits);
-        a1 = cell_average(c.sum[1], cnt, t.frac_bits);
-        a2 = cell_average(c.sum[2], cnt, t.frac_bits);
+        a0 = t.average(c, 0);
+        a1 = t.average(c, 1);
+        a2 = t.average(c, 2);
     }
     ro[i] = a0;
     go[i] = a1;

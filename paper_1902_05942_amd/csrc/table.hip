@@ -3,6 +3,8 @@
 // statistics.  Occupied slots are recorded in a bitmap (one atomicOr per
 // claimed slot, spread over 2^m/32 words) so that no kernel updates a
 // shared counter per cell.
+#include <type_traits>
+
 #include "pf_kernels.h"
 #include "pf_ops.h"
 
@@ -63,7 +65,8 @@ hipError_t launch_clear(const Tab &t, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------- insert
-template <bool kAgg>
+// V = int64_t: fixed-point sums; V = float: binary32 sums (PF_SUMS_FLOAT32).
+template <bool kAgg, typename V>
 __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *__restrict__ key,
                                                         const float *__restrict__ r, const float *__restrict__ g,
                                                         const float *__restrict__ b, uint8_t *__restrict__ flags,
@@ -72,8 +75,13 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *_
     const bool in = i < n;
     uint8_t fl = in ? flags[i] : (uint8_t)PF_V_INVALID;
     const uint8_t fl0 = fl;
-    int64_t q0 = 0, q1 = 0, q2 = 0;
-    if (fl == 0) fl = fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
+    V q0 = 0, q1 = 0, q2 = 0;
+    if (fl == 0) {
+        if constexpr (std::is_same<V, float>::value)
+            fl = float_contribution(r[i], g[i], b[i], q0, q1, q2);
+        else
+            fl = fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
+    }
     uint32_t slot = kNoSlot;
     if (fl == 0) {
         slot = find_or_claim(t, key[i]);
@@ -88,17 +96,26 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(Tab t, const uint64_t *_
         if (slot != kNoSlot) accumulate(t, slot, 1, q0, q1, q2);
     } else {
         __shared__ AggLds<kBlock> L;
-        accumulate_group<kBlock>(t, L, agg, slot, q0, q1, q2);
+        accumulate_group<kBlock, V>(t, L, agg, slot, q0, q1, q2);
     }
+}
+
+template <typename V>
+static void launch_insert_t(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
+                            uint8_t *flags, uint32_t *slot_out, uint32_t n, uint32_t agg_width, hipStream_t st) {
+    const uint32_t blocks = (n + kBlock - 1) / kBlock;
+    if (agg_width <= 1)
+        insert_kernel<false, V><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, 1);
+    else
+        insert_kernel<true, V><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, agg_width);
 }
 
 hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
                          uint8_t *flags, uint32_t *slot_out, uint32_t n, uint32_t agg_width, hipStream_t st) {
-    const uint32_t blocks = (n + kBlock - 1) / kBlock;
-    if (agg_width <= 1)
-        insert_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, 1);
+    if (t.fsum)
+        launch_insert_t<float>(t, key, r, g, b, flags, slot_out, n, agg_width, st);
     else
-        insert_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, r, g, b, flags, slot_out, n, agg_width);
+        launch_insert_t<int64_t>(t, key, r, g, b, flags, slot_out, n, agg_width, st);
     return hipGetLastError();
 }
 

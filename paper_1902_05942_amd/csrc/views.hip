@@ -44,6 +44,7 @@ __device__ __forceinline__ Tab to_tab(const pf_table &t) {
     k.mask = (uint32_t)((1ull << t.log2_slots) - 1);
     k.max_probe = t.max_probe;
     k.frac_bits = t.frac_bits;
+    k.fsum = 0;  // float tables are rejected on the host
     return k;
 }
 

@@ -100,6 +100,17 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_temporal_update(ctypes.byref(t3), None, ctypes.c_float(0.2), 0, None) == lp.PF_EINVAL
     assert L.pf_query_average(ctypes.byref(t3), fake, None, fake, fake, fake, fake, 5, 1, fake, fake, fake, None,
                               None) == lp.PF_EINVAL
+    # binary32 sums: accepted by the atomic insert's checks, refused by the binned insert; unknown formats refused
+    tf = lp.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(0x7C0000000000), 10, 1, 64, 24, ctypes.byref(tf)) == 0
+    assert tf.sum_format == lp.SUMS_FIXED64
+    tf.sum_format = lp.SUMS_FLOAT32
+    assert L.pf_insert_accumulate(ctypes.byref(tf), fake, fake, fake, None, fake, None, 5, 0, None) == lp.PF_EINVAL
+    assert L.pf_insert_accumulate(ctypes.byref(tf), fake, fake, fake, fake, fake, None, 5, 3, None) == lp.PF_ERANGE
+    assert L.pf_insert_accumulate_binned(ctypes.byref(tf), fake, fake, fake, fake, fake, fake, 5, fake, 1 << 30,
+                                         None) == lp.PF_EINVAL
+    tf.sum_format = 2
+    assert L.pf_clear(ctypes.byref(tf), None) == lp.PF_EINVAL
     # a corrupted table descriptor
     t.log2_slots = 40
     assert L.pf_clear(ctypes.byref(t), None) == lp.PF_ERANGE

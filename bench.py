@@ -39,8 +39,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=16)
     p.add_argument("--workload", default="hd_1080p_x3")
     p.add_argument("--agg", type=int, default=64, help="aggregation width of insert (0 = none)")
-    p.add_argument("--insert", choices=("atomic", "binned"), default="atomic",
-                   help="atomic: device atomics per aggregated group; binned: LDS reduction per slot range")
+    p.add_argument("--insert", choices=("atomic", "binned"), default="binned",
+                   help="binned: vertices merged per chunk in LDS, one record per group, reduced per slot range "
+                        "without atomics on the sums; atomic: device atomics per aggregated group")
     p.add_argument("--frames", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle timed on the host")
@@ -242,9 +243,22 @@ def main():
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    launches = {"insert_accumulate": ("aggregate, colscan, binscan, scatter, reduce" if a.insert == "binned"
+                                      else "insert")}
+    roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, a.workload, a.insert),
                 "algorithmic_bytes_per_launch": int(algo_bytes[dom])}
+
+    # random-access roofline of the headline (insert + query): per valid vertex
+    # the method makes a probe and a cell update when inserting and a probe and
+    # a cell read when looking up, plus one claim per cell (4V + C touches)
+    ra = random_access(dev, (1 << view.log2_slots) * 32)
+    touches = 4 * nv + cells
+    t_iq = (per["insert_accumulate"] + per["query_average"]) * 1e-6
+    ra["insert_query_touches"] = int(touches)
+    ra["achieved_G_touches_per_s"] = round(touches / t_iq / 1e9, 2)
+    ra["frac_of_gather"] = round(touches / t_iq / 1e9 / ra["G_per_s"]["gather_32B"], 4)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -268,6 +282,7 @@ def main():
         "rmse": {"unfiltered": round(q_noisy, 5), "filtered": round(q_plain, 5), "filtered_temporal": round(q_temporal, 5)},
         "mlp": mlp_info,
         "roofline": roofline,
+        "random_access": ra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -337,6 +352,39 @@ def main_multiview(a):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+
+
+def random_access(dev, footprint):
+    """Measured denominators at the table's footprint (library probe
+    kernels): random 32-byte gathers, scatters, cell read-modify-writes with
+    the insert's atomics and compare-and-swaps per second, and the copy
+    bandwidth over 1 GiB."""
+    import torch
+
+    import paper_1902_05942_amd as pf
+    buf = torch.empty(footprint, dtype=torch.uint8, device=dev)
+    buf.zero_()
+    rates = {}
+    for name, kind in (("gather_32B", pf.MB_GATHER), ("scatter_32B", pf.MB_SCATTER), ("cell_rmw", pf.MB_RMW),
+                       ("cas", pf.MB_CAS)):
+        pf.microbench(kind, buf, 32, 4)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        n = sum(pf.microbench(kind, buf, 32, 8, seed=11 + r) for r in range(3))
+        ev[1].record()
+        torch.cuda.synchronize()
+        rates[name] = round(n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9, 2)
+    del buf
+    big = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    pf.microbench(pf.MB_COPY, big)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    moved = sum(2 * pf.microbench(pf.MB_COPY, big) for _ in range(3))
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy = moved / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+    del big
+    return {"footprint_bytes": footprint, "G_per_s": rates, "copy_GB_per_s": round(copy, 1)}
 
 
 def cpu_baseline(frames, wl, k):

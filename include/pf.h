@@ -403,6 +403,31 @@ pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block,
                           uint32_t grid_per_cu, void *workspace, void *stream);
 
 /* ------------------------------------------------------------ diagnostics */
+/* ------------------------------------------------------------ diagnostics */
+/* Memory-system probe giving the filter's rooflines measured denominators
+ * (not a step of the method).  PF_MB_COPY copies the first half of buf to
+ * the second.  The other kinds make accesses_per_thread * PF_MB_THREADS
+ * accesses, each to a granule of `grain` bytes chosen at random (fmix64 of
+ * seed and the access number) among the bytes / grain granules of buf:
+ *   PF_MB_GATHER   reads the granule
+ *   PF_MB_SCATTER  writes the granule
+ *   PF_MB_RMW      adds to a 32-byte cell's count and three sums with the
+ *                  insert's device atomics (u32 + 3 x u64; grain 32)
+ *   PF_MB_CAS      compares-and-swaps the granule's first word
+ * buf (256-byte aligned) is overwritten; bytes / grain must be a power of
+ * two (PF_MB_COPY: bytes a multiple of 32).  sink: one device uint32 that
+ * keeps the reads alive (practically never written).
+ * Errors: PF_EINVAL (NULL, misaligned), PF_ERANGE (kind, grain, bytes,
+ * accesses_per_thread 0). */
+#define PF_MB_COPY 0
+#define PF_MB_GATHER 1
+#define PF_MB_SCATTER 2
+#define PF_MB_RMW 3
+#define PF_MB_CAS 4
+#define PF_MB_THREADS 2097152u
+pf_status pf_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint32_t accesses_per_thread,
+                        uint64_t seed, uint32_t *sink, void *stream);
+
 /* Derives USED, DISP and HIST from the table (occupancy bitmap and keys),
  * copies the PF_STATS_LEN counters to host memory and waits for the copy.
  * The only call that blocks the host. */

@@ -15,7 +15,8 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    V_OVERFLOW, V_RADRANGE, Mlp, PfError, Table, build_keys, clear, geometry, insert_accumulate,
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
-                   filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned)
+                   filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
+                   microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS)
 
 
 class MlpFallback:

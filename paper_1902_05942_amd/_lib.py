@@ -97,6 +97,7 @@ def _load():
                                vp], i),
         "pf_mlp_features": ([ctypes.POINTER(pf_geometry), vp, u64, vp, vp], i),
         "pf_mlp_infer": ([ctypes.POINTER(pf_mlp), ctypes.POINTER(pf_geometry), vp, vp, u64, vp, vp, vp, vp], i),
+        "pf_microbench": ([i, vp, u64, u32, u32, u64, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -111,7 +112,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats", "pf_mlp_bytes",
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
-            "pf_insert_workspace_bytes", "pf_insert_accumulate_binned")
+            "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench")
 
 
 def _ptr(t):
@@ -233,6 +234,20 @@ def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_ou
 def temporal_update(cur: Table, prev, alpha_old: float, mode: int = 0, stream=None):
     _check("pf_temporal_update", lib.pf_temporal_update(cur.ref, None if prev is None else prev.ref,
                                                         float(alpha_old), mode, _stream(stream)))
+
+
+MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS = 0, 1, 2, 3, 4
+MB_THREADS = 2097152
+
+
+def microbench(kind: int, buf, grain: int = 32, per_thread: int = 8, seed: int = 1, sink=None, stream=None):
+    """One memory-system probe launch over the whole of `buf` (a device
+    uint8 tensor, 256-byte aligned); returns the number of accesses made."""
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    _check("pf_microbench", lib.pf_microbench(kind, _ptr(buf), buf.numel(), grain, per_thread, seed, _ptr(sink),
+                                              _stream(stream)))
+    return buf.numel() // 2 if kind == MB_COPY else per_thread * MB_THREADS
 
 
 def read_stats(t: Table, stream=None):

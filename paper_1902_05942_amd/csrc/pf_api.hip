@@ -386,6 +386,24 @@ pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block,
     return launched(pfk::launch_views(dev_views, nviews, block, agg_width, grid_per_cu, ws, (hipStream_t)stream));
 }
 
+pf_status pf_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint32_t accesses_per_thread,
+                        uint64_t seed, uint32_t *sink, void *stream) {
+    if (kind < PF_MB_COPY || kind > PF_MB_CAS) return PF_ERANGE;
+    if (!buf || !sink || (reinterpret_cast<uintptr_t>(buf) % 256) || !aligned(sink)) return PF_EINVAL;
+    if (kind == PF_MB_COPY) {
+        if (bytes < 32 || bytes % 32) return PF_ERANGE;
+    } else {
+        if (grain != 16 && grain != 32 && grain != 64) return PF_ERANGE;
+        if (kind == PF_MB_RMW && grain != 32) return PF_ERANGE;
+        if (bytes < grain || bytes % grain) return PF_ERANGE;
+        const uint64_t granules = bytes / grain;
+        if (granules & (granules - 1)) return PF_ERANGE;
+        if (accesses_per_thread == 0) return PF_ERANGE;
+    }
+    return launched(pfk::launch_microbench(kind, buf, bytes, grain, (uint64_t)accesses_per_thread * PF_MB_THREADS,
+                                           seed, sink, (hipStream_t)stream));
+}
+
 pf_status pf_read_stats(const pf_table *t, uint64_t *host_out, void *stream) {
     const pf_status s = check_table(t);
     if (s != PF_OK) return s;

@@ -52,6 +52,8 @@ struct GeoArgs {
 };
 
 size_t views_counter_bytes();
+hipError_t launch_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint64_t accesses, uint64_t seed,
+                             uint32_t *sink, hipStream_t st);
 hipError_t launch_views(const pf_view *views_dev, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,
                         uint32_t *ws, hipStream_t st);
 hipError_t launch_mlp_init(const MlpArgs &a, hipStream_t st);

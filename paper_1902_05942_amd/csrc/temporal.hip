@@ -1,22 +1,116 @@
 // Temporal blend over two sets of averages (Section 3.4.1) for gfx950.
-// One lane per slot of the current table (grid-stride); lanes whose
-// occupancy bit is clear leave at once, so the work beyond a bitmap read is
-// proportional to the cells of the current frame.
+// One lane per occupancy word of the current table: its occupied slots are
+// taken four at a time, and each step of their lookups in the previous
+// table (cell and key, fingerprint probe, key check, old value) is issued
+// for all four before any result is used, so a lane waits for four
+// dependent round trips per four cells instead of per cell.  Work beyond
+// the bitmap read is proportional to the cells of the current frame.
 #include "pf_kernels.h"
 #include "pf_ops.h"
 
 namespace pfk {
 
-constexpr uint32_t kTemporalGrid = 2048;
+constexpr int kTB = 4;  // cells of one lane looked up together
 
 template <bool kHasPrev>
 __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta) {
-    const uint32_t nslots = cur.mask + 1;
+    const uint32_t nwords = cur.nwords();
     const uint32_t stride = gridDim.x * kBlock;
+    const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
     uint32_t hits = 0;
-    for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < nslots; s += stride) {
-        if (((cur.occ[s >> 5] >> (s & 31)) & 1u) == 0) continue;
-        hits += temporal_cell<kHasPrev>(cur, prev, s, alpha, beta) ? 1u : 0u;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nwords; j += stride) {
+        uint32_t w = cur.occ[j];
+        while (w) {
+            uint32_t s[kTB];
+            bool has[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                has[k] = w != 0;
+                s[k] = has[k] ? j * 32 + __builtin_ctz(w) : 0u;
+                w &= w - 1;
+            }
+            uint4 lo[kTB], hi[kTB];
+            uint64_t key[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                if (has[k]) {
+                    lo[k] = cells[2 * s[k]];
+                    hi[k] = cells[2 * s[k] + 1];
+                    if constexpr (kHasPrev) key[k] = cur.key[s[k]];
+                }
+            }
+            float v[kTB][3];
+            uint32_t cnt[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                if (!has[k]) continue;
+                pf_cell c;
+                c.fp = lo[k].x;
+                c.count = lo[k].y;
+                c.sum[0] = (int64_t)((uint64_t)lo[k].z | (uint64_t)lo[k].w << 32);
+                c.sum[1] = (int64_t)((uint64_t)hi[k].x | (uint64_t)hi[k].y << 32);
+                c.sum[2] = (int64_t)((uint64_t)hi[k].z | (uint64_t)hi[k].w << 32);
+                cnt[k] = c.count;
+                v[k][0] = cur.average(c, 0);
+                v[k][1] = cur.average(c, 1);
+                v[k][2] = cur.average(c, 2);
+            }
+            if constexpr (kHasPrev) {
+                // search each key in prev: fingerprint probe confirmed by the stored key
+                uint32_t p[kTB];
+                bool active[kTB], found[kTB];
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) {
+                    active[k] = has[k];
+                    found[k] = false;
+                    p[k] = has[k] ? home_of(key[k], prev.mask) : 0u;
+                }
+                for (uint32_t d = 0; d < prev.max_probe; ++d) {
+                    bool any = false;
+#pragma unroll
+                    for (int k = 0; k < kTB; ++k) any |= active[k];
+                    if (!any) break;
+                    uint32_t pf[kTB];
+                    uint64_t pk[kTB];
+#pragma unroll
+                    for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell[p[k]].fp : 0u;
+#pragma unroll
+                    for (int k = 0; k < kTB; ++k) {
+                        pk[k] = 0;
+                        if (active[k] && pf[k] == lo[k].x) pk[k] = prev.key[p[k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < kTB; ++k) {
+                        if (!active[k]) continue;
+                        if (pf[k] == 0) {
+                            active[k] = false;  // empty slot: not in prev
+                        } else if (pf[k] == lo[k].x && pk[k] == key[k]) {
+                            active[k] = false;
+                            found[k] = true;
+                        } else {
+                            p[k] = (p[k] + 1) & prev.mask;
+                        }
+                    }
+                }
+                float4 old[kTB];
+#pragma unroll
+                for (int k = 0; k < kTB; ++k)
+                    if (found[k]) old[k] = prev.blend[p[k]];
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) {
+                    if (!found[k]) continue;
+                    const float a0 = alpha * old[k].x, a1 = alpha * old[k].y, a2 = alpha * old[k].z;
+                    const float b0 = beta * v[k][0], b1 = beta * v[k][1], b2 = beta * v[k][2];
+                    v[k][0] = a0 + b0;
+                    v[k][1] = a1 + b1;
+                    v[k][2] = a2 + b2;
+                    ++hits;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kTB; ++k)
+                if (has[k]) cur.blend[s[k]] = make_float4(v[k][0], v[k][1], v[k][2], (float)cnt[k]);
+        }
     }
     if constexpr (kHasPrev) {
         // one device atomic per block, spread over 32 partial counters
@@ -32,10 +126,12 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
 hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, hipStream_t st) {
     (void)mode;
     const float beta = 1.0f - alpha_old;
+    uint32_t blocks = (cur.nwords() + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
     if (prev)
-        temporal_kernel<true><<<kTemporalGrid, kBlock, 0, st>>>(cur, *prev, alpha_old, beta);
+        temporal_kernel<true><<<blocks, kBlock, 0, st>>>(cur, *prev, alpha_old, beta);
     else
-        temporal_kernel<false><<<kTemporalGrid, kBlock, 0, st>>>(cur, cur, alpha_old, beta);
+        temporal_kernel<false><<<blocks, kBlock, 0, st>>>(cur, cur, alpha_old, beta);
     return hipGetLastError();
 }
 

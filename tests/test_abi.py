@@ -111,6 +111,16 @@ def test_argument_checks_return_before_launch(pf):
                                          None) == lp.PF_EINVAL
     tf.sum_format = 2
     assert L.pf_clear(ctypes.byref(tf), None) == lp.PF_EINVAL
+    # memory-system probe: kinds, granules and footprints are checked before any launch
+    buf = ctypes.c_void_p(0x7B0000000000)
+    assert L.pf_microbench(9, buf, 1 << 20, 32, 1, 1, fake, None) == lp.PF_ERANGE
+    assert L.pf_microbench(lp.MB_GATHER, buf, 1 << 20, 24, 1, 1, fake, None) == lp.PF_ERANGE
+    assert L.pf_microbench(lp.MB_RMW, buf, 1 << 20, 16, 1, 1, fake, None) == lp.PF_ERANGE
+    assert L.pf_microbench(lp.MB_GATHER, buf, 3 << 20, 32, 1, 1, fake, None) == lp.PF_ERANGE
+    assert L.pf_microbench(lp.MB_GATHER, buf, 1 << 20, 32, 0, 1, fake, None) == lp.PF_ERANGE
+    assert L.pf_microbench(lp.MB_GATHER, ctypes.c_void_p(0x7B0000000010), 1 << 20, 32, 1, 1, fake,
+                           None) == lp.PF_EINVAL
+    assert L.pf_microbench(lp.MB_COPY, buf, 48, 32, 1, 1, fake, None) == lp.PF_ERANGE
     # a corrupted table descriptor
     t.log2_slots = 40
     assert L.pf_clear(ctypes.byref(t), None) == lp.PF_ERANGE

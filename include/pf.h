@@ -234,19 +234,35 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
 
 /* --------------------------------------------------------------- temporal */
 /* Two sets of averages (Section 3.4.1).  For every occupied cell of `cur`
- * (found through its occupancy bitmap),
- * computes c_new = sum / count as in the lookup, searches its key in `prev`
- * (fingerprint probe confirmed by the stored 64-bit key) and stores
- *   mode 0: c = alpha_old * c_old + (1 - alpha_old) * c_new  (each product
- *           and the sum rounded to binary32; 1 - alpha_old rounded once),
- *           or c = c_new when the key is absent or prev is NULL,
- * into cur->blend together with the count.  Cells of prev that do not
- * occur in cur are dropped (prev holds the previous frame only).
+ * (found through its occupancy bitmap), computes c_new = sum / count as in
+ * the lookup, searches its key in `prev` (fingerprint probe confirmed by the
+ * stored 64-bit key) and stores into cur->blend the value c and a count N:
+ *   mode 0 (moving average): c = alpha_old * c_old + (1 - alpha_old) * c_new
+ *           (each product and the sum rounded to binary32; 1 - alpha_old
+ *           rounded once), N = this frame's count;
+ *   mode 1 (temporal integration): as pf_temporal_integrate with
+ *           max_samples = PF_MAX_SAMPLES;
+ * and c = c_new when the key is absent or prev is NULL.  Cells of prev that
+ * do not occur in cur are dropped (prev holds the previous frame only).
+ * The lookup with use_blend returns c and N as the vertex's count.
  * cur and prev must have the same log2_slots and both carry blend arrays.
- * Errors: PF_EINVAL (no blend array), PF_ERANGE (alpha_old outside [0, 1],
- * unknown mode, differing sizes). */
+ * Errors: PF_EINVAL (no blend array), PF_ERANGE (alpha_old outside [0, 1]
+ * in mode 0, unknown mode, differing sizes). */
 pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode,
                              void *stream);
+
+/* Temporal integration (Section 3.4.1): weighting the previous value by
+ * alpha = N_old / (N_old + N_new), where N_old is its stored count and N_new
+ * the cell's count in this frame, makes c the pooled mean of the samples of
+ * both; the stored count is min(N_old + N_new, max_samples), so that once
+ * the threshold is reached the history keeps a fixed weight (the paper's
+ * heuristic of accumulating up to a number of samples).  Arithmetic:
+ * alpha = N_old / (N_old + N_new) as one binary32 division of exact
+ * integers, then c = alpha * c_old + (1 - alpha) * c_new as in mode 0.
+ * Absent keys (or prev NULL): c = c_new, N = min(N_new, max_samples).
+ * max_samples in [1, PF_MAX_SAMPLES].  Errors as pf_temporal_update. */
+#define PF_MAX_SAMPLES 16777216u /* 2^24: counts stay exact in binary32 */
+pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint32_t max_samples, void *stream);
 
 
 /* ------------------------------------------------------- learned fallback */

@@ -57,6 +57,7 @@ def lib():
         L.orc_average.argtypes = [u64, vp, vp, i32, vp]
         L.orc_query.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_temporal_ema.argtypes = [u64, vp, vp, u64, vp, vp, f32, vp]
+        L.orc_temporal_integrate.argtypes = [u64, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         _lib = L
     return _lib
 
@@ -182,6 +183,21 @@ def temporal_ema(gkey, gnew, pkey, pold, alpha_old):
     return out[:3 * G].reshape(G, 3).copy()
 
 
+def temporal_integrate(gkey, gnew, gcnt, pkey, pold, pcnt, max_samples):
+    """Section 3.4.1's temporal integration with the sample-count threshold;
+    returns (values [G,3] float32, stored counts [G] uint32)."""
+    G = gkey.shape[0]
+    out = np.zeros(3 * max(G, 1), np.float32)
+    outn = np.zeros(max(G, 1), np.uint32)
+    pk = np.ascontiguousarray(pkey, np.uint64)
+    assert np.all(pk[1:] > pk[:-1]), "previous keys must be strictly ascending"
+    lib().orc_temporal_integrate(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(_f32(gnew).reshape(-1)),
+                                 _p(np.ascontiguousarray(gcnt, np.uint32)), pk.shape[0], _p(pk),
+                                 _p(_f32(pold).reshape(-1)), _p(np.ascontiguousarray(pcnt, np.uint32)),
+                                 int(max_samples), _p(out), _p(outn))
+    return out[:3 * G].reshape(G, 3).copy(), outn[:G].copy()
+
+
 def query(vgroup, gslot, gval, gcnt, r, g, b, flags):
     n = vgroup.shape[0]
     out = np.zeros(3 * max(n, 1), np.float32)
@@ -212,17 +228,21 @@ class FrameResult:
     table: TableSim
     out: np.ndarray          # [n,3] per-vertex result
     cnt: np.ndarray          # [n] per-vertex cell count (0 when unfiltered)
-    state: tuple             # (keys ascending, values) of placed cells, for the next frame
+    state: tuple             # (keys ascending, values, counts) of placed cells, for the next frame
 
 
 def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
-                 idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None):
+                 idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None,
+                 max_samples=None):
     """The whole hot path for one view and frame on the CPU.
 
     f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
     parameters cam, s, seed, log2_slots, max_probe, frac_bits (overridable).
     With temporal=True the lookup returns the moving average against
-    prev_state (the state of the previous frame, None for the first frame).
+    prev_state (the state of the previous frame, None for the first frame),
+    or, when max_samples is given, the temporal integration of Section 3.4.1
+    with the stored sample count kept at most max_samples; the lookup's count
+    is then the stored count.
     """
     A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
          ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
@@ -246,12 +266,17 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     sim = simulate_table(gkey, gfp, ghome, m, P)
     gavg = average(gcnt, gsum, F)
     placed = sim.gslot >= 0
-    if temporal and prev_state is not None:
+    gn = gcnt
+    if temporal and max_samples is not None:
+        pk, pv, pc = prev_state if prev_state is not None else (np.zeros(0, np.uint64), np.zeros((0, 3), np.float32),
+                                                                np.zeros(0, np.uint32))
+        gval, gn = temporal_integrate(gkey, gavg, gcnt, pk, pv, pc, max_samples)
+    elif temporal and prev_state is not None:
         gval = temporal_ema(gkey, gavg, prev_state[0], prev_state[1], alpha_old)
     else:
         gval = gavg
-    out, cnt = query(vgroup, sim.gslot, gval, gcnt, A["r"], A["g"], A["b"], flags)
-    state = (gkey[placed].copy(), gval[placed].copy())
+    out, cnt = query(vgroup, sim.gslot, gval, gn, A["r"], A["g"], A["b"], flags)
+    state = (gkey[placed].copy(), gval[placed].copy(), gn[placed].copy())
     return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,
                        sim, out, cnt, state)
 

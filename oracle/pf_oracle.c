@@ -453,3 +453,39 @@ void orc_temporal_ema(uint64_t G, const uint64_t *gkey, const float *gnew,
         }
     }
 }
+
+/* Temporal integration (Section 3.4.1): with alpha = N_old / (N_old + N_new)
+ * the blend of the previous value (N_old samples) and this frame's average
+ * (N_new samples) is their pooled mean.  The threshold heuristic of the same
+ * section keeps the stored count at most max_samples, after which the
+ * history keeps that weight.  alpha is the binary32 quotient of the two
+ * counts (exact integers below 2^24), then c = alpha*c_old + (1-alpha)*c_new
+ * with each product and the sum rounded, as for the moving average. */
+void orc_temporal_integrate(uint64_t G, const uint64_t *gkey, const float *gnew, const uint32_t *gcnt,
+                            uint64_t Gp, const uint64_t *pkey, const float *pold, const uint32_t *pcnt,
+                            uint32_t max_samples, float *out, uint32_t *outn)
+{
+    for (uint64_t g = 0; g < G; ++g) {
+        uint64_t lo = 0, hi = Gp;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (pkey[mid] < gkey[g]) lo = mid + 1; else hi = mid;
+        }
+        int found = (lo < Gp && pkey[lo] == gkey[g]);
+        uint64_t n = gcnt[g];
+        if (found) {
+            const uint64_t nsum = (uint64_t)pcnt[lo] + gcnt[g];
+            const float alpha = (float)pcnt[lo] / (float)nsum;
+            const float beta = 1.0f - alpha;
+            for (int c = 0; c < 3; ++c) {
+                float a = alpha * pold[3 * lo + c];
+                float b = beta * gnew[3 * g + c];
+                out[3 * g + c] = a + b;
+            }
+            n = nsum;
+        } else {
+            for (int c = 0; c < 3; ++c) out[3 * g + c] = gnew[3 * g + c];
+        }
+        outn[g] = (uint32_t)(n < max_samples ? n : max_samples);
+    }
+}

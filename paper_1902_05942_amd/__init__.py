@@ -16,7 +16,7 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
-                   microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS)
+                   microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES)
 
 
 class MlpFallback:
@@ -57,7 +57,8 @@ class FrameFilter:
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
-                 mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False):
+                 mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
+                 max_samples: "int | None" = None):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -66,6 +67,7 @@ class FrameFilter:
         self.log2_slots = log2_slots
         self.temporal = temporal
         self.alpha_old = alpha_old
+        self.max_samples = max_samples  # None: moving average; else temporal integration with this threshold
         self.agg_width = agg_width
         self.key = torch.empty(n_max, dtype=torch.int64, device=device)
         self.vflags = torch.empty(n_max, dtype=torch.uint8, device=device)
@@ -102,7 +104,10 @@ class FrameFilter:
         else:
             insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
         if self.temporal:
-            temporal_update(cur, self.prev, self.alpha_old)
+            if self.max_samples is None:
+                temporal_update(cur, self.prev, self.alpha_old)
+            else:
+                temporal_integrate(cur, self.prev, self.max_samples)
         if out is None:
             out = (torch.empty_like(r), torch.empty_like(g), torch.empty_like(b))
         query_average(cur, key, slot, r, g, b, vflags, self.temporal, out[0], out[1], out[2], cnt)

@@ -85,6 +85,7 @@ def _load():
         "pf_insert_accumulate_binned": ([T, vp, vp, vp, vp, vp, vp, u64, vp, ctypes.c_size_t, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
+        "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
         "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
         "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, vp], i),
@@ -112,7 +113,8 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats", "pf_mlp_bytes",
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
-            "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench")
+            "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
+            "pf_temporal_integrate")
 
 
 def _ptr(t):
@@ -234,6 +236,14 @@ def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_ou
 def temporal_update(cur: Table, prev, alpha_old: float, mode: int = 0, stream=None):
     _check("pf_temporal_update", lib.pf_temporal_update(cur.ref, None if prev is None else prev.ref,
                                                         float(alpha_old), mode, _stream(stream)))
+
+
+MAX_SAMPLES = 1 << 24
+
+
+def temporal_integrate(cur: Table, prev, max_samples: int = MAX_SAMPLES, stream=None):
+    _check("pf_temporal_integrate", lib.pf_temporal_integrate(cur.ref, None if prev is None else prev.ref,
+                                                              int(max_samples), _stream(stream)))
 
 
 MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS = 0, 1, 2, 3, 4

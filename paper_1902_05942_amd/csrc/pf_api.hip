@@ -181,12 +181,11 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
                                       r_out, g_out, b_out, count_out, (hipStream_t)stream));
 }
 
-pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode, void *stream) {
+static pf_status temporal(const pf_table *cur, const pf_table *prev, float alpha_old, int mode, uint32_t cap,
+                          void *stream) {
     pf_status s = check_table(cur);
     if (s != PF_OK) return s;
     if (!cur->blend) return PF_EINVAL;
-    if (!(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
-    if (mode != 0) return PF_ERANGE;
     if (prev) {
         s = check_table(prev);
         if (s != PF_OK) return s;
@@ -195,7 +194,18 @@ pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float al
     }
     Tab p;
     if (prev) p = to_tab(prev);
-    return launched(pfk::launch_temporal(to_tab(cur), prev ? &p : nullptr, alpha_old, mode, (hipStream_t)stream));
+    return launched(pfk::launch_temporal(to_tab(cur), prev ? &p : nullptr, alpha_old, mode, cap, (hipStream_t)stream));
+}
+
+pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode, void *stream) {
+    if (mode == 0 && !(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
+    if (mode != 0 && mode != 1) return PF_ERANGE;
+    return temporal(cur, prev, alpha_old, mode, PF_MAX_SAMPLES, stream);
+}
+
+pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint32_t max_samples, void *stream) {
+    if (max_samples < 1 || max_samples > PF_MAX_SAMPLES) return PF_ERANGE;
+    return temporal(cur, prev, 0.0f, 1, max_samples, stream);
 }
 
 // ------------------------------------------------------------------ learned fallback

@@ -12,8 +12,11 @@ namespace pfk {
 
 constexpr int kTB = 4;  // cells of one lane looked up together
 
-template <bool kHasPrev>
-__global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta) {
+// kIntegrate: temporal integration, alpha = N_old / (N_old + N_new) per cell
+// with the stored count kept at most `cap`; else the moving average with a
+// fixed alpha (the stored count is this frame's).
+template <bool kHasPrev, bool kIntegrate>
+__global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta, uint32_t cap) {
     const uint32_t nwords = cur.nwords();
     const uint32_t stride = gridDim.x * kBlock;
     const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
                 }
             }
             float v[kTB][3];
-            uint32_t cnt[kTB];
+            uint32_t cnt[kTB], keep[kTB];
 #pragma unroll
             for (int k = 0; k < kTB; ++k) {
                 if (!has[k]) continue;
@@ -51,6 +54,7 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
                 c.sum[1] = (int64_t)((uint64_t)hi[k].x | (uint64_t)hi[k].y << 32);
                 c.sum[2] = (int64_t)((uint64_t)hi[k].z | (uint64_t)hi[k].w << 32);
                 cnt[k] = c.count;
+                keep[k] = kIntegrate ? min(c.count, cap) : c.count;
                 v[k][0] = cur.average(c, 0);
                 v[k][1] = cur.average(c, 1);
                 v[k][2] = cur.average(c, 2);
@@ -99,8 +103,17 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
 #pragma unroll
                 for (int k = 0; k < kTB; ++k) {
                     if (!found[k]) continue;
-                    const float a0 = alpha * old[k].x, a1 = alpha * old[k].y, a2 = alpha * old[k].z;
-                    const float b0 = beta * v[k][0], b1 = beta * v[k][1], b2 = beta * v[k][2];
+                    float al = alpha, be = beta;
+                    if constexpr (kIntegrate) {
+                        // counts are exact integers in binary32 (at most 2^24)
+                        const float nsum = old[k].w + (float)cnt[k];
+                        al = old[k].w / nsum;
+                        be = 1.0f - al;
+                        const uint32_t n = (uint32_t)nsum;
+                        keep[k] = n < cap ? n : cap;
+                    }
+                    const float a0 = al * old[k].x, a1 = al * old[k].y, a2 = al * old[k].z;
+                    const float b0 = be * v[k][0], b1 = be * v[k][1], b2 = be * v[k][2];
                     v[k][0] = a0 + b0;
                     v[k][1] = a1 + b1;
                     v[k][2] = a2 + b2;
@@ -109,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
             }
 #pragma unroll
             for (int k = 0; k < kTB; ++k)
-                if (has[k]) cur.blend[s[k]] = make_float4(v[k][0], v[k][1], v[k][2], (float)cnt[k]);
+                if (has[k]) cur.blend[s[k]] = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
         }
     }
     if constexpr (kHasPrev) {
@@ -123,15 +136,22 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
     }
 }
 
-hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, hipStream_t st) {
-    (void)mode;
+hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, uint32_t cap,
+                           hipStream_t st) {
     const float beta = 1.0f - alpha_old;
     uint32_t blocks = (cur.nwords() + kBlock - 1) / kBlock;
     if (blocks > 4096) blocks = 4096;
-    if (prev)
-        temporal_kernel<true><<<blocks, kBlock, 0, st>>>(cur, *prev, alpha_old, beta);
-    else
-        temporal_kernel<false><<<blocks, kBlock, 0, st>>>(cur, cur, alpha_old, beta);
+    if (mode == 1) {
+        if (prev)
+            temporal_kernel<true, true><<<blocks, kBlock, 0, st>>>(cur, *prev, 0.0f, 0.0f, cap);
+        else
+            temporal_kernel<false, true><<<blocks, kBlock, 0, st>>>(cur, cur, 0.0f, 0.0f, cap);
+    } else {
+        if (prev)
+            temporal_kernel<true, false><<<blocks, kBlock, 0, st>>>(cur, *prev, alpha_old, beta, cap);
+        else
+            temporal_kernel<false, false><<<blocks, kBlock, 0, st>>>(cur, cur, alpha_old, beta, cap);
+    }
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ def table_contents(t: pf.Table):
 
 
 def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=False, alpha=0.2,
-              idx_base=0, in_place=False, clear=True, want_fp_home=True):
+              idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None):
     """One frame through the C ABI; returns per-vertex results and stats."""
     n = g["px"].numel()
     dev = g["px"].device
@@ -52,7 +52,9 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
         pf.insert_accumulate_binned(cur, key, g["r"], g["g"], g["b"], vflags, slot, ws)
     else:
         pf.insert_accumulate(cur, key, g["r"], g["g"], g["b"], vflags, slot if use_slot else None, agg)
-    if temporal:
+    if temporal and max_samples is not None:
+        pf.temporal_integrate(cur, prev, max_samples)
+    elif temporal:
         pf.temporal_update(cur, prev, alpha)
     if in_place:
         out = (g["r"].clone(), g["g"].clone(), g["b"].clone())

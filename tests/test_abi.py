@@ -92,6 +92,8 @@ def test_argument_checks_return_before_launch(pf):
                                   None) == lp.PF_EINVAL
     assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(1.5), 0, None) == lp.PF_ERANGE
     assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(0.2), 7, None) == lp.PF_ERANGE
+    assert L.pf_temporal_integrate(ctypes.byref(t), None, 0, None) == lp.PF_ERANGE
+    assert L.pf_temporal_integrate(ctypes.byref(t), None, (1 << 24) + 1, None) == lp.PF_ERANGE
     t2 = lp.pf_table()
     assert L.pf_table_carve(ctypes.c_void_p(0x7E0000000000), 11, 1, 64, 24, ctypes.byref(t2)) == 0
     assert L.pf_temporal_update(ctypes.byref(t), ctypes.byref(t2), ctypes.c_float(0.2), 0, None) == lp.PF_ERANGE

@@ -8,7 +8,7 @@ import torch
 import oracle
 import paper_1902_05942_amd as pf
 import synth
-from gpu_util import assert_bits_equal, check_frame_against_oracle, gpu_frame, to_dev
+from gpu_util import assert_bits_equal, check_frame_against_oracle, gpu_frame, table_contents, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +151,30 @@ def test_temporal_sixteen_frames_bit_exact(gpu, agg):
         if frame:
             assert int(res["stats"][pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, state[0]).sum())
         state = R.state
+
+
+@pytest.mark.parametrize("agg,max_samples", [(64, 1 << 24), ("binned", 40)])
+def test_temporal_integration_sixteen_frames_bit_exact(gpu, agg, max_samples):
+    """Temporal integration (alpha = N_old / (N_old + N_new), stored count
+    at most max_samples) over 16 frames: values and stored counts equal the
+    oracle's every frame; 40 makes the threshold bind within a few frames."""
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(20), pf.Table(20)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(16):
+        f = synth.generate(wl, frame=frame, width=480, height=270)
+        f["log2_slots"] = 20
+        cur, prev = tabs[frame % 2], (tabs[(frame + 1) % 2] if frame else None)
+        res = gpu_frame(f, to_dev(f), cur, prev=prev, agg=agg, temporal=True, max_samples=max_samples)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, max_samples=max_samples)
+        check_frame_against_oracle(res, R, cur)
+        blend = table_contents(cur)["blend"]
+        assert np.all(blend[:, 3] <= max_samples)
+        state = R.state
+    if max_samples == 40:
+        assert int(state[2].max()) == 40
 
 
 def test_temporal_full_hd_three_frames(gpu):

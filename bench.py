@@ -17,6 +17,10 @@ Other workloads (--workload):
   multiview_8      8 views of uneven resolution (59.5M vertex slots) in one
                    persistent launch per frame, workgroup size and
                    aggregation width chosen by the autotuner.
+  uhd_4k_x4        3840x2160x4 (33.2M slots, 2^25-slot table): a real frame,
+                   then synthetic key streams at table loads 0.1-0.7 for
+                   probe limits 32, 64, 128 (insert + lookup per point,
+                   displacement statistics, overflow counts).
 """
 from __future__ import annotations
 
@@ -110,6 +114,8 @@ def main():
         return copy_probe(a.copy_probe_mib)
     if a.workload == "multiview_8":
         return main_multiview(a)
+    if a.workload == "uhd_4k_x4":
+        return main_uhd(a)
     import numpy as np
     import torch
 
@@ -350,6 +356,104 @@ def main_multiview(a):
                      "traffic": counted_traffic("views_kernel", "multiview_8", "persistent"),
                      "algorithmic_bytes_per_launch": int(algo)},
         "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_uhd(a):
+    """3840x2160x4 (33,177,600 slots, 2^25-slot table): a real frame at the
+    default scale, then synthetic key streams at table loads 0.1 .. 0.7 for
+    probe limits 32, 64, 128.  Per point: insert (binned) + lookup time,
+    achieved load, mean displacement, displacement percentiles and overflow."""
+    import numpy as np
+    import torch
+
+    import paper_1902_05942_amd as pf
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = synth.get("uhd_4k_x4")
+    m = wl.views[0].log2_slots
+    n = 3840 * 2160 * 4
+    reps = max(3, min(a.steps, 20))
+    key = torch.empty(n, dtype=torch.int64, device=dev)
+    vflags = torch.empty(n, dtype=torch.uint8, device=dev)
+    slot = torch.empty(n, dtype=torch.int32, device=dev)
+    outs = [torch.empty(n, device=dev) for _ in range(3)]
+    ws = torch.empty(pf.insert_workspace_bytes(n, m), dtype=torch.uint8, device=dev)
+
+    def timed(t, keys_fn, r, g, b):
+        """mean insert and lookup microseconds over reps (after one warm-up)"""
+        ti, tq = [], []
+        for k in range(reps + 1):
+            pf.clear(t)
+            keys_fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            pf.insert_accumulate_binned(t, key, r, g, b, vflags, slot, ws)
+            ev[1].record()
+            pf.query_average(t, key, slot, r, g, b, vflags, False, outs[0], outs[1], outs[2], None)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if k:
+                ti.append(ev[0].elapsed_time(ev[1]) * 1e3)
+                tq.append(ev[1].elapsed_time(ev[2]) * 1e3)
+        return float(np.mean(ti)), float(np.mean(tq))
+
+    def point(t, nvalid, ti, tq):
+        st = pf.read_stats(t)
+        used = int(st[pf.STAT_USED])
+        hist = st[pf.STAT_HIST:pf.STAT_HIST + 65].astype(np.int64)
+        cum = np.cumsum(hist) / max(used, 1)
+        return {"cells": used, "load": round(used / (1 << m), 4), "valid_vertices": nvalid,
+                "insert_us": round(ti, 1), "query_us": round(tq, 1),
+                "vertices_per_s": round(nvalid / ((ti + tq) * 1e-6), 1),
+                "mean_displacement": round(int(st[pf.STAT_DISP]) / max(used, 1), 3),
+                "displacement_p50": int(np.searchsorted(cum, 0.5)), "displacement_p99": int(np.searchsorted(cum, 0.99)),
+                "displacement_max": int(np.nonzero(hist)[0].max(initial=0)), "displacement_hist_le8":
+                [int(x) for x in hist[:9]], "overflow_vertices": int(st[pf.STAT_OVERFLOW])}
+
+    print("[bench] 4K frame", file=sys.stderr, flush=True)
+    f = synth.generate(wl, frame=0, device=dev)
+    nvalid = int(f["valid"].sum())
+    t = pf.Table(m, wl.max_probe, wl.frac_bits, with_blend=False)
+    pf.table_init(t)
+    frame = None
+    for s in (wl.s, wl.s / 5):
+        def keys_fn(s=s):
+            pf.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], s, f["seed"], 0,
+                          m, key, None, None, vflags)
+        ti, tq = timed(t, keys_fn, f["r"], f["g"], f["b"])
+        pt = dict(point(t, nvalid, ti, tq), s=s)
+        frame = frame or pt
+        print(f"[bench] scene s={s}: {json.dumps(pt)}", file=sys.stderr, flush=True)
+        scene_small = pt
+    del f
+    sweep = []
+    for load in (0.1, 0.3, 0.5, 0.7):
+        d = synth.synthetic_keys(n, int(load * (1 << m)), device=dev)
+        for P in (32, 64, 128):
+            tp = pf.Table(m, P, wl.frac_bits, with_blend=False)
+            pf.table_init(tp)
+
+            def keys_fn(d=d):
+                key.copy_(d["key"])
+                vflags.zero_()
+            ti, tq = timed(tp, keys_fn, d["r"], d["g"], d["b"])
+            pt = dict(point(tp, n, ti, tq), target_load=load, max_probe=P)
+            print(f"[bench] keys load {load} P {P}: {json.dumps(pt)}", file=sys.stderr, flush=True)
+            sweep.append(pt)
+            del tp
+        del d
+    line = {
+        "metric": "vertices/s filtered (insert+query) at 3840x2160x4 per table load",
+        "value": frame["vertices_per_s"], "unit": "vertices/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round((frame["insert_us"] + frame["query_us"]) * 1e-3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
+        "config": {"workload": "uhd_4k_x4", "vertex_slots": n, "log2_slots": m, "insert": "binned",
+                   "parallelism": "single-gpu"},
+        "scene": frame, "scene_small_cells": scene_small, "key_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 

@@ -58,6 +58,7 @@ def lib():
         L.orc_query.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_temporal_ema.argtypes = [u64, vp, vp, u64, vp, vp, f32, vp]
         L.orc_temporal_integrate.argtypes = [u64, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
+        L.orc_key_hashes.argtypes = [u64, vp, u32, vp, vp]
         _lib = L
     return _lib
 
@@ -279,6 +280,37 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     state = (gkey[placed].copy(), gval[placed].copy(), gn[placed].copy())
     return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,
                        sim, out, cnt, state)
+
+
+def key_hashes(key, log2_slots):
+    """Home index and fingerprint of given keys (Algorithm 1's two hashes)."""
+    k = np.ascontiguousarray(key, np.uint64)
+    home = np.zeros(max(k.shape[0], 1), np.uint32); fp = np.zeros(max(k.shape[0], 1), np.uint32)
+    lib().orc_key_hashes(k.shape[0], _p(k), log2_slots, _p(home), _p(fp))
+    return home[:k.shape[0]].copy(), fp[:k.shape[0]].copy()
+
+
+def filter_keys(key, r, g, b, valid, log2_slots, max_probe=64, frac_bits=24):
+    """Accumulation, table simulation and lookup (no temporal blend) for a
+    given key stream: Algorithm 1's hashes of each key, then the same steps
+    as filter_frame after key construction."""
+    key = np.ascontiguousarray(key, np.uint64)
+    n = key.shape[0]
+    home, fp = key_hashes(key, log2_slots)
+    flags = np.where(np.asarray(valid) != 0, 0, INVALID).astype(np.uint8)
+    q = quantize_radiance(r, g, b, frac_bits, flags)
+    gkey, gcnt, gsum, vgroup = group_by(key, flags, q)
+    G = gkey.shape[0]
+    first = np.full(G, -1, np.int64)
+    idx = np.nonzero(vgroup >= 0)[0]
+    first[vgroup[idx][::-1]] = idx[::-1]
+    gfp = fp[first] if G else np.zeros(0, np.uint32)
+    ghome = home[first] if G else np.zeros(0, np.uint32)
+    sim = simulate_table(gkey, gfp, ghome, log2_slots, max_probe)
+    gavg = average(gcnt, gsum, frac_bits)
+    out, cnt = query(vgroup, sim.gslot, gavg, gcnt, r, g, b, flags)
+    return FrameResult(key, fp, home, flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gavg, sim, out, cnt,
+                       (gkey[sim.gslot >= 0].copy(), gavg[sim.gslot >= 0].copy(), gcnt[sim.gslot >= 0].copy()))
 
 
 # ---------------------------------------------------- binary32 sums (variant)

@@ -149,6 +149,16 @@ int orc_level_of_detail(const float cam[3], float x, float y, float z)
 /* per-axis sign class: 1 positive, 2 negative, 0 zero (either sign) */
 static uint32_t normal_class(float c) { return (c > 0.0f) ? 1u : ((c < 0.0f) ? 2u : 0u); }
 
+/* i <- hash(x~, ...): the normal is left out of the home index;
+ * f <- hash2(x~, n, ...): 0 is the empty-cell sentinel. */
+static void key_hashes(uint64_t k, uint64_t mask, uint32_t *home, uint32_t *fp)
+{
+    const uint64_t kpos = k & ((1ULL << 56) - 1);   /* position and level only */
+    *home = (uint32_t)(orc_fmix64(kpos) & mask);
+    const uint32_t f = (uint32_t)(orc_splitmix64(k) >> 32);
+    *fp = f ? f : 1u;
+}
+
 /*
  * Builds key, fingerprint, home index and flags for n vertices.
  * Flagged vertices get key = fp = home = 0.
@@ -215,15 +225,17 @@ void orc_build_keys(uint64_t n,
                    | ((uint64_t)(uint32_t)(q[2] + ORC_QMAX) << 34)
                    | ((uint64_t)(uint32_t)(lp - ORC_LMIN) << 51)
                    | ((uint64_t)code << 56);
-        uint64_t kpos = k & ((1ULL << 56) - 1);   /* position and level only */
-
-        /* i <- hash(x~, ...): the normal is left out of the home index */
-        home[i] = (uint32_t)(orc_fmix64(kpos) & mask);
-        /* f <- hash2(x~, n, ...): 0 is the empty-cell sentinel */
-        uint32_t f = (uint32_t)(orc_splitmix64(k) >> 32);
-        fp[i] = f ? f : 1u;
+        key_hashes(k, mask, &home[i], &fp[i]);
         key[i] = k;
     }
+}
+
+/* Home index and fingerprint of given keys (for key streams that do not
+ * come from positions, such as the table-load sweeps). */
+void orc_key_hashes(uint64_t n, const uint64_t *key, uint32_t log2_slots, uint32_t *home, uint32_t *fp)
+{
+    const uint64_t mask = (1ULL << log2_slots) - 1;
+    for (uint64_t i = 0; i < n; ++i) key_hashes(key[i], mask, &home[i], &fp[i]);
 }
 
 /* Fixed-point radiance.  Only vertices not yet flagged are examined;

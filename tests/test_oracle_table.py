@@ -248,3 +248,31 @@ def test_interior_cell_error_matches_lognormal_variance():
     assert 0.85 < ratio < 1.15, ratio
     unf = ((f["r"].astype(np.float64) - mu) ** 2).mean()
     assert abs(unf / (mu ** 2 * (np.exp(sigma ** 2) - 1)) - 1) < 0.1
+
+
+def test_key_hashes_match_the_key_builder():
+    import synth
+    f = synth.generate(synth.get("tiny_64x64"), frame=0)
+    K = oracle.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"],
+                          f["seed"], 0, 14)
+    home, fp = oracle.key_hashes(K["key"], 14)
+    ok = K["flags"] == 0
+    assert np.array_equal(home[ok], K["home"][ok]) and np.array_equal(fp[ok], K["fp"][ok])
+
+
+def test_filter_keys_equals_filter_frame_on_its_keys():
+    import synth
+    f = synth.generate(synth.get("tiny_64x64"), frame=2)
+    Q = oracle.filter_frame(f, temporal=False)
+    R = oracle.filter_keys(Q.key, f["r"].numpy(), f["g"].numpy(), f["b"].numpy(), (Q.flags == 0).astype(np.uint8),
+                           f["log2_slots"])
+    assert np.array_equal(R.out, Q.out) and np.array_equal(R.gsum, Q.gsum)
+    assert np.array_equal(R.table.occupied, Q.table.occupied)
+
+
+def test_synthetic_keys_have_exactly_the_requested_cells():
+    import synth
+    d = synth.synthetic_keys(100000, 31337)
+    assert len(np.unique(d["key"].numpy())) == 31337
+    R = oracle.filter_keys(d["key"].numpy(), d["r"].numpy(), d["g"].numpy(), d["b"].numpy(), d["valid"].numpy(), 16)
+    assert len(R.gkey) == 31337 and int(R.gcnt.sum()) == 100000

@@ -43,12 +43,15 @@ def parse():
     p.add_argument("--warmup", type=int, default=16)
     p.add_argument("--workload", default="hd_1080p_x3")
     p.add_argument("--agg", type=int, default=64, help="aggregation width of insert (0 = none)")
-    p.add_argument("--insert", choices=("atomic", "binned"), default="binned",
+    p.add_argument("--insert", choices=("atomic", "binned", "fused"), default="fused",
                    help="binned: vertices merged per chunk in LDS, one record per group, reduced per slot range "
-                        "without atomics on the sums; atomic: device atomics per aggregated group")
+                        "without atomics on the sums; fused: the same with the keys built inside it; atomic: device "
+                        "atomics per aggregated group")
     p.add_argument("--frames", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle timed on the host")
+    p.add_argument("--lean", action="store_true",
+                   help="time the frames only (no probes, segments, quality or oracle legs): for profiler runs")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -138,46 +141,57 @@ def main():
         from synth.mlp_init import init_params
         fb = pf.MlpFallback(n, init_params(1902), batch=16384, steps=4, lr=1e-3)
     flt = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
-                         agg_width=a.agg, device=dev, binned=(a.insert == "binned"))
+                         agg_width=a.agg, device=dev, binned=(a.insert == "binned"), fused=(a.insert == "fused"))
     outs = (torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev))
     count = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
-    names = ["clear", "build_keys", "insert_accumulate", "temporal_update", "query_average"]
-    if use_mlp:
-        names.append("mlp_select_train_infer")
+    fused = a.insert == "fused"
 
-    def step(k, ev=None):
+    def stages(k):
+        """(name, call) of one frame's steps, in order"""
         f = frames[k % len(frames)]
         key, vflags, slot = flt.key[:n], flt.vflags[:n], flt.slot[:n]
         cur = flt.cur
-        if ev is not None:
-            ev[0].record(stream)
-        pf.clear(cur)
-        if ev is not None:
-            ev[1].record(stream)
-        pf.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"],
-                      f["seed"], 0, view.log2_slots, key, None, None, vflags)
-        if ev is not None:
-            ev[2].record(stream)
-        if flt.ws is not None:
-            pf.insert_accumulate_binned(cur, key, f["r"], f["g"], f["b"], vflags, slot, flt.ws)
+        st = [("clear", lambda: pf.clear(cur))]
+        if fused:
+            st.append(("build_keys_insert", lambda: pf.build_keys_insert_binned(
+                cur, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"], f["seed"], 0,
+                f["r"], f["g"], f["b"], key if use_mlp else None, vflags, slot, flt.ws)))
         else:
-            pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)
-        if ev is not None:
-            ev[3].record(stream)
-        pf.temporal_update(cur, flt.prev, wl.alpha_old)
-        if ev is not None:
-            ev[4].record(stream)
-        pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True, outs[0], outs[1], outs[2],
-                         count if use_mlp else None)
-        if ev is not None:
-            ev[5].record(stream)
+            st.append(("build_keys", lambda: pf.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"],
+                                                           f["valid"], f["cam"], f["s"], f["seed"], 0,
+                                                           view.log2_slots, key, None, None, vflags)))
+            if flt.ws is not None:
+                st.append(("insert_accumulate",
+                           lambda: pf.insert_accumulate_binned(cur, key, f["r"], f["g"], f["b"], vflags, slot, flt.ws)))
+            else:
+                st.append(("insert_accumulate",
+                           lambda: pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)))
+        st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
+        st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
+                                                             outs[0], outs[1], outs[2], count if use_mlp else None)))
         if use_mlp:
-            geo = pf.geometry(key, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["cam"])
-            fb.apply(cur, geo, vflags, count, slot, outs, f["seed"])
+            def mlp():
+                geo = pf.geometry(key, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["cam"])
+                fb.apply(cur, geo, vflags, count, slot, outs, f["seed"], timing=mlp_ev["now"])
+            st.append(("mlp_select_train_infer", mlp))
+        return st
+
+    names = [nm for nm, _ in stages(0)]
+    mlp_ev = {"now": None, "all": []}
+
+    def step(k, ev=None):
+        if use_mlp:
+            mlp_ev["now"] = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if ev is not None else None
             if ev is not None:
-                ev[6].record(stream)
+                mlp_ev["all"].append(mlp_ev["now"])
+        for j, (nm, call) in enumerate(stages(k)):
+            if ev is not None:
+                ev[j].record(stream)
+            call()
+        if ev is not None:
+            ev[len(names)].record(stream)
         flt.tables.reverse()
         flt.frames += 1
 
@@ -198,6 +212,9 @@ def main():
     gpu_ms = events[0][0].elapsed_time(events[-1][nev - 1])
     per = {nm: float(np.mean([events[k][j].elapsed_time(events[k][j + 1]) for k in range(a.steps)])) * 1e3
            for j, nm in enumerate(names)}  # microseconds
+    spread = {nm: [round(float(np.percentile([events[k][j].elapsed_time(events[k][j + 1]) * 1e3
+                                              for k in range(a.steps)], q)), 2) for q in (10, 50, 90)]
+              for j, nm in enumerate(names)}
     valid_total = sum(n_valid[(a.warmup + k) % len(frames)] for k in range(a.steps))
     ms_per_step = wall * 1e3 / a.steps
     value = valid_total / wall
@@ -205,6 +222,11 @@ def main():
     # statistics of the last frame (untimed): cells, displacement, temporal hits
     st = pf.read_stats(flt.prev)
     cells = int(st[pf.STAT_USED])
+    if a.lean:
+        print(json.dumps({"metric": "per-stage microseconds (lean profiling run)", "kernel_us":
+                          {k: round(v, 2) for k, v in per.items()}, "ms_per_step": round(wall * 1e3 / a.steps, 4),
+                          "insert": a.insert, "steps": a.steps}), flush=True)
+        return
 
     # quality: RMSE against the noise-free radiance over valid vertices (evaluation only)
     def rmse(x, f):
@@ -226,10 +248,17 @@ def main():
         q_sparse_ref = float(torch.sqrt(((torch.stack(o_ref, 1)[sparse] - f_last["truth"][sparse]) ** 2).mean()))
         mlp_us = per["mlp_select_train_infer"]
         flops = 4 * 16384 * 2 * (10240 + 15360)
+        train_us = float(np.mean([e[1].elapsed_time(e[2]) for e in mlp_ev["all"]])) * 1e3
+        select_us = float(np.mean([e[0].elapsed_time(e[1]) for e in mlp_ev["all"]])) * 1e3
+        infer_us = float(np.mean([e[2].elapsed_time(e[3]) for e in mlp_ev["all"]])) * 1e3
         mlp_info = {"sparse_vertices": int(sparse.sum()), "rmse_sparse_without": round(q_sparse_ref, 5),
                     "rmse_sparse_with": round(q_sparse_mlp, 5), "rmse_all_without": round(rmse(o_ref, f_last), 5),
                     "rmse_all_with": round(q_temporal, 5), "us_per_frame": round(mlp_us, 2),
-                    "train_flops_per_frame": flops, "loss": float(fb.net.loss().cpu()[0])}
+                    "select_us": round(select_us, 2), "train_us": round(train_us, 2), "infer_us": round(infer_us, 2),
+                    "train_flops_per_frame": flops,
+                    "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
+                    "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),
+                    "loss": float(fb.net.loss().cpu()[0])}
     q_noisy = rmse((f_last["r"], f_last["g"], f_last["b"]), f_last)
     plain = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=False, agg_width=a.agg,
                            device=dev)
@@ -246,11 +275,14 @@ def main():
         "insert_accumulate": n * (1 + 4) + nv * (8 + 12 + 4 + 28),
         "temporal_update": cells * (32 + 8 + 4 + 8 + 16 + 16) + (1 << view.log2_slots) // 8,
         "query_average": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12,
+        # fused: positions, normals, valid in; flags and slot out; contribution, probe, cell update per valid vertex
+        "build_keys_insert": n * (6 * 4 + 1 + 1 + 4) + nv * (12 + 4 + 28),
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
     launches = {"insert_accumulate": ("aggregate, colscan, binscan, scatter, reduce" if a.insert == "binned"
-                                      else "insert")}
+                                      else "insert"),
+                "build_keys_insert": "aggregate (keys built in it), colscan, binscan, scatter, reduce"}
     roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, a.workload, a.insert),
@@ -261,7 +293,8 @@ def main():
     # a cell read when looking up, plus one claim per cell (4V + C touches)
     ra = random_access(dev, (1 << view.log2_slots) * 32)
     touches = 4 * nv + cells
-    t_iq = (per["insert_accumulate"] + per["query_average"]) * 1e-6
+    t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
+    t_iq = (t_ins + per["query_average"]) * 1e-6
     ra["insert_query_touches"] = int(touches)
     ra["achieved_G_touches_per_s"] = round(touches / t_iq / 1e9, 2)
     ra["frac_of_gather"] = round(touches / t_iq / 1e9 / ra["G_per_s"]["gather_32B"], 4)
@@ -282,8 +315,10 @@ def main():
                    "parallelism": "single-gpu"},
         "vertex_slots_per_s": round(n * a.steps / wall, 1),
         "gpu_ms_per_step": round(gpu_ms / a.steps, 4),
-        "insert_query_vertices_per_s": round(nv / ((per["insert_accumulate"] + per["query_average"]) * 1e-6), 1),
+        "insert_query_vertices_per_s": round(nv / t_iq, 1),
         "kernel_us": {k: round(v, 2) for k, v in per.items()},
+        "kernel_us_p10_p50_p90": spread,
+        "segments": segments(dev, frames[(a.warmup + a.steps - 1) % len(frames)], view, wl),
         "cells_last_frame": cells,
         "rmse": {"unfiltered": round(q_noisy, 5), "filtered": round(q_plain, 5), "filtered_temporal": round(q_temporal, 5)},
         "mlp": mlp_info,
@@ -456,6 +491,51 @@ def main_uhd(a):
         "scene": frame, "scene_small_cells": scene_small, "key_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
+
+
+def segments(dev, f, view, wl, reps=20):
+    """The paper separates coherent primary hits from incoherent bounces
+    (Section 4): key construction + binned insert and the lookup timed on
+    the primary segment (the first W*H slots) and on the bounce segments
+    alone, each into a fresh table (medians of `reps` after one warm-up)."""
+    import numpy as np
+    import torch
+
+    import paper_1902_05942_amd as pf
+    wh = view.width * view.height
+    n = f["px"].numel()
+    out = {}
+    for name, lo, hi in (("primary", 0, wh), ("bounces", wh, n)):
+        m = hi - lo
+        sl = {k: f[k][lo:hi] for k in ("px", "py", "pz", "nx", "ny", "nz", "valid", "r", "g", "b")}
+        t = pf.Table(view.log2_slots, wl.max_probe, wl.frac_bits, with_blend=False, device=dev)
+        pf.table_init(t)
+        vflags = torch.empty(m, dtype=torch.uint8, device=dev)
+        slot = torch.empty(m, dtype=torch.int32, device=dev)
+        o = [torch.empty(m, device=dev) for _ in range(3)]
+        ws = torch.empty(pf.insert_workspace_bytes(m, view.log2_slots), dtype=torch.uint8, device=dev)
+        ti, tq = [], []
+        for k in range(reps + 1):
+            pf.clear(t)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            pf.build_keys_insert_binned(t, sl["px"], sl["py"], sl["pz"], sl["nx"], sl["ny"], sl["nz"], sl["valid"],
+                                        f["cam"], f["s"], f["seed"], lo, sl["r"], sl["g"], sl["b"], None, vflags,
+                                        slot, ws)
+            ev[1].record()
+            pf.query_average(t, None, slot, sl["r"], sl["g"], sl["b"], vflags, False, o[0], o[1], o[2], None)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if k:
+                ti.append(ev[0].elapsed_time(ev[1]) * 1e3)
+                tq.append(ev[1].elapsed_time(ev[2]) * 1e3)
+        nv = int(sl["valid"].sum())
+        cells = int(pf.read_stats(t)[pf.STAT_USED])
+        tki, tkq = float(np.median(ti)), float(np.median(tq))
+        out[name] = {"slots": m, "valid_vertices": nv, "cells": cells, "build_keys_insert_us": round(tki, 1),
+                     "query_us": round(tkq, 1), "vertices_per_s": round(nv / ((tki + tkq) * 1e-6), 1)}
+        del t, ws
+    return out
 
 
 def random_access(dev, footprint):

@@ -216,6 +216,20 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
                                       const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
                                       void *workspace, size_t workspace_bytes, void *stream);
 
+/* Key construction and the binned insert in one pass: the same keys, flags,
+ * slots and table as pf_build_keys(px.., kp, t->log2_slots, key, NULL,
+ * NULL, vflags) followed by pf_insert_accumulate_binned(t, key, r, g, b,
+ * vflags, slot_out, ...), without the key and flag round trip through
+ * memory between them.  key (nullable) receives the keys; vflags is
+ * output only (0, PF_V_INVALID, PF_V_KEYRANGE, PF_V_RADRANGE or
+ * PF_V_OVERFLOW per vertex); slot_out is required.  workspace as for
+ * pf_insert_accumulate_binned.  Errors: those of the two calls. */
+pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const float *py, const float *pz,
+                                      const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                      const pf_key_params *kp, const float *r, const float *g, const float *b,
+                                      uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                      void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------ query */
 /* Lookup (Sections 3.2, 3.3.1): for each vertex with vflags == 0, finds its
  * cell (from slot[i] when slot is non-NULL, else by probing with key[i]) and

@@ -16,7 +16,8 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
-                   microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES)
+                   microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
+                   build_keys_insert_binned)
 
 
 class MlpFallback:
@@ -36,14 +37,24 @@ class MlpFallback:
         self.counts = torch.zeros(2, dtype=torch.int32, device=device)
         self.ws = torch.empty(max(mlp_select_workspace_bytes(n_max), 4), dtype=torch.uint8, device=device)
 
-    def apply(self, table, geo, vflags, count, slot, out, seed):
+    def apply(self, table, geo, vflags, count, slot, out, seed, timing=None):
+        """timing: optional 4 events recorded on the current stream before
+        selection, after selection, after the training steps, after inference."""
         n = vflags.numel()
+        if timing:
+            timing[0].record()
         mlp_select(vflags, count, self.sparse_below, self.train_from, self.train_idx[:n], self.sparse_idx[:n],
                    self.counts, self.ws)
+        if timing:
+            timing[1].record()
         for k in range(self.steps):
             mlp_train_step(self.net, table, geo, slot, self.train_idx[:n], self.counts, self.batch,
                            (int(seed) ^ ((k + 1) * 0x9E3779B97F4A7C15)) & 0xFFFFFFFFFFFFFFFF, self.lr)
+        if timing:
+            timing[2].record()
         mlp_infer(self.net, geo, self.sparse_idx[:n], self.counts, out[0], out[1], out[2])
+        if timing:
+            timing[3].record()
 
 
 class FrameFilter:
@@ -58,7 +69,7 @@ class FrameFilter:
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
-                 max_samples: "int | None" = None):
+                 max_samples: "int | None" = None, fused: bool = False):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -76,7 +87,8 @@ class FrameFilter:
         self.frames = 0
         self.mlp = mlp
         self.ws = None
-        if binned:
+        self.fused = fused  # keys built inside the binned insert (implies binned)
+        if binned or fused:
             nb = insert_workspace_bytes(n_max, log2_slots)
             if nb == 0:
                 raise PfError("pf_insert_workspace_bytes", _lib.PF_ERANGE)
@@ -98,11 +110,15 @@ class FrameFilter:
         cnt = self.count[:n] if (with_count or self.mlp is not None) else None
         cur = self.cur
         clear(cur)
-        build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, self.log2_slots, key, None, None, vflags)
-        if self.ws is not None:
-            insert_accumulate_binned(cur, key, r, g, b, vflags, slot, self.ws)
+        if self.fused:  # the keys are only written when the learned fallback reads them
+            build_keys_insert_binned(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b,
+                                     key if self.mlp is not None else None, vflags, slot, self.ws)
         else:
-            insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
+            build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, self.log2_slots, key, None, None, vflags)
+            if self.ws is not None:
+                insert_accumulate_binned(cur, key, r, g, b, vflags, slot, self.ws)
+            else:
+                insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
         if self.temporal:
             if self.max_samples is None:
                 temporal_update(cur, self.prev, self.alpha_old)

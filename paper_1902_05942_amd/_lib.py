@@ -83,6 +83,8 @@ def _load():
         "pf_insert_accumulate": ([T, vp, vp, vp, vp, vp, vp, u64, u32, vp], i),
         "pf_insert_workspace_bytes": ([u64, u32], ctypes.c_size_t),
         "pf_insert_accumulate_binned": ([T, vp, vp, vp, vp, vp, vp, u64, vp, ctypes.c_size_t, vp], i),
+        "pf_build_keys_insert_binned": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp, vp, vp,
+                                                          vp, ctypes.c_size_t, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_temporal_integrate": ([T, T, u32, vp], i),
@@ -114,7 +116,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
-            "pf_temporal_integrate")
+            "pf_temporal_integrate", "pf_build_keys_insert_binned")
 
 
 def _ptr(t):
@@ -222,6 +224,20 @@ def insert_workspace_bytes(n: int, log2_slots: int) -> int:
 def insert_accumulate_binned(t: Table, key, r, g, b, vflags, slot_out, workspace, stream=None):
     _check("pf_insert_accumulate_binned", lib.pf_insert_accumulate_binned(
         t.ref, _ptr(key), _ptr(r), _ptr(g), _ptr(b), _ptr(vflags), _ptr(slot_out), key.numel(), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def build_keys_insert_binned(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b, key, vflags,
+                             slot_out, workspace, stream=None):
+    kp = pf_key_params()
+    for c in range(3):
+        kp.cam[c] = float(cam[c])
+    kp.s = float(s)
+    kp.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    kp.idx_base = int(idx_base)
+    _check("pf_build_keys_insert_binned", lib.pf_build_keys_insert_binned(
+        t.ref, _ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(valid), ctypes.byref(kp), _ptr(r),
+        _ptr(g), _ptr(b), vflags.numel(), _ptr(key), _ptr(vflags), _ptr(slot_out), _ptr(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)))
 
 

@@ -45,6 +45,14 @@ struct __align__(16) Rec {
 };
 static_assert(sizeof(Rec) == 32, "record is two 16-byte words");
 
+// Inputs of key construction when the insert builds the keys itself.
+struct FusedKeys {
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    const uint8_t *valid;
+    KeyArgs a;
+    uint64_t *key_out;  // nullable
+};
+
 struct Plan {
     uint32_t log2_bins, nbins, bin_shift, bin_slots, ntiles, tile, cap;
     size_t lds_aggregate, lds_reduce;
@@ -226,13 +234,23 @@ __device__ __forceinline__ int merge_into_lds(unsigned long long *lkey, unsigned
     return ok ? e : -1;
 }
 
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void aggregate_kernel(Tab t, const uint64_t *__restrict__ key,
-                                                       const float *__restrict__ r, const float *__restrict__ g,
-                                                       const float *__restrict__ b, uint8_t *__restrict__ flags,
-                                                       uint32_t *__restrict__ slot_out, uint32_t n, uint32_t tile,
-                                                       uint32_t cap, uint32_t nbins, uint32_t bin_shift,
-                                                       uint32_t *__restrict__ H, uint32_t *__restrict__ ntr,
-                                                       Rec *__restrict__ trec) {
+// Key of vertex i built in the insert itself (Algorithm 1, as pf_build_keys).
+__device__ __forceinline__ uint8_t fused_key(const FusedKeys &fk, uint32_t i, uint64_t &k) {
+    const float x[3] = {fk.px[i], fk.py[i], fk.pz[i]};
+    const float nr[3] = {fk.nx[i], fk.ny[i], fk.nz[i]};
+    const bool v = fk.valid == nullptr || fk.valid[i] != 0;
+    uint32_t fp, home;
+    return vertex_key(x, nr, v, fk.a.cam, fk.a.s, fk.a.seed, fk.a.idx_base + i, fk.a.mask, k, fp, home);
+}
+
+// kKeys: keys are built here from positions and normals (fk) and the flags
+// are outputs only; otherwise key[] and flags[] come from pf_build_keys.
+template <bool kKeys>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void aggregate_kernel(
+    Tab t, const uint64_t *__restrict__ key, const float *__restrict__ r, const float *__restrict__ g,
+    const float *__restrict__ b, uint8_t *__restrict__ flags, uint32_t *__restrict__ slot_out, uint32_t n,
+    uint32_t tile, uint32_t cap, uint32_t nbins, uint32_t bin_shift, uint32_t *__restrict__ H,
+    uint32_t *__restrict__ ntr, Rec *__restrict__ trec, FusedKeys fk) {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *lkey = reinterpret_cast<unsigned long long *>(lds);
     unsigned long long *ls0 = lkey + cap, *ls1 = ls0 + cap, *ls2 = ls1 + cap;
@@ -259,14 +277,33 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         // only the flags (8 bits per vertex) and the LDS entries (16 bits,
         // 0xffff = none) stay live across the barriers, packed; the rare
         // vertex that finds no room reloads its key and contribution
-        uint32_t flp0 = 0;
+        uint32_t flp0 = 0, flp = 0;
+        uint64_t ep = 0;
+        if constexpr (kKeys) {
+            flp0 = 0xffffffffu;  // no input flags: every vertex's flags are written
+#pragma unroll 1
+            for (uint32_t u = 0; u < kPer; ++u) {
+                const uint32_t i = c0 + u * kT + threadIdx.x;
+                uint32_t f = PF_V_INVALID;
+                uint64_t k = 0;
+                int64_t q0 = 0, q1 = 0, q2 = 0;
+                if (i < i1) {
+                    const float cr = r[i], cg = g[i], cb = b[i];
+                    f = fused_key(fk, i, k);
+                    if (fk.key_out) fk.key_out[i] = k;
+                    if (f == 0) f = fixed_point(cr, cg, cb, t.frac_bits, q0, q1, q2);
+                }
+                flp |= f << (8 * u);
+                const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
+                ep |= (uint64_t)(uint16_t)e << (16 * u);
+            }
+        } else {
 #pragma unroll
         for (uint32_t u = 0; u < kPer; ++u) {
             const uint32_t i = c0 + u * kT + threadIdx.x;
             flp0 |= (uint32_t)(i < i1 ? flags[i] : (uint8_t)PF_V_INVALID) << (8 * u);
         }
-        uint32_t flp = flp0;
-        uint64_t ep = 0;
+        flp = flp0;
         // software pipeline: the contribution and key of vertex u + 1 are in
         // flight while vertex u is merged
         float nr = 0.0f, ng = 0.0f, nb = 0.0f;
@@ -296,19 +333,20 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
             ep |= (uint64_t)(uint16_t)e << (16 * u);
         }
+        }
         __syncthreads();
         // one probe / claim and one staged record per group; the first probes
         // of a thread's entries are issued before either is resolved
-        uint64_t fk[kFlush];
+        uint64_t gk[kFlush];
         uint32_t fs[kFlush], fcur[kFlush];
 #pragma unroll
         for (uint32_t v = 0; v < kFlush; ++v) {
             const uint32_t j = v * kT + threadIdx.x;
-            fk[v] = j < cap ? lkey[j] : kEmpty;
+            gk[v] = j < cap ? lkey[j] : kEmpty;
             fs[v] = 0;
             fcur[v] = 0;
-            if (fk[v] != kEmpty) {
-                fs[v] = home_of(fk[v], t.mask);
+            if (gk[v] != kEmpty) {
+                fs[v] = home_of(gk[v], t.mask);
                 fcur[v] = load_fp_probe(&t.cell[fs[v]].fp);
             }
         }
@@ -316,17 +354,17 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         for (uint32_t v = 0; v < kFlush; ++v) {
             const uint32_t j = v * kT + threadIdx.x;
             uint32_t s = kNoSlot;
-            if (fk[v] != kEmpty) {
-                s = claim_from(t, fk[v], fingerprint_of(fk[v]), fs[v], fcur[v]);
+            if (gk[v] != kEmpty) {
+                s = claim_from(t, gk[v], fingerprint_of(gk[v]), fs[v], fcur[v]);
                 if (s == kNoSlot) atomicAdd(&misc[1], lcnt[j]);
             }
-            const bool stage = fk[v] != kEmpty && s != kNoSlot;
+            const bool stage = gk[v] != kEmpty && s != kNoSlot;
             const uint32_t pos = wave_reserve(&misc[0], stage);
             if (stage) {
                 store_rec(out + pos, s, lcnt[j], ls0[j], ls1[j], ls2[j]);
                 atomicAdd(&hist[s >> bin_shift], 1u);
             }
-            if (fk[v] != kEmpty) lcnt[j] = s;
+            if (gk[v] != kEmpty) lcnt[j] = s;
         }
         __syncthreads();
 #pragma unroll 1
@@ -342,7 +380,12 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                     s = lcnt[e];
                 } else {  // no room in the LDS table: a group of its own
                     fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
-                    s = claim(t, key[i]);
+                    uint64_t k;
+                    if constexpr (kKeys)
+                        fused_key(fk, i, k);
+                    else
+                        k = key[i];
+                    s = claim(t, k);
                     alone = s != kNoSlot;
                     if (!alone) atomicAdd(&misc[1], 1u);
                 }
@@ -560,9 +603,11 @@ size_t binned_workspace_bytes(uint32_t n, uint32_t log2_slots) {
     return binned::make_plan(n, log2_slots).bytes;
 }
 
-hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
-                                uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, hipStream_t st) {
-    using namespace binned;
+namespace binned {
+
+template <bool kKeys>
+static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
+                      uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, const FusedKeys &fk, hipStream_t st) {
     const uint32_t log2_slots = 32 - __builtin_clz(t.mask + 1) - 1;
     const Plan p = make_plan(n, log2_slots);
     char *base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ws) + 255) / 256 * 256);
@@ -574,16 +619,19 @@ hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *
     Rec *rec = reinterpret_cast<Rec *>(base + p.off_rec);
     static bool attrs = false;  // dynamic LDS above 64 KB needs the attribute, set once per function
     if (!attrs) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(aggregate_kernel),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(aggregate_kernel<false>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(aggregate_kernel<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(reduce_kernel),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4096 * 28));
         if (e != hipSuccess) return e;
         attrs = true;
     }
-    aggregate_kernel<<<p.ntiles, kT, p.lds_aggregate, st>>>(t, key, r, g, b, flags, slot_out, n, p.tile, p.cap,
-                                                            p.nbins, p.bin_shift, H, ntr, trec);
+    aggregate_kernel<kKeys><<<p.ntiles, kT, p.lds_aggregate, st>>>(t, key, r, g, b, flags, slot_out, n, p.tile, p.cap,
+                                                                   p.nbins, p.bin_shift, H, ntr, trec, fk);
     colscan_kernel<<<(p.nbins + kScanBins - 1) / kScanBins, kScanBins * kScanRows, 0, st>>>(H, p.ntiles, p.nbins,
                                                                                           tot);
     binscan_kernel<<<1, 1024, 0, st>>>(tot, p.nbins, start);
@@ -591,6 +639,23 @@ hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *
                                                               rec);
     reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot, p.bin_slots);
     return hipGetLastError();
+}
+
+}  // namespace binned
+
+hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
+                                uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, hipStream_t st) {
+    binned::FusedKeys none{};
+    return binned::run<false>(t, key, r, g, b, flags, slot_out, n, ws, none, st);
+}
+
+hipError_t launch_keys_insert_binned(const Tab &t, const float *px, const float *py, const float *pz,
+                                     const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                     const KeyArgs &a, uint64_t *key_out, const float *r, const float *g,
+                                     const float *b, uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws,
+                                     hipStream_t st) {
+    const binned::FusedKeys fk{px, py, pz, nx, ny, nz, valid, a, key_out};
+    return binned::run<true>(t, nullptr, r, g, b, flags, slot_out, n, ws, fk, st);
 }
 
 }  // namespace pfk

@@ -165,6 +165,38 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
                                               (hipStream_t)stream));
 }
 
+pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const float *py, const float *pz,
+                                      const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                      const pf_key_params *kp, const float *r, const float *g, const float *b,
+                                      uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                      void *workspace, size_t workspace_bytes, void *stream) {
+    const pf_status s = check_table(t);
+    if (s != PF_OK) return s;
+    if (!kp) return PF_EINVAL;
+    if (n > kMaxN) return PF_EINVAL;
+    if (t->sum_format != PF_SUMS_FIXED64) return PF_EINVAL;
+    if (!(kp->s > 0.0f) || !isfinite(kp->s) || !isfinite(kp->cam[0]) || !isfinite(kp->cam[1]) ||
+        !isfinite(kp->cam[2]))
+        return PF_ERANGE;
+    const size_t need = pf_insert_workspace_bytes(n, t->log2_slots);
+    if (need == 0) return PF_ERANGE;
+    if (n == 0) return PF_OK;
+    if (!px || !py || !pz || !nx || !ny || !nz || !r || !g || !b || !vflags || !slot_out || !workspace ||
+        workspace_bytes < need)
+        return PF_EINVAL;
+    if (!aligned(px) || !aligned(py) || !aligned(pz) || !aligned(nx) || !aligned(ny) || !aligned(nz) ||
+        !aligned(r) || !aligned(g) || !aligned(b) || !aligned(slot_out) || (key && !aligned(key)))
+        return PF_EINVAL;
+    pfk::KeyArgs a;
+    for (int c = 0; c < 3; ++c) a.cam[c] = kp->cam[c];
+    a.s = kp->s;
+    a.seed = kp->seed;
+    a.idx_base = kp->idx_base;
+    a.mask = (uint32_t)((1ull << t->log2_slots) - 1);
+    return launched(pfk::launch_keys_insert_binned(to_tab(t), px, py, pz, nx, ny, nz, valid, a, key, r, g, b, vflags,
+                                                   slot_out, (uint32_t)n, workspace, (hipStream_t)stream));
+}
+
 pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_t *slot, const float *r_in,
                            const float *g_in, const float *b_in, const uint8_t *vflags, uint64_t n, int use_blend,
                            float *r_out, float *g_out, float *b_out, uint32_t *count_out, void *stream) {

@@ -44,10 +44,20 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
     cnt = torch.empty(n, dtype=torch.int32, device=dev)
     if clear:
         pf.clear(cur)
-    pf.build_keys(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"], f["s"], f["seed"],
-                  idx_base, cur.log2_slots, key, fp, home, vflags)
-    flags_keys = vflags.clone()
-    if agg == "binned":
+    if agg == "fused":
+        fp = home = None
+        want_fp_home = False
+        ws = torch.empty(pf.insert_workspace_bytes(n, cur.log2_slots), dtype=torch.uint8, device=dev)
+        pf.build_keys_insert_binned(cur, g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"],
+                                    f["s"], f["seed"], idx_base, g["r"], g["g"], g["b"], key, vflags, slot, ws)
+        flags_keys = None
+    else:
+        pf.build_keys(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"], f["s"], f["seed"],
+                      idx_base, cur.log2_slots, key, fp, home, vflags)
+        flags_keys = vflags.clone()
+    if agg == "fused":
+        pass
+    elif agg == "binned":
         ws = torch.empty(pf.insert_workspace_bytes(n, cur.log2_slots), dtype=torch.uint8, device=dev)
         pf.insert_accumulate_binned(cur, key, g["r"], g["g"], g["b"], vflags, slot, ws)
     else:
@@ -67,7 +77,7 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
     torch.cuda.synchronize()
     res = {
         "key": key.cpu().numpy().view(np.uint64),
-        "flags_keys": flags_keys.cpu().numpy(),
+        "flags_keys": None if flags_keys is None else flags_keys.cpu().numpy(),
         "flags": vflags.cpu().numpy(),
         "out": np.stack([o.cpu().numpy() for o in out], 1),
         "cnt": cnt.cpu().numpy().view(np.uint32),

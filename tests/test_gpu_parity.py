@@ -95,6 +95,7 @@ def test_build_keys_edge_cases(gpu):
     ("scaled_ragged", 256, False),
     ("hd_full", BENCH_AGG, True), ("hd_full", 0, False),
     ("tiny", "binned", True), ("scaled_ragged", "binned", True), ("hd_full", "binned", True),
+    ("tiny", "fused", True), ("scaled_ragged", "fused", True), ("hd_full", "fused", True),
 ])
 def test_filter_frame_bit_exact(gpu, case, agg, use_slot):
     if case == "tiny":
@@ -132,7 +133,7 @@ def test_in_place_query(gpu):
     check_frame_against_oracle(res, oracle.filter_frame(_host(f), temporal=False), t)
 
 
-@pytest.mark.parametrize("agg", [0, 64, "binned"])
+@pytest.mark.parametrize("agg", [0, 64, "binned", "fused"])
 def test_temporal_sixteen_frames_bit_exact(gpu, agg):
     """Exponential moving average over 16 frames of the orbiting camera with
     double-buffered tables; every frame's output equals the oracle's."""

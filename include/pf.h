@@ -185,13 +185,15 @@ pf_status pf_build_keys(const float *px, const float *py, const float *pz,
  * On a PF_SUMS_FLOAT32 table the contribution is added as it is, with one
  * binary32 atomic add per component (no RADRANGE; a sum may overflow to
  * infinity), and combined lanes add in LDS first, in binary32 as well.
- * agg_width: 0 = one set of atomics per vertex; k > 0 = lanes of a wavefront
- * that reach the same slot combine their contributions first (at most k
- * distinct slots per wavefront are combined, the rest go directly).
+ * agg_width: 0 or 1 = one set of atomics per vertex; k = 2, 4, ..., 256 =
+ * the lanes of each group of k consecutive threads of a 256-thread
+ * workgroup that reach the same slot combine their contributions in LDS
+ * first (they meet through 2k buckets indexed by the slot's low bits; a
+ * lane whose bucket another slot took goes directly).
  * slot_out (nullable): receives the slot of each vertex (0xffffffff if
  * flagged) so that pf_query_average can skip probing.
  * Several batches may be inserted before one lookup.
- * Errors: PF_EINVAL, PF_ERANGE (agg_width > 64). */
+ * Errors: PF_EINVAL, PF_ERANGE (agg_width above 256 or not a power of two). */
 pf_status pf_insert_accumulate(const pf_table *t, const uint64_t *key, const float *r, const float *g,
                                const float *b, uint8_t *vflags, uint32_t *slot_out, uint64_t n,
                                uint32_t agg_width, void *stream);

@@ -373,25 +373,44 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
     }
 }
 
-// Sum of the per-workgroup partials in workgroup order, then Adam.
+// Sum of the per-workgroup partials, then Adam.  A workgroup takes 64
+// parameters; its four groups of 64 lanes each sum a contiguous quarter of
+// the partials (independent loads in flight together), and the four
+// quarter sums are added in a fixed order, so the result is deterministic.
+constexpr int kRedParams = 64;
 __global__ __launch_bounds__(kThreads) void reduce_adam_kernel(float *__restrict__ w, uint16_t *__restrict__ wb,
                                                                float *__restrict__ m, float *__restrict__ v,
                                                                const float *__restrict__ partial, uint32_t nblocks,
                                                                const uint32_t *__restrict__ counts, float lr,
                                                                float c1, float c2, float *__restrict__ loss,
                                                                float loss_scale) {
+    static_assert(kThreads == 4 * kRedParams, "four groups of 64 lanes");
+    __shared__ float quarter[4][kRedParams];
     if (counts[0] == 0) return;
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p > kNParam) return;
-    float g = 0.0f;
-    for (uint32_t b = 0; b < nblocks; ++b) g += partial[(size_t)b * (kNParam + 1) + p];
+    const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
+    const int p = blockIdx.x * kRedParams + pl;
+    const uint32_t per = (nblocks + 3) / 4;
+    const uint32_t b0 = grp * per, b1 = min(nblocks, b0 + per);
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (p <= kNParam) {
+        uint32_t bb = b0;
+        for (; bb + 8 <= b1; bb += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += partial[(size_t)(bb + u) * (kNParam + 1) + p];
+        }
+        for (; bb < b1; ++bb) acc[0] += partial[(size_t)bb * (kNParam + 1) + p];
+    }
+    quarter[grp][pl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (grp != 0 || p > kNParam) return;
+    const float g = (quarter[0][pl] + quarter[1][pl]) + (quarter[2][pl] + quarter[3][pl]);
     if (p == kNParam) {
         loss[0] = g * loss_scale;
         return;
     }
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float mn = b1 * m[p] + (1.0f - b1) * g;
-    const float vn = b2 * v[p] + (1.0f - b2) * (g * g);
+    const float be1 = 0.9f, be2 = 0.999f, eps = 1e-8f;
+    const float mn = be1 * m[p] + (1.0f - be1) * g;
+    const float vn = be2 * v[p] + (1.0f - be2) * (g * g);
     m[p] = mn;
     v[p] = vn;
     const float mh = mn * c1, vh = vn * c2;
@@ -637,7 +656,7 @@ hipError_t launch_mlp_train(const MlpArgs &a, const Tab &t, const GeoArgs &g, co
     mlp::train_kernel<<<nblocks, mlp::kThreads, lds, st>>>(A, a.wb, a.w, a.partial);
     const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
     const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));
-    mlp::reduce_adam_kernel<<<(mlp::kNParam + 1 + mlp::kThreads - 1) / mlp::kThreads, mlp::kThreads, 0, st>>>(
+    mlp::reduce_adam_kernel<<<(mlp::kNParam + 1 + mlp::kRedParams - 1) / mlp::kRedParams, mlp::kThreads, 0, st>>>(
         a.w, a.wb, a.m, a.v, a.partial, nblocks, counts, lr, (float)c1, (float)c2, a.loss,
         (float)(1.0 / (3.0 * (double)batch)));
     return hipGetLastError();

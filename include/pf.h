@@ -14,7 +14,8 @@
  *   4. looks up its cell and replaces its contribution by the cell average,
  *      sum divided by counter (Sections 3.2 and 3.3.1),
  *   5. blends cell averages across frames with an exponential moving
- *      average over two sets of averages (Section 3.4.1).
+ *      average over two sets of averages, or integrates them weighted by
+ *      sample counts (Section 3.4.1).
  *
  * Conventions for every entry point:
  *   - Pointers are DEVICE pointers unless marked [host].  The library never
@@ -28,7 +29,8 @@
  *     never fail a call: they are reported in the per-vertex flags.
  *   - Vertex arrays are structure-of-arrays, n elements each, naturally
  *     aligned (4 bytes for float/uint32, 8 for uint64).
- *   - n may be 0 (nothing is launched).  n must be below 2^32.
+ *   - n may be 0 (nothing is launched).  n is at most PF_MAX_VERTICES
+ *     (2^31); larger n fails with PF_EINVAL.
  */
 #ifndef PF_H
 #define PF_H
@@ -39,6 +41,8 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+#define PF_MAX_VERTICES 2147483648ull /* 2^31: vertex indices and launch sizes stay in 32 bits */
 
 /* ------------------------------------------------------------------ status */
 typedef int pf_status;
@@ -399,7 +403,7 @@ typedef struct pf_view {
     pf_table cur;             /* cleared, then filled by this launch */
     pf_table prev;            /* previous frame (read only); prev.cell == NULL: none */
     pf_key_params kp;
-    uint32_t n;               /* vertices (< 2^32) */
+    uint32_t n;               /* vertices (at most PF_MAX_VERTICES) */
     float alpha_old;          /* moving-average weight of the previous value */
     int32_t temporal;         /* 1: lookup returns the moving average (cur needs a blend array) */
     uint32_t reserved;

@@ -11,7 +11,7 @@ using pfk::Tab;
 
 namespace {
 
-constexpr uint64_t kMaxN = 0xffffffffull;  // vertex indices are 32-bit
+constexpr uint64_t kMaxN = PF_MAX_VERTICES;  // 32-bit indices: n + block - 1 cannot wrap
 
 template <typename T>
 bool aligned(const T *p) {
@@ -388,6 +388,7 @@ pf_status check_view(const pf_view &d) {
         !aligned(d.r_out) || !aligned(d.g_out) || !aligned(d.b_out) || (d.count_out && !aligned(d.count_out)))
         return PF_EINVAL;
     if (d.r_out == d.r || d.g_out == d.g || d.b_out == d.b) return PF_EINVAL;
+    if (d.n > kMaxN) return PF_EINVAL;
     pf_status s = check_table(&d.cur);
     if (s != PF_OK) return s;
     if (d.cur.sum_format != PF_SUMS_FIXED64) return PF_EINVAL;

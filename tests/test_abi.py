@@ -90,6 +90,11 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, fake, fake, None, 5, 512, None) == lp.PF_ERANGE
     assert L.pf_insert_accumulate(ctypes.byref(t), fake, fake, fake, fake, fake, None, 1 << 32, 0,
                                   None) == lp.PF_EINVAL
+    # launch sizes are computed in 32 bits: n is limited to 2^31
+    assert L.pf_build_keys(*([fake] * 6), None, (1 << 31) + 1, ctypes.byref(kp), 10, fake, None, None, fake,
+                           None) == lp.PF_EINVAL
+    assert L.pf_query_average(ctypes.byref(t), fake, None, fake, fake, fake, fake, (1 << 31) + 1, 0, fake, fake,
+                              fake, None, None) == lp.PF_EINVAL
     assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(1.5), 0, None) == lp.PF_ERANGE
     assert L.pf_temporal_update(ctypes.byref(t), None, ctypes.c_float(0.2), 7, None) == lp.PF_ERANGE
     assert L.pf_temporal_integrate(ctypes.byref(t), None, 0, None) == lp.PF_ERANGE

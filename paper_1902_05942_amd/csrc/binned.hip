@@ -234,13 +234,13 @@ __device__ __forceinline__ int merge_into_lds(unsigned long long *lkey, unsigned
     return ok ? e : -1;
 }
 
-// Key of vertex i built in the insert itself (Algorithm 1, as pf_build_keys).
+// Key of vertex i built in the insert itself (Algorithm 1, as pf_build_keys);
+// the caller has checked the vertex's valid byte.
 __device__ __forceinline__ uint8_t fused_key(const FusedKeys &fk, uint32_t i, uint64_t &k) {
     const float x[3] = {fk.px[i], fk.py[i], fk.pz[i]};
     const float nr[3] = {fk.nx[i], fk.ny[i], fk.nz[i]};
-    const bool v = fk.valid == nullptr || fk.valid[i] != 0;
     uint32_t fp, home;
-    return vertex_key(x, nr, v, fk.a.cam, fk.a.s, fk.a.seed, fk.a.idx_base + i, fk.a.mask, k, fp, home);
+    return vertex_key(x, nr, true, fk.a.cam, fk.a.s, fk.a.seed, fk.a.idx_base + i, fk.a.mask, k, fp, home);
 }
 
 // kKeys: keys are built here from positions and normals (fk) and the flags
@@ -281,18 +281,27 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         uint64_t ep = 0;
         if constexpr (kKeys) {
             flp0 = 0xffffffffu;  // no input flags: every vertex's flags are written
+            // the valid bytes of the thread's vertices first: masked vertices
+            // (sky, escaped paths) read nothing more
+            uint32_t live = 0;
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; ++u) {
+                const uint32_t i = c0 + u * kT + threadIdx.x;
+                const bool v = i < i1 && (fk.valid == nullptr || fk.valid[i] != 0);
+                live |= (v ? 1u : 0u) << u;
+            }
 #pragma unroll 1
             for (uint32_t u = 0; u < kPer; ++u) {
                 const uint32_t i = c0 + u * kT + threadIdx.x;
                 uint32_t f = PF_V_INVALID;
                 uint64_t k = 0;
                 int64_t q0 = 0, q1 = 0, q2 = 0;
-                if (i < i1) {
+                if ((live >> u) & 1u) {
                     const float cr = r[i], cg = g[i], cb = b[i];
                     f = fused_key(fk, i, k);
-                    if (fk.key_out) fk.key_out[i] = k;
                     if (f == 0) f = fixed_point(cr, cg, cb, t.frac_bits, q0, q1, q2);
                 }
+                if (fk.key_out && i < i1) fk.key_out[i] = k;
                 flp |= f << (8 * u);
                 const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
                 ep |= (uint64_t)(uint16_t)e << (16 * u);

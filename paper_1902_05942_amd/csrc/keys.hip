@@ -1,5 +1,6 @@
 // Key construction (Algorithm 1) for gfx950: one vertex per lane, coalesced
-// structure-of-arrays streams in, 8-byte keys and 1-byte flags out.
+// structure-of-arrays streams in (positions and normals of valid vertices
+// only), 8-byte keys and 1-byte flags out.
 #include "pf_kernels.h"
 #include "pf_ops.h"
 
@@ -12,12 +13,14 @@ __global__ __launch_bounds__(kBlock) void build_keys_kernel(
     uint32_t *__restrict__ fp_out, uint32_t *__restrict__ home_out, uint8_t *__restrict__ flags_out) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const float x[3] = {px[i], py[i], pz[i]};
-    const float nr[3] = {nx[i], ny[i], nz[i]};
-    uint64_t key;
-    uint32_t fp, home;
-    const uint8_t flags = vertex_key(x, nr, valid == nullptr || valid[i] != 0, a.cam, a.s, a.seed, a.idx_base + i,
-                                     a.mask, key, fp, home);
+    uint64_t key = 0;
+    uint32_t fp = 0, home = 0;
+    uint8_t flags = PF_V_INVALID;
+    if (valid == nullptr || valid[i] != 0) {  // masked vertices read nothing more
+        const float x[3] = {px[i], py[i], pz[i]};
+        const float nr[3] = {nx[i], ny[i], nz[i]};
+        flags = vertex_key(x, nr, true, a.cam, a.s, a.seed, a.idx_base + i, a.mask, key, fp, home);
+    }
     key_out[i] = key;
     flags_out[i] = flags;
     if (fp_out) fp_out[i] = fp;

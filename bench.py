@@ -362,6 +362,7 @@ def main_multiview(a):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert mvf.status() == 0
+    phases = [round(x, 1) for x in mvf.phase_us()]
     launch_us = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)])) * 1e3
     valid_total = sum(n_valid[(a.warmup + k) % nfr] for k in range(a.steps))
     n_total = sum(s for s, _ in shapes)
@@ -385,6 +386,8 @@ def main_multiview(a):
                    sum(1 << l for _, l in shapes), "block": block, "agg_width": agg, "frames": nfr,
                    "parallelism": "single-gpu"},
         "launch_us": round(launch_us, 2),
+        "phase_us_last_launch": {"clear": phases[0], "keys_insert": phases[1], "temporal": phases[2],
+                                 "lookup": phases[3]},
         "autotune_ms": {f"{b}/{g}": round(v, 4) for (b, g), v in sorted(table.items())},
         "roofline": {"bound": "hbm", "kernel": "views_kernel", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

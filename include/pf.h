@@ -417,8 +417,12 @@ size_t pf_views_workspace_bytes(uint32_t nviews);
 
 /* Filters nviews views in ONE persistent launch (a cooperative grid of
  * resident workgroups of `block` threads): per view it clears `cur`, builds
- * the keys and inserts every vertex (as pf_build_keys + pf_insert_accumulate
- * with aggregation width agg_width), computes the temporal values when
+ * the keys and inserts every vertex (as pf_build_keys + pf_insert_accumulate;
+ * agg_width 0: one claim and one set of device atomics per vertex; nonzero:
+ * each workgroup merges sub-chunks of 2 x block consecutive vertices by key
+ * in LDS -- runs of equal keys across a wavefront first -- and each group
+ * claims its cell once and adds its count and sums with one set of device
+ * atomics), computes the temporal values when
  * temporal is set (as pf_temporal_update, mode 0), and looks up every vertex
  * (as pf_query_average with the slots).  Phases are separated by grid-wide
  * barriers; the work items of all views are spread over all workgroups.
@@ -431,7 +435,10 @@ size_t pf_views_workspace_bytes(uint32_t nviews);
  * aligned; its first uint32 is a status word, non-zero if a barrier wait
  * ever exceeded its bound (every workgroup then stops; with a cooperative
  * launch all workgroups are resident, so it stays 0); the next words hold
- * the grid size and, after a timed-out wait, the arrivals that were seen.
+ * the grid size and, after a timed-out wait, the arrivals that were seen;
+ * words 4..13 hold five 64-bit wall-clock readings of workgroup 0 (start,
+ * end of clear, of keys + insert, of temporal values, of its own lookup),
+ * in ticks of pf_wall_clock_hz().
  * Errors: PF_EINVAL (NULL, misaligned, inconsistent descriptor, a
  * PF_SUMS_FLOAT32 table), PF_ERANGE (nviews 0 or above PF_MAX_VIEWS,
  * block, agg_width, parameters), PF_ELAUNCH. */
@@ -468,6 +475,10 @@ pf_status pf_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uin
  * copies the PF_STATS_LEN counters to host memory and waits for the copy.
  * The only call that blocks the host. */
 pf_status pf_read_stats(const pf_table *t, uint64_t *host_out, void *stream);
+
+/* [host] Frequency of the current device's wall clock (the stamps of
+ * pf_filter_views), in Hz; 0 if it cannot be queried. */
+uint64_t pf_wall_clock_hz(void);
 
 /* Library version string [host]. */
 const char *pf_version(void);

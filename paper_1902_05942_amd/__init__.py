@@ -200,6 +200,14 @@ class MultiViewFilter:
     def status(self) -> int:
         return int(self.ws[:4].view(torch.int32).cpu()[0])
 
+    def phase_us(self):
+        """Microseconds of the last launch's phases as seen by workgroup 0:
+        clear, keys + insert, temporal values, lookup."""
+        w = self.ws[:64].view(torch.int32).cpu().numpy().view("uint32").astype("uint64")
+        t = [int(w[4 + 2 * k]) | (int(w[5 + 2 * k]) << 32) for k in range(5)]
+        hz = int(_lib.lib.pf_wall_clock_hz()) or 100_000_000
+        return [(t[k + 1] - t[k]) * 1e6 / hz for k in range(4)]
+
     def status_words(self):
         """status, grid size, arrivals seen by a timed-out wait, its barrier number."""
         return [int(x) for x in self.ws[:16].view(torch.int32).cpu()]

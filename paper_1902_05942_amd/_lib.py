@@ -101,6 +101,7 @@ def _load():
         "pf_mlp_features": ([ctypes.POINTER(pf_geometry), vp, u64, vp, vp], i),
         "pf_mlp_infer": ([ctypes.POINTER(pf_mlp), ctypes.POINTER(pf_geometry), vp, vp, u64, vp, vp, vp, vp], i),
         "pf_microbench": ([i, vp, u64, u32, u32, u64, vp, vp], i),
+        "pf_wall_clock_hz": ([], u64),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -116,7 +117,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
-            "pf_temporal_integrate", "pf_build_keys_insert_binned")
+            "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz")
 
 
 def _ptr(t):

@@ -14,7 +14,7 @@ import os
 import torch
 
 BLOCKS = (64, 128, 256, 512, 1024)
-AGGS = (0, 4, 16, 64, 256)
+AGGS = (0, 1)  # 0: device atomics per vertex; nonzero: vertices merged by key in LDS first
 
 
 def cache_path() -> str:

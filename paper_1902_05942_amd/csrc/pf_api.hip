@@ -54,6 +54,13 @@ extern "C" {
 
 const char *pf_version(void) { return "pf-gfx950 1.0"; }
 
+uint64_t pf_wall_clock_hz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) return 0;
+    return (uint64_t)khz * 1000ull;
+}
+
 size_t pf_table_bytes(uint32_t log2_slots, int with_blend) {
     if (log2_slots < 4 || log2_slots > 30) return 0;
     const size_t S = (size_t)1 << log2_slots;

@@ -217,31 +217,122 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
     __syncthreads();  // the scratch may be reused right after
 }
 
-// Temporal value of one occupied cell: the current average blended with the
-// previous frame's value when the key is found there.  Returns whether it
-// was found.
-template <bool kHasPrev>
-__device__ __forceinline__ bool temporal_cell(const Tab &cur, const Tab &prev, uint32_t s, float alpha, float beta) {
-    const pf_cell c = cur.cell[s];
-    float v0 = cur.average(c, 0);
-    float v1 = cur.average(c, 1);
-    float v2 = cur.average(c, 2);
-    bool hit = false;
-    if constexpr (kHasPrev) {
-        const uint64_t key = cur.key[s];
-        const uint32_t p = find_exact(prev, key, c.fp);
-        if (p != kNoSlot) {
-            const float4 old = prev.blend[p];
-            const float a0 = alpha * old.x, a1 = alpha * old.y, a2 = alpha * old.z;
-            const float b0 = beta * v0, b1 = beta * v1, b2 = beta * v2;
-            v0 = a0 + b0;
-            v1 = a1 + b1;
-            v2 = a2 + b2;
-            hit = true;
+// Temporal values of the occupied cells recorded in occupancy word j of
+// `cur` (Section 3.4.1); returns how many found their key in `prev`.  The
+// word's cells are taken kTB at a time, and each step of their lookups in
+// the previous table (cell and key, fingerprint probe, key check, old value)
+// is issued for all of them before any result is used.  kIntegrate: temporal
+// integration, alpha = N_old / (N_old + N_new) per cell with the stored count
+// kept at most `cap`; else the moving average with a fixed alpha (the stored
+// count is this frame's).
+template <bool kHasPrev, bool kIntegrate, int kTB = 4>  // kTB: cells of one lane looked up together
+__device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &prev, uint32_t j, float alpha,
+                                                  float beta, uint32_t cap) {
+    const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
+    uint32_t hits = 0;
+    uint32_t w = cur.occ[j];
+    while (w) {
+        uint32_t s[kTB];
+        bool has[kTB];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            has[k] = w != 0;
+            s[k] = has[k] ? j * 32 + __builtin_ctz(w) : 0u;
+            w &= w - 1;
         }
+        uint4 lo[kTB], hi[kTB];
+        uint64_t key[kTB];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            if (has[k]) {
+                lo[k] = cells[2 * s[k]];
+                hi[k] = cells[2 * s[k] + 1];
+                if constexpr (kHasPrev) key[k] = cur.key[s[k]];
+            }
+        }
+        float v[kTB][3];
+        uint32_t cnt[kTB], keep[kTB];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            if (!has[k]) continue;
+            pf_cell c;
+            c.fp = lo[k].x;
+            c.count = lo[k].y;
+            c.sum[0] = (int64_t)((uint64_t)lo[k].z | (uint64_t)lo[k].w << 32);
+            c.sum[1] = (int64_t)((uint64_t)hi[k].x | (uint64_t)hi[k].y << 32);
+            c.sum[2] = (int64_t)((uint64_t)hi[k].z | (uint64_t)hi[k].w << 32);
+            cnt[k] = c.count;
+            keep[k] = kIntegrate ? min(c.count, cap) : c.count;
+            v[k][0] = cur.average(c, 0);
+            v[k][1] = cur.average(c, 1);
+            v[k][2] = cur.average(c, 2);
+        }
+        if constexpr (kHasPrev) {
+            // search each key in prev: fingerprint probe confirmed by the stored key
+            uint32_t p[kTB];
+            bool active[kTB], found[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                active[k] = has[k];
+                found[k] = false;
+                p[k] = has[k] ? home_of(key[k], prev.mask) : 0u;
+            }
+            for (uint32_t d = 0; d < prev.max_probe; ++d) {
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) any |= active[k];
+                if (!any) break;
+                uint32_t pf[kTB];
+                uint64_t pk[kTB];
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell[p[k]].fp : 0u;
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) {
+                    pk[k] = 0;
+                    if (active[k] && pf[k] == lo[k].x) pk[k] = prev.key[p[k]];
+                }
+#pragma unroll
+                for (int k = 0; k < kTB; ++k) {
+                    if (!active[k]) continue;
+                    if (pf[k] == 0) {
+                        active[k] = false;  // empty slot: not in prev
+                    } else if (pf[k] == lo[k].x && pk[k] == key[k]) {
+                        active[k] = false;
+                        found[k] = true;
+                    } else {
+                        p[k] = (p[k] + 1) & prev.mask;
+                    }
+                }
+            }
+            float4 old[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k)
+                if (found[k]) old[k] = prev.blend[p[k]];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                if (!found[k]) continue;
+                float al = alpha, be = beta;
+                if constexpr (kIntegrate) {
+                    // counts are exact integers in binary32 (at most 2^24)
+                    const float nsum = old[k].w + (float)cnt[k];
+                    al = old[k].w / nsum;
+                    be = 1.0f - al;
+                    const uint32_t n = (uint32_t)nsum;
+                    keep[k] = n < cap ? n : cap;
+                }
+                const float a0 = al * old[k].x, a1 = al * old[k].y, a2 = al * old[k].z;
+                const float b0 = be * v[k][0], b1 = be * v[k][1], b2 = be * v[k][2];
+                v[k][0] = a0 + b0;
+                v[k][1] = a1 + b1;
+                v[k][2] = a2 + b2;
+                ++hits;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTB; ++k)
+            if (has[k]) cur.blend[s[k]] = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
     }
-    cur.blend[s] = make_float4(v0, v1, v2, (float)c.count);
-    return hit;
+    return hits;
 }
 
 // Lookup for one vertex: writes its filtered contribution (or its own when

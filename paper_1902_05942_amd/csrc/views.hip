@@ -6,6 +6,7 @@
 // The per-vertex and per-cell arithmetic is that of the single-view kernels
 // (pf_ops.h).
 #include "pf_kernels.h"
+#include "pf_merge.h"
 #include "pf_ops.h"
 
 namespace pfk {
@@ -106,9 +107,16 @@ __device__ bool grid_barrier(const Barrier &bar, uint32_t epoch) {
     return s_ok != 0;
 }
 
+// LDS merge table of the insert phase: a sub-chunk of 2B vertices merges into
+// at most 2B entries (1536 for B = 1024, keeping the table in static LDS).
+template <int B>
+constexpr uint32_t kMergeCap = 2 * B < 1536 ? 2 * B : 1536;
+
 template <int B>
 struct Lds {
-    AggLds<B> agg;
+    unsigned long long mkey[kMergeCap<B>];
+    unsigned long long ms0[kMergeCap<B>], ms1[kMergeCap<B>], ms2[kMergeCap<B>];
+    uint32_t mcnt[kMergeCap<B>];           // count, then the group's slot
     uint32_t first[4][PF_MAX_VIEWS + 1];  // per phase: first global item of each view
     uint32_t hits;
 };
@@ -121,21 +129,37 @@ __device__ __forceinline__ void item_of(const Lds<B> &L, int phase, uint32_t nvi
     local = it - L.first[phase][v];
 }
 
+// Key, flags and fixed-point contribution of vertex i of a view (masked
+// vertices read nothing more than their valid byte).
+__device__ __forceinline__ uint8_t view_vertex(const pf_view &d, const Tab &t, uint32_t i, uint64_t &key,
+                                               int64_t &q0, int64_t &q1, int64_t &q2) {
+    key = 0;
+    q0 = q1 = q2 = 0;
+    if (d.valid != nullptr && d.valid[i] == 0) return PF_V_INVALID;
+    const float x[3] = {d.px[i], d.py[i], d.pz[i]};
+    const float nr[3] = {d.nx[i], d.ny[i], d.nz[i]};
+    uint32_t fp, home;
+    uint8_t fl = vertex_key(x, nr, true, d.kp.cam, d.kp.s, d.kp.seed, d.kp.idx_base + i, t.mask, key, fp, home);
+    if (fl == 0) fl = fixed_point(d.r[i], d.g[i], d.b[i], t.frac_bits, q0, q1, q2);
+    return fl;
+}
+
 template <int B>
 __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ views, uint32_t nviews, uint32_t agg,
                                                   Barrier bar) {
     __shared__ Lds<B> L;
     constexpr uint32_t kItem = (uint32_t)B * kIters;
-    // work items per view and phase: 0 clear (bitmap words), 1 keys + insert
-    // (vertices), 2 temporal (slots), 3 lookup (vertices)
+    // work items per view and phase: 0 clear (B bitmap words), 1 keys +
+    // insert (8 x B vertices), 2 temporal (B bitmap words), 3 lookup (8 x B
+    // vertices)
     if (threadIdx.x == 0) {
         uint32_t acc[4] = {0, 0, 0, 0};
         for (uint32_t v = 0; v < nviews; ++v) {
             const pf_view &d = views[v];
             const uint32_t slots = 1u << d.cur.log2_slots;
             const uint32_t words = (slots + 31) / 32;
-            const uint32_t items[4] = {(words + kItem - 1) / kItem, (d.n + kItem - 1) / kItem,
-                                       d.temporal ? (slots + kItem - 1) / kItem : 0u, (d.n + kItem - 1) / kItem};
+            const uint32_t items[4] = {(words + B - 1) / B, (d.n + kItem - 1) / kItem,
+                                       d.temporal ? (words + B - 1) / B : 0u, (d.n + kItem - 1) / kItem};
             for (int p = 0; p < 4; ++p) {
                 L.first[p][v] = acc[p];
                 acc[p] += items[p];
@@ -143,7 +167,17 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
         }
         for (int p = 0; p < 4; ++p) L.first[p][nviews] = acc[p];
     }
+    // block 0 stamps the start and the end of every phase (wall clock, as
+    // 64-bit values in status words 4..13) for the caller's diagnostics
+    auto stamp = [&](int k) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const uint64_t w = wall_clock64();
+            bar.status[4 + 2 * k] = (uint32_t)w;
+            bar.status[5 + 2 * k] = (uint32_t)(w >> 32);
+        }
+    };
     if (blockIdx.x == 0 && threadIdx.x == 0) bar.status[1] = gridDim.x;
+    stamp(0);
     __syncthreads();
     const uint32_t G = gridDim.x;
 
@@ -152,13 +186,10 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
         uint32_t v, local;
         item_of(L, 0, nviews, it, v, local);
         const Tab t = to_tab(views[v].cur);
-        const uint32_t nwords = t.nwords();
-        for (int k = 0; k < kIters; ++k) {
-            const uint32_t j = local * kItem + k * B + threadIdx.x;
-            if (j >= nwords) break;
+        const uint32_t j = local * B + threadIdx.x;  // one bitmap word per lane
+        if (j < t.nwords()) {
             uint32_t w = t.occ[j];
-            if (w == 0) continue;
-            t.occ[j] = 0;
+            if (w) t.occ[j] = 0;
             while (w) {
                 const uint32_t b = __builtin_ctz(w);
                 w &= w - 1;
@@ -171,45 +202,106 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
             for (uint32_t k = threadIdx.x; k < PF_STATS_LEN; k += B) t.stats[k] = 0;
     }
     if (!grid_barrier(bar, 1)) return;
+    stamp(1);
 
-    // ---- phase 1: keys and insertion
+    // ---- phase 1: keys and insertion.  agg == 0: one claim and one set of
+    // device atomics per vertex.  Otherwise each sub-chunk of 2B vertices
+    // merges by key in LDS (runs across lanes first), then every group claims
+    // its cell once and adds its count and sums with one set of atomics.
+    constexpr uint32_t kCap = kMergeCap<B>;
     for (uint32_t it = blockIdx.x; it < L.first[1][nviews]; it += G) {
         uint32_t v, local;
         item_of(L, 1, nviews, it, v, local);
         const pf_view &d = views[v];
         const Tab t = to_tab(d.cur);
-        for (int k = 0; k < kIters; ++k) {
-            const uint32_t i = local * kItem + k * B + threadIdx.x;
-            const bool in = i < d.n;
-            uint32_t slot = kNoSlot;
-            int64_t q0 = 0, q1 = 0, q2 = 0;
-            if (in) {
-                const float x[3] = {d.px[i], d.py[i], d.pz[i]};
-                const float nr[3] = {d.nx[i], d.ny[i], d.nz[i]};
+        if (agg == 0) {
+            for (int k = 0; k < kIters; ++k) {
+                const uint32_t i = local * kItem + k * B + threadIdx.x;
+                if (i >= d.n) break;
                 uint64_t key;
-                uint32_t fp, home;
-                uint8_t fl = vertex_key(x, nr, d.valid == nullptr || d.valid[i] != 0, d.kp.cam, d.kp.s, d.kp.seed,
-                                        d.kp.idx_base + i, t.mask, key, fp, home);
-                if (fl == 0) fl = fixed_point(d.r[i], d.g[i], d.b[i], t.frac_bits, q0, q1, q2);
+                int64_t q0 = 0, q1 = 0, q2 = 0;
+                uint32_t slot = kNoSlot;
+                uint8_t fl = view_vertex(d, t, i, key, q0, q1, q2);
                 if (fl == 0) {
                     slot = find_or_claim(t, key);
                     if (slot == kNoSlot) {
                         fl = PF_V_OVERFLOW;
                         add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], 1ull);
+                    } else {
+                        accumulate(t, slot, 1, q0, q1, q2);
                     }
                 }
                 d.key[i] = key;
                 d.vflags[i] = fl;
                 d.slot[i] = slot;
             }
-            if (k * B + local * kItem >= d.n) {
-                // whole step beyond the view: uniform across the workgroup
-                break;
+            continue;
+        }
+        for (int sub = 0; sub < kIters / 2; ++sub) {
+            const uint32_t base = local * kItem + sub * 2 * B;
+            if (base >= d.n) break;  // uniform across the workgroup
+            for (uint32_t j = threadIdx.x; j < kCap; j += B) {
+                L.mkey[j] = kEmpty;
+                L.ms0[j] = 0;
+                L.ms1[j] = 0;
+                L.ms2[j] = 0;
+                L.mcnt[j] = 0;
             }
-            accumulate_group<B>(t, L.agg, agg, slot, q0, q1, q2);
+            __syncthreads();
+            uint64_t kv[2];
+            int64_t qv[2][3];
+            uint8_t fv[2];
+            int ev[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t i = base + u * B + threadIdx.x;
+                kv[u] = 0;
+                qv[u][0] = qv[u][1] = qv[u][2] = 0;
+                fv[u] = PF_V_INVALID;
+                if (i < d.n) fv[u] = view_vertex(d, t, i, kv[u], qv[u][0], qv[u][1], qv[u][2]);
+                ev[u] = merge_into_lds(L.mkey, L.ms0, L.ms1, L.ms2, L.mcnt, kCap, fv[u] == 0, kv[u], qv[u][0],
+                                       qv[u][1], qv[u][2]);
+            }
+            __syncthreads();
+            for (uint32_t j = threadIdx.x; j < kCap; j += B) {
+                const unsigned long long kk = L.mkey[j];
+                if (kk == kEmpty) continue;
+                const uint32_t c = L.mcnt[j];
+                const uint32_t slot = find_or_claim(t, kk);
+                if (slot != kNoSlot)
+                    accumulate(t, slot, c, (int64_t)L.ms0[j], (int64_t)L.ms1[j], (int64_t)L.ms2[j]);
+                else
+                    add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], (unsigned long long)c);
+                L.mcnt[j] = slot;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t i = base + u * B + threadIdx.x;
+                if (i >= d.n) continue;
+                uint8_t fl = fv[u];
+                uint32_t slot = kNoSlot;
+                if (fl == 0) {
+                    if (ev[u] >= 0) {
+                        slot = L.mcnt[ev[u]];
+                    } else {  // no room in the LDS table: on its own
+                        slot = find_or_claim(t, kv[u]);
+                        if (slot != kNoSlot)
+                            accumulate(t, slot, 1, qv[u][0], qv[u][1], qv[u][2]);
+                        else
+                            add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], 1ull);
+                    }
+                    if (slot == kNoSlot) fl = PF_V_OVERFLOW;
+                }
+                d.key[i] = kv[u];
+                d.vflags[i] = fl;
+                d.slot[i] = slot;
+            }
+            __syncthreads();  // the table is cleared for the next sub-chunk
         }
     }
     if (!grid_barrier(bar, 2)) return;
+    stamp(2);
 
     // ---- phase 2: temporal values
     for (uint32_t it = blockIdx.x; it < L.first[2][nviews]; it += G) {
@@ -220,16 +312,15 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
         const bool has_prev = d.prev.cell != nullptr;
         const Tab prev = has_prev ? to_tab(d.prev) : cur;
         const float alpha = d.alpha_old, beta = 1.0f - d.alpha_old;
-        const uint32_t nslots = cur.mask + 1;
+        // an item is one word per lane: a word holds 32 slots, so finer items
+        // than the other phases' keep every workgroup busy
+        const uint32_t j = local * B + threadIdx.x;
         uint32_t hits = 0;
-        for (int k = 0; k < kIters; ++k) {
-            const uint32_t s = local * kItem + k * B + threadIdx.x;
-            if (s >= nslots) break;
-            if (((cur.occ[s >> 5] >> (s & 31)) & 1u) == 0) continue;
+        if (j < cur.nwords()) {
             if (has_prev)
-                hits += temporal_cell<true>(cur, prev, s, alpha, beta) ? 1u : 0u;
+                hits = temporal_word<true, false, 2>(cur, prev, j, alpha, beta, 0u);
             else
-                temporal_cell<false>(cur, prev, s, alpha, beta);
+                temporal_word<false, false, 2>(cur, prev, j, alpha, beta, 0u);
         }
         if (has_prev) {
             if (threadIdx.x == 0) L.hits = 0;
@@ -241,6 +332,7 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
         }
     }
     if (!grid_barrier(bar, 3)) return;
+    stamp(3);
 
     // ---- phase 3: lookup
     for (uint32_t it = blockIdx.x; it < L.first[3][nviews]; it += G) {
@@ -258,6 +350,8 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
                 query_vertex<false>(t, slot, i, d.r, d.g, d.b, d.r_out, d.g_out, d.b_out, d.count_out, false);
         }
     }
+    // the lookup has no barrier after it: block 0 stamps its own end
+    stamp(4);
 }
 
 __global__ void views_reset_kernel(uint32_t *ws, uint32_t words) {

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "pf.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:pf_status|size_t|const char \*)\s*(pf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:pf_status|size_t|uint64_t|const char \*)\s*(pf_\w+)\s*\(", src, re.M)))
 
 
 @pytest.fixture(scope="module")

@@ -27,7 +27,7 @@ def _views(frame):
     return wl, out
 
 
-@pytest.mark.parametrize("block,agg", [(64, 0), (256, 64), (1024, 256), (512, 4), (128, 128)])
+@pytest.mark.parametrize("block,agg", [(64, 0), (256, 1), (1024, 1), (512, 0), (128, 1)])
 def test_views_bit_exact_over_frames(gpu, block, agg):
     mvf = pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=True, alpha_old=0.2)
     states = [None] * len(SHAPES)

@@ -335,6 +335,17 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
     return hits;
 }
 
+// The value a vertex's lookup returns: its cell's temporal value (blend)
+// or average, with the count in w, or its own contribution when it has no
+// slot (then w is 0).
+__device__ __forceinline__ float4 lookup_value(const Tab &t, uint32_t slot, uint32_t i, const float *r, const float *g,
+                                               const float *b, bool blend) {
+    if (slot == kNoSlot) return make_float4(r[i], g[i], b[i], 0.0f);
+    if (blend) return t.blend[slot];
+    const pf_cell c = t.cell[slot];
+    return make_float4(t.average(c, 0), t.average(c, 1), t.average(c, 2), (float)c.count);
+}
+
 // Lookup for one vertex: writes its filtered contribution (or its own when
 // unfiltered) and count.
 template <bool kBlend>

@@ -340,14 +340,32 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
         item_of(L, 3, nviews, it, v, local);
         const pf_view &d = views[v];
         const Tab t = to_tab(d.cur);
-        for (int k = 0; k < kIters; ++k) {
-            const uint32_t i = local * kItem + k * B + threadIdx.x;
-            if (i >= d.n) break;
-            const uint32_t slot = d.vflags[i] == 0 ? d.slot[i] : kNoSlot;
-            if (d.temporal)
-                query_vertex<true>(t, slot, i, d.r, d.g, d.b, d.r_out, d.g_out, d.b_out, d.count_out, false);
-            else
-                query_vertex<false>(t, slot, i, d.r, d.g, d.b, d.r_out, d.g_out, d.b_out, d.count_out, false);
+        // four vertices at a time: their slots (kNoSlot for flagged vertices),
+        // then every value they read, then the stores, so the loads of the
+        // four are in flight together
+        for (int k0 = 0; k0 < kIters; k0 += 4) {
+            uint32_t slot[4];
+            float4 val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = local * kItem + (k0 + u) * B + threadIdx.x;
+                slot[u] = i < d.n ? d.slot[i] : kNoSlot;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = local * kItem + (k0 + u) * B + threadIdx.x;
+                if (i >= d.n) continue;
+                val[u] = lookup_value(t, slot[u], i, d.r, d.g, d.b, d.temporal != 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = local * kItem + (k0 + u) * B + threadIdx.x;
+                if (i >= d.n) continue;
+                d.r_out[i] = val[u].x;
+                d.g_out[i] = val[u].y;
+                d.b_out[i] = val[u].z;
+                if (d.count_out) d.count_out[i] = slot[u] == kNoSlot ? 0u : (uint32_t)val[u].w;
+            }
         }
     }
     // the lookup has no barrier after it: block 0 stamps its own end

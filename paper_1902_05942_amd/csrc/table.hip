@@ -129,8 +129,13 @@ __global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__
                                                        bool inplace) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    uint32_t slot = kNoSlot;
-    if (flags[i] == 0) slot = slot_in ? slot_in[i] : find_slot(t, key[i]);
+    // the flag and the slot are loaded together; the flag decides
+    const uint8_t fl = flags[i];
+    uint32_t slot = slot_in ? slot_in[i] : kNoSlot;
+    if (fl != 0)
+        slot = kNoSlot;
+    else if (!slot_in)
+        slot = find_slot(t, key[i]);
     query_vertex<kBlend>(t, slot, i, r, g, b, ro, go, bo, count_out, inplace);
 }
 

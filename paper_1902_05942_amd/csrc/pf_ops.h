@@ -218,7 +218,8 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 }
 
 // Temporal values of the occupied cells recorded in occupancy word j of
-// `cur` (Section 3.4.1); returns how many found their key in `prev`.  The
+// `cur` (Section 3.4.1), restricted to the bits of `part`; returns how many
+// found their key in `prev`.  The
 // word's cells are taken kTB at a time, and each step of their lookups in
 // the previous table (cell and key, fingerprint probe, key check, old value)
 // is issued for all of them before any result is used.  kIntegrate: temporal
@@ -227,10 +228,10 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 // count is this frame's).
 template <bool kHasPrev, bool kIntegrate, int kTB = 4>  // kTB: cells of one lane looked up together
 __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &prev, uint32_t j, float alpha,
-                                                  float beta, uint32_t cap) {
+                                                  float beta, uint32_t cap, uint32_t part = 0xffffffffu) {
     const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
     uint32_t hits = 0;
-    uint32_t w = cur.occ[j];
+    uint32_t w = cur.occ[j] & part;  // the slots of the word this lane takes
     while (w) {
         uint32_t s[kTB];
         bool has[kTB];

@@ -1,5 +1,5 @@
-// Temporal blend over two sets of averages (Section 3.4.1) for gfx950: one
-// lane per occupancy word of the current table (temporal_word), so the work
+// Temporal blend over two sets of averages (Section 3.4.1) for gfx950: four
+// lanes per occupancy word of the current table (temporal_word), so the work
 // beyond the bitmap read is proportional to the cells of the current frame.
 #include "pf_kernels.h"
 #include "pf_ops.h"
@@ -8,11 +8,13 @@ namespace pfk {
 
 template <bool kHasPrev, bool kIntegrate>
 __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta, uint32_t cap) {
-    const uint32_t nwords = cur.nwords();
+    // four lanes per occupancy word, 8 slots each: enough lanes in flight to
+    // hide the chain of dependent lookups
+    const uint32_t nparts = cur.nwords() * 4;
     const uint32_t stride = gridDim.x * kBlock;
     uint32_t hits = 0;
-    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nwords; j += stride)
-        hits += temporal_word<kHasPrev, kIntegrate>(cur, prev, j, alpha, beta, cap);
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nparts; q += stride)
+        hits += temporal_word<kHasPrev, kIntegrate, 2>(cur, prev, q >> 2, alpha, beta, cap, 0xffu << (8 * (q & 3)));
     if constexpr (kHasPrev) {
         // one device atomic per block, spread over 32 partial counters
         __shared__ uint32_t s_hits;
@@ -27,8 +29,8 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
 hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, uint32_t cap,
                            hipStream_t st) {
     const float beta = 1.0f - alpha_old;
-    uint32_t blocks = (cur.nwords() + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
+    uint32_t blocks = (cur.nwords() * 4 + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
     if (mode == 1) {
         if (prev)
             temporal_kernel<true, true><<<blocks, kBlock, 0, st>>>(cur, *prev, 0.0f, 0.0f, cap);

@@ -95,12 +95,12 @@ Plan make_plan(uint32_t n, uint32_t log2_slots) {
 }
 
 // Probe / claim like find_or_claim, without the occupancy bit (set by the
-// reduce pass, which owns the bitmap words of its bin), continuing from slot
-// s whose fingerprint word was already read as cur.
-__device__ __forceinline__ uint32_t claim_from(const Tab &t, uint64_t key, uint32_t f, uint32_t s, uint32_t cur) {
-    for (uint32_t d = 0; d < t.max_probe; ++d) {
+// reduce pass, which owns the bitmap words of its bin), from probe d0 at
+// slot s onwards.
+__device__ __forceinline__ uint32_t claim_next(const Tab &t, uint64_t key, uint32_t f, uint32_t s, uint32_t d0) {
+    for (uint32_t d = d0; d < t.max_probe; ++d) {
         uint32_t *pfp = &t.cell[s].fp;
-        if (d) cur = load_fp_probe(pfp);
+        uint32_t cur = load_fp_probe(pfp);
         if (cur == 0) {
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -117,8 +117,7 @@ __device__ __forceinline__ uint32_t claim_from(const Tab &t, uint64_t key, uint3
 }
 
 __device__ __forceinline__ uint32_t claim(const Tab &t, uint64_t key) {
-    const uint32_t s = home_of(key, t.mask);
-    return claim_from(t, key, fingerprint_of(key), s, load_fp_probe(&t.cell[s].fp));
+    return claim_next(t, key, fingerprint_of(key), home_of(key, t.mask), 0);
 }
 
 __device__ __forceinline__ void store_rec(Rec *p, uint32_t slot, uint32_t count, uint64_t s0, uint64_t s1,
@@ -238,19 +237,33 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         }
         __syncthreads();
-        // one probe / claim and one staged record per group; the first probes
-        // of a thread's entries are issued before either is resolved
+        // one probe / claim and one staged record per group; a thread's
+        // entries issue their home-slot loads, then their compare-and-swaps
+        // on empty home slots, before either result is needed
         uint64_t gk[kFlush];
-        uint32_t fs[kFlush], fcur[kFlush];
+        uint32_t fs[kFlush], ff[kFlush], fcur[kFlush];
 #pragma unroll
         for (uint32_t v = 0; v < kFlush; ++v) {
             const uint32_t j = v * kT + threadIdx.x;
             gk[v] = j < cap ? lkey[j] : kEmpty;
             fs[v] = 0;
+            ff[v] = 0;
             fcur[v] = 0;
             if (gk[v] != kEmpty) {
                 fs[v] = home_of(gk[v], t.mask);
+                ff[v] = fingerprint_of(gk[v]);
                 fcur[v] = load_fp_probe(&t.cell[fs[v]].fp);
+            }
+        }
+        bool won[kFlush];
+#pragma unroll
+        for (uint32_t v = 0; v < kFlush; ++v) {
+            won[v] = false;
+            if (gk[v] != kEmpty && fcur[v] == 0) {
+                uint32_t expected = 0;
+                won[v] = __hip_atomic_compare_exchange_strong(&t.cell[fs[v]].fp, &expected, ff[v], __ATOMIC_RELAXED,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fcur[v] = won[v] ? ff[v] : expected;
             }
         }
 #pragma unroll
@@ -258,7 +271,9 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             const uint32_t j = v * kT + threadIdx.x;
             uint32_t s = kNoSlot;
             if (gk[v] != kEmpty) {
-                s = claim_from(t, gk[v], fingerprint_of(gk[v]), fs[v], fcur[v]);
+                if (won[v]) t.key[fs[v]] = gk[v];
+                // the home slot holds another key: probe on from the next
+                s = fcur[v] == ff[v] ? fs[v] : claim_next(t, gk[v], ff[v], (fs[v] + 1) & t.mask, 1);
                 if (s == kNoSlot) atomicAdd(&misc[1], lcnt[j]);
             }
             const bool stage = gk[v] != kEmpty && s != kNoSlot;

@@ -46,20 +46,25 @@ __device__ __forceinline__ int lds_insert(unsigned long long *lkey, uint32_t cap
 // masked off, read 0.
 template <int kCtrl, int kRowMask = 0xf>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, kRowMask == 0xf);
 }
 template <int kCtrl, int kRowMask = 0xf>
 __device__ __forceinline__ uint64_t dpp(uint64_t v) {
     return (uint64_t)dpp<kCtrl, kRowMask>((uint32_t)v) | (uint64_t)dpp<kCtrl, kRowMask>((uint32_t)(v >> 32)) << 32;
 }
+// a += the DPP source lane's a, as two 32-bit adds chained by the carry
 template <int kCtrl, int kRowMask = 0xf>
-__device__ __forceinline__ void dpp_add(uint32_t &c, uint64_t &a0, uint64_t &a1, uint64_t &a2) {
-    const uint32_t dc = dpp<kCtrl, kRowMask>(c);
-    const uint64_t d0 = dpp<kCtrl, kRowMask>(a0), d1 = dpp<kCtrl, kRowMask>(a1), d2 = dpp<kCtrl, kRowMask>(a2);
-    c += dc;
-    a0 += d0;
-    a1 += d1;
-    a2 += d2;
+__device__ __forceinline__ void dpp_add(uint64_t &a) {
+    const uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
+    const uint32_t nlo = lo + dpp<kCtrl, kRowMask>(lo);
+    const uint32_t nhi = hi + dpp<kCtrl, kRowMask>(hi) + (nlo < lo ? 1u : 0u);
+    a = (uint64_t)nlo | (uint64_t)nhi << 32;
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ void dpp_add(uint64_t &a0, uint64_t &a1, uint64_t &a2) {
+    dpp_add<kCtrl, kRowMask>(a0);
+    dpp_add<kCtrl, kRowMask>(a1);
+    dpp_add<kCtrl, kRowMask>(a2);
 }
 
 // Adds one vertex per lane (lanes with ok) to the chunk's LDS table and
@@ -85,20 +90,19 @@ __device__ __forceinline__ int merge_into_lds(unsigned long long *lkey, unsigned
     uint64_t a0 = (uint64_t)q0, a1 = (uint64_t)q1, a2 = (uint64_t)q2;
     if (__ballot(ok && !head)) {  // some run spans several lanes
         const uint32_t first = 63u - (uint32_t)__builtin_clzll(heads & upto);
-        uint32_t pc = cnt;
         uint64_t p0 = a0, p1 = a1, p2 = a2;
-        dpp_add<0x111>(pc, p0, p1, p2);  // row_shr:1
-        dpp_add<0x112>(pc, p0, p1, p2);  // row_shr:2
-        dpp_add<0x114>(pc, p0, p1, p2);  // row_shr:4
-        dpp_add<0x118>(pc, p0, p1, p2);  // row_shr:8
-        dpp_add<0x142, 0xa>(pc, p0, p1, p2);  // row_bcast:15 into rows 1 and 3
-        dpp_add<0x143, 0xc>(pc, p0, p1, p2);  // row_bcast:31 into rows 2 and 3
-        // exclusive prefix at the run's first lane
-        const uint32_t ec = __shfl(pc - cnt, (int)first);
+        dpp_add<0x111>(p0, p1, p2);  // row_shr:1
+        dpp_add<0x112>(p0, p1, p2);  // row_shr:2
+        dpp_add<0x114>(p0, p1, p2);  // row_shr:4
+        dpp_add<0x118>(p0, p1, p2);  // row_shr:8
+        dpp_add<0x142, 0xa>(p0, p1, p2);  // row_bcast:15 into rows 1 and 3
+        dpp_add<0x143, 0xc>(p0, p1, p2);  // row_bcast:31 into rows 2 and 3
+        // exclusive prefix at the run's first lane; a run of valid lanes
+        // holds only valid lanes (invalid ones carry kEmpty)
         const uint64_t e0 = __shfl((unsigned long long)(p0 - a0), (int)first);
         const uint64_t e1 = __shfl((unsigned long long)(p1 - a1), (int)first);
         const uint64_t e2 = __shfl((unsigned long long)(p2 - a2), (int)first);
-        cnt = pc - ec;
+        cnt = ok ? tail - first + 1 : 0u;
         a0 = p0 - e0;
         a1 = p1 - e1;
         a2 = p2 - e2;

@@ -35,7 +35,7 @@ constexpr uint32_t kMaxTiles = 512;          // two workgroups on each of 256 CU
 constexpr uint32_t kLdsBudget = 80 * 1024;   // two 1024-thread workgroups per CU
 constexpr uint32_t kFlush = 2;               // LDS entries per thread (entries <= kFlush * kT)
 constexpr uint32_t kMaxLog2Slots = 25;
-constexpr int kReduceThreads = 512;
+constexpr int kReduceThreads = 1024;  // the bin's LDS sums allow two workgroups per CU
 
 // One staged group: the cell layout with the slot in place of the fingerprint.
 struct __align__(16) Rec {
@@ -503,14 +503,15 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
                 cells[2 * k] = make_uint4(lo[u].x, lo[u].y + c[u], (uint32_t)s0, (uint32_t)(s0 >> 32));
                 cells[2 * k + 1] = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
             }
+            // occupancy: a wavefront's 64 consecutive slots are two bitmap
+            // words of this bin (bins hold >= 32 slots, or the whole table)
+            const uint64_t m = __ballot(c[u] != 0);
+            if ((threadIdx.x & 63) == 0 && m) {
+                const uint32_t w = (base + k) >> 5;
+                if ((uint32_t)m) t.occ[w] |= (uint32_t)m;
+                if (m >> 32) t.occ[w + 1] |= (uint32_t)(m >> 32);
+            }
         }
-    }
-    // occupancy words of this bin (bins hold >= 32 slots, or the whole table)
-    const uint32_t words = (bin_slots + 31) / 32;
-    for (uint32_t w = threadIdx.x; w < words; w += kReduceThreads) {
-        uint32_t bits = 0;
-        for (uint32_t k = 0; k < 32 && w * 32 + k < bin_slots; ++k) bits |= (cnt[w * 32 + k] != 0 ? 1u : 0u) << k;
-        if (bits) t.occ[(base >> 5) + w] |= bits;
     }
 }
 

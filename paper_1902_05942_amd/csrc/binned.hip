@@ -6,9 +6,11 @@
 // sends one per group of vertices that share a key within a chunk of 4096
 // consecutive vertices, and no atomic at all for the sums:
 //   aggregate  per tile (every ntiles-th chunk): each chunk's vertices are
-//              merged by key, first along runs of equal keys within a
-//              wavefront, then in an LDS hash table (count and fixed-point
-//              sums added with LDS atomics); each group then probes / claims its cell
+//              merged by key in an LDS hash table (count and fixed-point
+//              sums added with LDS atomics; the LDS serialises the lanes of
+//              a coherent run on one entry more cheaply than a wavefront
+//              prefix sum over them costs in VALU work, which bounds this
+//              kernel); each group then probes / claims its cell
 //              once (compare-and-swap on new cells only), writes one record
 //              {slot, count, sums} to the tile's staging area and counts it
 //              in the tile's histogram of slot bins; every vertex receives
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 }
                 if (fk.key_out && i < i1) fk.key_out[i] = k;
                 flp |= f << (8 * u);
-                const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
+                const int e = merge_into_lds<false>(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
                 ep |= (uint64_t)(uint16_t)e << (16 * u);
             }
         } else {
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             int64_t q0 = 0, q1 = 0, q2 = 0;
             if (f == 0) f = fixed_point(cr, cg, cb, t.frac_bits, q0, q1, q2);
             flp |= f << (8 * u);  // bits change only where they were 0
-            const int e = merge_into_lds(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
+            const int e = merge_into_lds<false>(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
             ep |= (uint64_t)(uint16_t)e << (16 * u);
         }
         }
@@ -331,24 +333,34 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 }
 
 // Per bin: exclusive running offset over the tiles (in place), bin total.
+// Tiles are taken XCD by XCD (workgroups are dealt to the 8 XCDs in turn,
+// so tile t runs on XCD t % 8): a bin's range is cut into 8 sub-ranges each
+// written by the scatter workgroups of one XCD, and a cache line of records
+// is filled through one L2 instead of several.
 // A workgroup takes 16 bins; each of its 64 rows of lanes holds the counts of
-// 8 consecutive tiles in registers, so a column is loaded once, summed in
-// parallel and rewritten without a second read.
+// 8 consecutive tiles of that order in registers, so a column is loaded
+// once, summed in parallel and rewritten without a second read.
 constexpr int kScanBins = 16, kScanRows = 64, kScanPer = 8;
+constexpr uint32_t kXcds = 8;
 static_assert(kScanRows * kScanPer >= kMaxTiles, "one register batch covers every tile");
+static_assert(kMaxTiles % kXcds == 0, "tiles split evenly over the XCDs");
 __global__ __launch_bounds__(kScanBins *kScanRows) void colscan_kernel(uint32_t *__restrict__ H, uint32_t ntiles,
                                                                        uint32_t nbins,
                                                                        uint32_t *__restrict__ total) {
     __shared__ uint32_t part[kScanRows][kScanBins + 1];
     const uint32_t bx = threadIdx.x % kScanBins, cy = threadIdx.x / kScanBins;
     const uint32_t bin = blockIdx.x * kScanBins + bx;
-    const uint32_t t0 = cy * kScanPer;
-    uint32_t v[kScanPer];
+    const uint32_t per = (ntiles + kXcds - 1) / kXcds;  // tiles per XCD (at most 64)
+    const uint32_t q0 = cy * kScanPer;
+    uint32_t v[kScanPer], tt[kScanPer];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-        const uint32_t t = t0 + k;
-        v[k] = (bin < nbins && t < ntiles) ? H[(size_t)t * nbins + bin] : 0u;
+        const uint32_t q = q0 + k;  // position in XCD-major order
+        tt[k] = (q % per) * kXcds + q / per;
+        const bool in = bin < nbins && q < kXcds * per && tt[k] < ntiles;
+        if (!in) tt[k] = ~0u;
+        v[k] = in ? H[(size_t)tt[k] * nbins + bin] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) s += v[k];
@@ -358,8 +370,7 @@ __global__ __launch_bounds__(kScanBins *kScanRows) void colscan_kernel(uint32_t 
     for (uint32_t c = 0; c < cy; ++c) run += part[c][bx];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-        const uint32_t t = t0 + k;
-        if (bin < nbins && t < ntiles) H[(size_t)t * nbins + bin] = run;
+        if (tt[k] != ~0u) H[(size_t)tt[k] * nbins + bin] = run;
         run += v[k];
     }
     if (cy == kScanRows - 1 && bin < nbins) total[bin] = run;

@@ -1,8 +1,8 @@
 // Merging of vertices that share a key inside a workgroup before they touch
 // the table, shared by the binned insert (binned.hip) and the batched
-// multi-view launch (views.hip): runs of equal keys across a wavefront's
-// lanes are summed with DPP, then run tails merge by key in an LDS hash
-// table of (key, count, fixed-point sums) entries.
+// multi-view launch (views.hip): vertices merge by key in an LDS hash table
+// of (key, count, fixed-point sums) entries, optionally after runs of equal
+// keys across a wavefront's lanes are summed with DPP.
 #pragma once
 
 #include "pf_device.h"
@@ -68,16 +68,31 @@ __device__ __forceinline__ void dpp_add(uint64_t &a0, uint64_t &a1, uint64_t &a2
 }
 
 // Adds one vertex per lane (lanes with ok) to the chunk's LDS table and
-// returns its entry (-1: no room).  The lanes of a wavefront hold
+// returns its entry (-1: no room).  kWaveRuns: the lanes of a wavefront hold
 // consecutive vertices, so runs of lanes with equal keys (coherent primary
 // hits) are summed across the wavefront first and only the last lane of a
 // run touches the LDS table: a run's total is the wavefront's inclusive
 // prefix sum at its last lane minus the exclusive prefix sum at its first
-// (integer sums, exact modulo 2^64).  Every lane of the wavefront must call.
+// (integer sums, exact modulo 2^64); every lane of the wavefront must call.
+// Otherwise every valid lane adds itself with LDS atomics.
+template <bool kWaveRuns = true>
 __device__ __forceinline__ int merge_into_lds(unsigned long long *lkey, unsigned long long *ls0,
                                               unsigned long long *ls1, unsigned long long *ls2, uint32_t *lcnt,
                                               uint32_t cap, bool ok, uint64_t k, int64_t q0, int64_t q1,
                                               int64_t q2) {
+    if constexpr (!kWaveRuns) {  // every valid lane adds itself
+        int e = -1;
+        if (ok) {
+            e = lds_insert(lkey, cap, k);
+            if (e >= 0) {
+                atomicAdd(&lcnt[e], 1u);
+                atomicAdd(&ls0[e], (unsigned long long)q0);
+                atomicAdd(&ls1[e], (unsigned long long)q1);
+                atomicAdd(&ls2[e], (unsigned long long)q2);
+            }
+        }
+        return e;
+    }
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t kv = ok ? k : kEmpty;
     const uint64_t prev = dpp<0x138>(kv);  // wave_shr:1, the previous lane's key

@@ -9,7 +9,8 @@ filter_frame() composes the steps in the paper's order:
   keys (Algorithm 1) -> fixed-point radiance -> exact group-by on the key
   (Eq. (7)/(8), Section 3.2's gather form) -> linear-probing simulation
   (Section 3.2) -> average = sum / counter (Sections 3.2, 3.3.1) ->
-  exponential moving average with the previous frame's set (Section 3.4.1).
+  exponential moving average with the previous frame's set (Section 3.4.1),
+  optionally followed by a low-density fallback (Section 3.3).
 """
 from __future__ import annotations
 
@@ -59,6 +60,8 @@ def lib():
         L.orc_temporal_ema.argtypes = [u64, vp, vp, u64, vp, vp, f32, vp]
         L.orc_temporal_integrate.argtypes = [u64, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         L.orc_key_hashes.argtypes = [u64, vp, u32, vp, vp]
+        L.orc_low_density.argtypes = [u64, vp, vp, vp, vp, u32, ctypes.c_int, i32, vp, vp]
+        L.orc_low_density.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -199,6 +202,29 @@ def temporal_integrate(gkey, gnew, gcnt, pkey, pold, pcnt, max_samples):
     return out[:3 * G].reshape(G, 3).copy(), outn[:G].copy()
 
 
+CUBE, NORMALS = 0, 1  # low-density fallback modes
+
+
+def low_density(gkey, gcnt, gsum, placed, gval, below, mode, frac_bits):
+    """Section 3.3's fallbacks for voxels with fewer than `below` vertices:
+    mode CUBE pools the 3x3x3 neighbourhood (same level and normal class),
+    mode NORMALS the voxels at the same position and level with a similar
+    normal class (positive dot product of the class vectors).  Returns
+    (values [G,3] float32 with pooled voxels replaced, pooled mask [G])."""
+    G = gkey.shape[0]
+    out = np.ascontiguousarray(_f32(gval).reshape(-1)).copy()
+    if out.shape[0] == 0:
+        out = np.zeros(3, np.float32)
+    pooled = np.zeros(max(G, 1), np.uint8)
+    rc = lib().orc_low_density(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(np.ascontiguousarray(gcnt, np.uint32)),
+                               _p(np.ascontiguousarray(gsum, np.int64).reshape(-1)),
+                               _p(np.ascontiguousarray(placed, np.uint8)), int(below), int(mode), int(frac_bits),
+                               _p(out), _p(pooled))
+    if rc < 0:
+        raise OverflowError("a pooled sum leaves int64")
+    return out[:3 * G].reshape(G, 3).copy(), pooled[:G].astype(bool)
+
+
 def query(vgroup, gslot, gval, gcnt, r, g, b, flags):
     n = vgroup.shape[0]
     out = np.zeros(3 * max(n, 1), np.float32)
@@ -234,7 +260,7 @@ class FrameResult:
 
 def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
                  idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None,
-                 max_samples=None):
+                 max_samples=None, low_density_fallback=None):
     """The whole hot path for one view and frame on the CPU.
 
     f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
@@ -243,7 +269,10 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     prev_state (the state of the previous frame, None for the first frame),
     or, when max_samples is given, the temporal integration of Section 3.4.1
     with the stored sample count kept at most max_samples; the lookup's count
-    is then the stored count.
+    is then the stored count.  low_density_fallback=(below, mode) then
+    replaces the value of every placed voxel with fewer than `below` vertices
+    in this frame by the pooled average of low_density(); the count the
+    lookup returns is unchanged.
     """
     A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
          ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
@@ -276,6 +305,9 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
         gval = temporal_ema(gkey, gavg, prev_state[0], prev_state[1], alpha_old)
     else:
         gval = gavg
+    if low_density_fallback is not None:
+        below, mode = low_density_fallback
+        gval, _ = low_density(gkey, gcnt, gsum, placed, gval, below, mode, F)
     out, cnt = query(vgroup, sim.gslot, gval, gn, A["r"], A["g"], A["b"], flags)
     state = (gkey[placed].copy(), gval[placed].copy(), gn[placed].copy())
     return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,

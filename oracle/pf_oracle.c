@@ -26,7 +26,10 @@
  *     unfiltered contribution as fallback for vertices that could not be
  *     placed;
  *   - the exponential moving average of Section 3.4.1 over two sets of
- *     averages.
+ *     averages, and its temporal integration with a sample-count threshold;
+ *   - the fallbacks of Section 3.3 for voxels with few vertices: the pooled
+ *     average of the neighbouring voxels, or of the voxels with a similar
+ *     normal in the same probe run.
  *
  * Readings of points the paper leaves open (each stated where it is used):
  *   level_of_detail(d) = floor(log2 d) computed as floor(floor(log2 d2)/2)
@@ -500,4 +503,89 @@ void orc_temporal_integrate(uint64_t G, const uint64_t *gkey, const float *gnew,
         }
         outn[g] = (uint32_t)(n < max_samples ? n : max_samples);
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Fallbacks for voxels with few vertices (Section 3.3).  A placed voxel
+ * whose count is below `below` takes the pooled average of a set of placed
+ * voxels around it: the integer sums and counts of the set are added and
+ * divided once, as for a single voxel.
+ *   mode 0, neighbourhood search: the 3 x 3 x 3 block of voxels at the
+ *     same level of detail and normal class whose quantised coordinates
+ *     differ from its own by at most one per axis (itself included;
+ *     coordinates outside the key range are skipped);
+ *   mode 1, similar normals along the probe run: the voxels with its
+ *     position and level whose normal class vector (one of -1, 0, +1 per
+ *     axis) has a positive dot product with its own -- the fingerprint sees
+ *     the normal but the home index does not, so these voxels share its
+ *     home slot and probe run.
+ * gval is overwritten for the pooled voxels, which are marked in gpooled.
+ * gkey must be ascending.  Returns -1 if a pooled sum leaves int64. */
+static int64_t find_key(uint64_t G, const uint64_t *gkey, uint64_t k)
+{
+    uint64_t lo = 0, hi = G;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (gkey[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return (lo < G && gkey[lo] == k) ? (int64_t)lo : -1;
+}
+
+static int class_sign(uint64_t code, int axis)
+{
+    const uint64_t v = (code >> (2 * axis)) & 3u;
+    return v == 1 ? 1 : (v == 2 ? -1 : 0);
+}
+
+int orc_low_density(uint64_t G, const uint64_t *gkey, const uint32_t *gcnt, const int64_t *gsum,
+                    const uint8_t *placed, uint32_t below, int mode, int32_t frac_bits,
+                    float *gval, uint8_t *gpooled)
+{
+    const uint64_t coord_mask = (1ull << 51) - 1;   /* the three 17-bit coordinates */
+    const uint64_t pos_mask = (1ull << 56) - 1;     /* coordinates and level */
+    for (uint64_t g = 0; g < G; ++g) {
+        gpooled[g] = 0;
+        if (!placed[g] || gcnt[g] >= below) continue;
+        const uint64_t K = gkey[g];
+        uint64_t cand[27];
+        int nc = 0;
+        if (mode == 0) {
+            int x[3];
+            for (int c = 0; c < 3; ++c) x[c] = (int)((K >> (17 * c)) & 0x1ffffu) - 65536;
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
+                        int ok = 1;
+                        for (int c = 0; c < 3; ++c) ok = ok && y[c] > -65536 && y[c] < 65536;
+                        if (!ok) continue;
+                        cand[nc++] = (K & ~coord_mask) | (uint64_t)(y[0] + 65536) |
+                                     ((uint64_t)(y[1] + 65536) << 17) | ((uint64_t)(y[2] + 65536) << 34);
+                    }
+        } else {
+            const uint64_t code = K >> 56;
+            for (uint64_t cx = 0; cx < 3; ++cx)
+                for (uint64_t cy = 0; cy < 3; ++cy)
+                    for (uint64_t cz = 0; cz < 3; ++cz) {
+                        const uint64_t other = cx | (cy << 2) | (cz << 4);
+                        int dot = 0;
+                        for (int c = 0; c < 3; ++c) dot += class_sign(code, c) * class_sign(other, c);
+                        if (dot > 0) cand[nc++] = (K & pos_mask) | (other << 56);
+                    }
+        }
+        __int128 S[3] = {0, 0, 0};
+        uint64_t N = 0;
+        for (int k = 0; k < nc; ++k) {
+            const int64_t j = find_key(G, gkey, cand[k]);
+            if (j < 0 || !placed[j]) continue;
+            N += gcnt[j];
+            for (int c = 0; c < 3; ++c) S[c] += gsum[3 * j + c];
+        }
+        for (int c = 0; c < 3; ++c) {
+            if (S[c] > (__int128)INT64_MAX || S[c] < (__int128)INT64_MIN) return -1;
+            gval[3 * g + c] = (float)(ldexp((double)(int64_t)S[c], -frac_bits) / (double)N);
+        }
+        gpooled[g] = 1;
+    }
+    return 0;
 }

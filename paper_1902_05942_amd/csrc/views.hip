@@ -259,7 +259,7 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
                 qv[u][0] = qv[u][1] = qv[u][2] = 0;
                 fv[u] = PF_V_INVALID;
                 if (i < d.n) fv[u] = view_vertex(d, t, i, kv[u], qv[u][0], qv[u][1], qv[u][2]);
-                ev[u] = merge_into_lds(L.mkey, L.ms0, L.ms1, L.ms2, L.mcnt, kCap, fv[u] == 0, kv[u], qv[u][0],
+                ev[u] = merge_into_lds<false>(L.mkey, L.ms0, L.ms1, L.ms2, L.mcnt, kCap, fv[u] == 0, kv[u], qv[u][0],
                                        qv[u][1], qv[u][2]);
             }
             __syncthreads();

@@ -52,6 +52,9 @@ def parse():
     p.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle timed on the host")
     p.add_argument("--lean", action="store_true",
                    help="time the frames only (no probes, segments, quality or oracle legs): for profiler runs")
+    p.add_argument("--low-density", default="",
+                   help="below,mode: add the low-density fallback (mode 0 neighbourhood, 1 similar normals) for "
+                        "cells with fewer than `below` vertices, timed as its own stage")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -147,6 +150,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     fused = a.insert == "fused"
+    low_density = tuple(int(x) for x in a.low_density.split(",")) if a.low_density else None
 
     def stages(k):
         """(name, call) of one frame's steps, in order"""
@@ -169,6 +173,8 @@ def main():
                 st.append(("insert_accumulate",
                            lambda: pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)))
         st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
+        if low_density:
+            st.append(("low_density", lambda: pf.low_density_fallback(cur, *low_density)))
         st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
                                                              outs[0], outs[1], outs[2], count if use_mlp else None)))
         if use_mlp:
@@ -246,6 +252,18 @@ def main():
             o_ref = ref.filter(fk["px"], fk["py"], fk["pz"], fk["nx"], fk["ny"], fk["nz"], fk["valid"], fk["r"],
                                fk["g"], fk["b"], fk["cam"], fk["s"], fk["seed"])
         q_sparse_ref = float(torch.sqrt(((torch.stack(o_ref, 1)[sparse] - f_last["truth"][sparse]) ** 2).mean()))
+        # the paper's own fallbacks for the same cells (Section 3.3), over the same frames
+        q_ld = {}
+        for mode, name in ((pf.LD_NEIGHBOURS, "neighbours"), (pf.LD_NORMALS, "normals")):
+            ldf = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True,
+                                 alpha_old=wl.alpha_old, device=dev, fused=True, low_density=(4, mode))
+            for k in range(a.frames):
+                fk = frames[(a.warmup + a.steps - a.frames + k) % len(frames)]
+                o_ld = ldf.filter(fk["px"], fk["py"], fk["pz"], fk["nx"], fk["ny"], fk["nz"], fk["valid"], fk["r"],
+                                  fk["g"], fk["b"], fk["cam"], fk["s"], fk["seed"])
+            q_ld[name] = {"rmse_sparse": round(float(torch.sqrt(((torch.stack(o_ld, 1)[sparse] -
+                                                                   f_last["truth"][sparse]) ** 2).mean())), 5),
+                          "rmse_all": round(rmse(o_ld, f_last), 5)}
         mlp_us = per["mlp_select_train_infer"]
         flops = 4 * 16384 * 2 * (10240 + 15360)
         train_us = float(np.mean([e[1].elapsed_time(e[2]) for e in mlp_ev["all"]])) * 1e3
@@ -258,7 +276,8 @@ def main():
                     "train_flops_per_frame": flops,
                     "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
                     "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),
-                    "loss": float(fb.net.loss().cpu()[0])}
+                    "loss": float(fb.net.loss().cpu()[0]),
+                    "low_density_fallback_below_4": q_ld}
     q_noisy = rmse((f_last["r"], f_last["g"], f_last["b"]), f_last)
     plain = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=False, agg_width=a.agg,
                            device=dev)

@@ -285,6 +285,32 @@ pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float al
 pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint32_t max_samples, void *stream);
 
 
+/* ------------------------------------------------- low-density fallbacks */
+/* Section 3.3's fallbacks for voxels with a low number of vertices.  For
+ * every occupied cell of t whose count in this frame is below `below`,
+ * replaces the rgb of its temporal value (t->blend, written for every
+ * occupied cell by pf_temporal_update / pf_temporal_integrate, which must
+ * run first; with prev = NULL it holds the plain averages) by the pooled
+ * average of a set of cells around it:
+ *   PF_LD_NEIGHBOURS (0), neighbourhood search (Section 3.3.1): the cells
+ *     of the 3 x 3 x 3 block of voxels at the same level and normal class
+ *     whose quantised coordinates differ from its own by at most one per
+ *     axis (itself included; coordinates outside the key range skipped);
+ *   PF_LD_NORMALS (1), similar normals (Section 3.2.2, linear probing with
+ *     the normal in the fingerprint only): the cells at the same position
+ *     and level found along its probe run, from its home slot to the first
+ *     empty slot (at most max_probe slots), whose normal class vector (-1,
+ *     0, +1 per axis) has a positive dot product with its own.
+ * Pooled value: (float)((double)S * 2^-frac_bits / (double)N) with S and N
+ * the integer sums and counts of the set (S wraps modulo 2^64, which no
+ * input within PF_V_RADRANGE reaches).  The stored count (blend's fourth
+ * float) is kept, so the lookup still reports the cell's own count.
+ * below <= 1 changes nothing.  Fixed-point tables only.
+ * Errors: PF_EINVAL (no blend array, binary32 sums), PF_ERANGE (mode). */
+#define PF_LD_NEIGHBOURS 0
+#define PF_LD_NORMALS 1
+pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream);
+
 /* ------------------------------------------------------- learned fallback */
 /* A small BF16 network that predicts the contribution of vertices whose
  * cell holds few samples, trained online on the averages of well-populated

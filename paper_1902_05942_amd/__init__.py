@@ -17,7 +17,7 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
-                   build_keys_insert_binned)
+                   build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS)
 
 
 class MlpFallback:
@@ -62,14 +62,15 @@ class FrameFilter:
     the per-vertex key, flag and slot buffers.
 
     filter() runs one frame: clear the current table, build keys, insert,
-    temporal blend against the previous frame's table, look up, then swap
-    the tables.  Every step is one library call on the current stream.
+    temporal blend against the previous frame's table, the low-density
+    fallback when asked for, look up, then swap the tables.  Every step is
+    one library call on the current stream.
     """
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
-                 max_samples: "int | None" = None, fused: bool = False):
+                 max_samples: "int | None" = None, fused: bool = False, low_density=None):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -79,6 +80,8 @@ class FrameFilter:
         self.temporal = temporal
         self.alpha_old = alpha_old
         self.max_samples = max_samples  # None: moving average; else temporal integration with this threshold
+        # (below, mode): cells with fewer vertices take the pooled value of low_density_fallback
+        self.low_density = low_density
         self.agg_width = agg_width
         self.key = torch.empty(n_max, dtype=torch.int64, device=device)
         self.vflags = torch.empty(n_max, dtype=torch.uint8, device=device)
@@ -119,14 +122,17 @@ class FrameFilter:
                 insert_accumulate_binned(cur, key, r, g, b, vflags, slot, self.ws)
             else:
                 insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
-        if self.temporal:
+        use_blend = self.temporal or self.low_density is not None
+        if use_blend:
             if self.max_samples is None:
                 temporal_update(cur, self.prev, self.alpha_old)
             else:
                 temporal_integrate(cur, self.prev, self.max_samples)
+        if self.low_density is not None:
+            low_density_fallback(cur, *self.low_density)
         if out is None:
             out = (torch.empty_like(r), torch.empty_like(g), torch.empty_like(b))
-        query_average(cur, key, slot, r, g, b, vflags, self.temporal, out[0], out[1], out[2], cnt)
+        query_average(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2], cnt)
         if self.mlp is not None:
             geo = geometry(key, px, py, pz, nx, ny, nz, cam)
             self.mlp.apply(cur, geo, vflags, cnt, slot, out, seed)

@@ -88,6 +88,7 @@ def _load():
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_temporal_integrate": ([T, T, u32, vp], i),
+        "pf_low_density_fallback": ([T, u32, i, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
         "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
         "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, vp], i),
@@ -117,7 +118,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
-            "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz")
+            "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback")
 
 
 def _ptr(t):
@@ -261,6 +262,16 @@ MAX_SAMPLES = 1 << 24
 def temporal_integrate(cur: Table, prev, max_samples: int = MAX_SAMPLES, stream=None):
     _check("pf_temporal_integrate", lib.pf_temporal_integrate(cur.ref, None if prev is None else prev.ref,
                                                               int(max_samples), _stream(stream)))
+
+
+LD_NEIGHBOURS, LD_NORMALS = 0, 1
+
+
+def low_density_fallback(t: Table, below: int, mode: int = LD_NEIGHBOURS, stream=None):
+    """Section 3.3's fallback for cells with fewer than `below` vertices
+    (after temporal_update / temporal_integrate, before query_average with
+    use_blend)."""
+    _check("pf_low_density_fallback", lib.pf_low_density_fallback(t.ref, int(below), int(mode), _stream(stream)))
 
 
 MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS = 0, 1, 2, 3, 4

@@ -247,6 +247,15 @@ pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint3
     return temporal(cur, prev, 0.0f, 1, max_samples, stream);
 }
 
+pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream) {
+    pf_status s = check_table(t);
+    if (s != PF_OK) return s;
+    if (!t->blend || t->sum_format != PF_SUMS_FIXED64) return PF_EINVAL;
+    if (mode != PF_LD_NEIGHBOURS && mode != PF_LD_NORMALS) return PF_ERANGE;
+    if (below <= 1) return PF_OK;
+    return launched(pfk::launch_low_density(to_tab(t), below, mode, (hipStream_t)stream));
+}
+
 // ------------------------------------------------------------------ learned fallback
 namespace {
 size_t mlp_partial_floats(uint32_t max_batch) { return (size_t)(max_batch / PF_MLP_BLOCK_SAMPLES) * (PF_MLP_NPARAM + 1); }

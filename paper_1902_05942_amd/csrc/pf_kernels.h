@@ -71,6 +71,7 @@ hipError_t launch_mlp_train(const MlpArgs &a, const Tab &t, const GeoArgs &g, co
 hipError_t launch_mlp_features(const GeoArgs &g, const uint32_t *idx, uint32_t n, uint16_t *out, hipStream_t st);
 hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *idx, const uint32_t *counts,
                             uint32_t n_max, float *r, float *gc, float *b, hipStream_t st);
+hipError_t launch_low_density(const Tab &t, uint32_t below, int mode, hipStream_t st);
 hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int mode, uint32_t cap,
                            hipStream_t st);
 

@@ -32,7 +32,7 @@ def table_contents(t: pf.Table):
 
 
 def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=False, alpha=0.2,
-              idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None):
+              idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None, low_density=None):
     """One frame through the C ABI; returns per-vertex results and stats."""
     n = g["px"].numel()
     dev = g["px"].device
@@ -64,8 +64,11 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
         pf.insert_accumulate(cur, key, g["r"], g["g"], g["b"], vflags, slot if use_slot else None, agg)
     if temporal and max_samples is not None:
         pf.temporal_integrate(cur, prev, max_samples)
-    elif temporal:
-        pf.temporal_update(cur, prev, alpha)
+    elif temporal or low_density is not None:
+        pf.temporal_update(cur, prev if temporal else None, alpha)
+    if low_density is not None:
+        pf.low_density_fallback(cur, *low_density)
+        temporal = True  # the lookup returns the temporal value
     if in_place:
         out = (g["r"].clone(), g["g"].clone(), g["b"].clone())
         pf.query_average(cur, key, slot if use_slot else None, out[0], out[1], out[2], vflags, temporal,

@@ -107,6 +107,11 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_temporal_update(ctypes.byref(t3), None, ctypes.c_float(0.2), 0, None) == lp.PF_EINVAL
     assert L.pf_query_average(ctypes.byref(t3), fake, None, fake, fake, fake, fake, 5, 1, fake, fake, fake, None,
                               None) == lp.PF_EINVAL
+    # low-density fallback: needs the blend array and fixed-point sums, a known mode; below <= 1 is a no-op
+    assert L.pf_low_density_fallback(ctypes.byref(t3), 4, 0, None) == lp.PF_EINVAL
+    assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE
+    assert L.pf_low_density_fallback(ctypes.byref(t), 1, 0, None) == lp.PF_OK
+    assert L.pf_low_density_fallback(None, 4, 0, None) == lp.PF_EINVAL
     # binary32 sums: accepted by the atomic insert's checks, refused by the binned insert; unknown formats refused
     tf = lp.pf_table()
     assert L.pf_table_carve(ctypes.c_void_p(0x7C0000000000), 10, 1, 64, 24, ctypes.byref(tf)) == 0

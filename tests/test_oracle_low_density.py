@@ -14,18 +14,8 @@ import synth
 F = 24
 
 
-def _random_frame(n, seed, s, spread=0.6):
-    rng = np.random.default_rng(seed)
-    pos = rng.uniform(-spread, spread, (n, 3)).astype(np.float32)
-    pos[:, 1] += 1.0
-    nrm = rng.normal(size=(n, 3))
-    nrm[rng.random((n, 3)) < 0.15] = 0.0          # some zero components: class 0 on that axis
-    nrm[np.all(nrm == 0, 1), 0] = 1.0
-    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
-    rgb = rng.uniform(0.05, 2.0, (n, 3)).astype(np.float32)
-    return {"px": pos[:, 0], "py": pos[:, 1], "pz": pos[:, 2], "nx": nrm[:, 0], "ny": nrm[:, 1], "nz": nrm[:, 2],
-            "r": rgb[:, 0], "g": rgb[:, 1], "b": rgb[:, 2], "valid": np.ones(n, np.uint8),
-            "cam": (0.0, 2.0, -6.0), "s": s, "seed": 7, "log2_slots": 15, "max_probe": 64, "frac_bits": F}
+def _random_frame(n, seed, s):
+    return synth.mixed_normals_frame(n, seed, s)
 
 
 def _vertex_attrs(f):

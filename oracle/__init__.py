@@ -10,7 +10,8 @@ filter_frame() composes the steps in the paper's order:
   (Eq. (7)/(8), Section 3.2's gather form) -> linear-probing simulation
   (Section 3.2) -> average = sum / counter (Sections 3.2, 3.3.1) ->
   exponential moving average with the previous frame's set (Section 3.4.1),
-  optionally followed by a low-density fallback (Section 3.3).
+  optionally followed by a low-density fallback (Section 3.3) or combined
+  with a coarser level (multi-level accumulation, Section 3.3.2).
 """
 from __future__ import annotations
 
@@ -51,7 +52,7 @@ def lib():
         L.orc_fmix64.argtypes = [u64]; L.orc_fmix64.restype = u64
         L.orc_splitmix64.argtypes = [u64]; L.orc_splitmix64.restype = u64
         L.orc_level_of_detail.argtypes = [vp, f32, f32, f32]; L.orc_level_of_detail.restype = ctypes.c_int
-        L.orc_build_keys.argtypes = [u64] + [vp] * 7 + [vp, f32, u64, u64, u32] + [vp] * 4 + [vp] * 3
+        L.orc_build_keys.argtypes = [u64] + [vp] * 7 + [vp, f32, u64, u64, u32] + [vp] * 4 + [vp] * 3 + [i32]
         L.orc_quantize_radiance.argtypes = [u64, vp, vp, vp, i32, vp, vp]
         L.orc_group_by.argtypes = [u64, vp, vp, vp, vp, vp, vp, vp]; L.orc_group_by.restype = ctypes.c_int64
         L.orc_simulate_table.argtypes = [u64, vp, vp, vp, u32, u32, vp, vp, vp]
@@ -101,8 +102,10 @@ def level_of_detail(cam, x, y, z) -> int:
     return int(lib().orc_level_of_detail(_p(c), float(np.float32(x)), float(np.float32(y)), float(np.float32(z))))
 
 
-def build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, log2_slots, steps=False):
-    """Key, fingerprint, home and flags per vertex (Algorithm 1)."""
+def build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, log2_slots, steps=False, level_up=0):
+    """Key, fingerprint, home and flags per vertex (Algorithm 1); level_up > 0
+    quantises the jittered position at level l' + level_up instead (the
+    enclosing voxel of multi-level accumulation, Section 3.3.2)."""
     arrs = [_f32(a) for a in (px, py, pz, nx, ny, nz)]
     n = arrs[0].shape[0]
     v = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
@@ -113,7 +116,7 @@ def build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, log2_slots
     xq = np.zeros(3 * n, np.int32) if steps else None
     camv = _f32(cam)
     lib().orc_build_keys(n, *[_p(a) for a in arrs], _p(v), _p(camv), float(np.float32(s)), seed, idx_base,
-                         log2_slots, _p(key), _p(fp), _p(home), _p(flags), _p(lvl), _p(xj), _p(xq))
+                         log2_slots, _p(key), _p(fp), _p(home), _p(flags), _p(lvl), _p(xj), _p(xq), int(level_up))
     out = {"key": key, "fp": fp, "home": home, "flags": flags}
     if steps:
         out["lvl"] = lvl.reshape(n, 2); out["xj"] = xj.reshape(n, 3); out["xq"] = xq.reshape(n, 3)
@@ -260,7 +263,7 @@ class FrameResult:
 
 def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
                  idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None,
-                 max_samples=None, low_density_fallback=None):
+                 max_samples=None, low_density_fallback=None, level_up=0):
     """The whole hot path for one view and frame on the CPU.
 
     f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
@@ -272,7 +275,9 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     is then the stored count.  low_density_fallback=(below, mode) then
     replaces the value of every placed voxel with fewer than `below` vertices
     in this frame by the pooled average of low_density(); the count the
-    lookup returns is unchanged.
+    lookup returns is unchanged.  level_up > 0 filters with the voxels
+    level_up levels coarser than each vertex's own (Section 3.3.2); a vertex
+    flagged at its own level keeps that flag.
     """
     A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
          ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
@@ -284,6 +289,14 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     F = f["frac_bits"] if frac_bits is None else frac_bits
 
     k = build_keys(A["px"], A["py"], A["pz"], A["nx"], A["ny"], A["nz"], A["valid"], cam, s, seed, idx_base, m)
+    if level_up:
+        fine = k["flags"]
+        k = build_keys(A["px"], A["py"], A["pz"], A["nx"], A["ny"], A["nz"], A["valid"], cam, s, seed, idx_base, m,
+                       level_up=level_up)
+        flagged = fine != 0
+        k["flags"] = np.where(flagged, fine, k["flags"]).astype(np.uint8)
+        for name in ("key", "fp", "home"):
+            k[name] = np.where(flagged, 0, k[name]).astype(k[name].dtype)
     flags = k["flags"].copy()
     q = quantize_radiance(A["r"], A["g"], A["b"], F, flags)
     gkey, gcnt, gsum, vgroup = group_by(k["key"], flags, q)
@@ -312,6 +325,17 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     state = (gkey[placed].copy(), gval[placed].copy(), gn[placed].copy())
     return FrameResult(k["key"], k["fp"], k["home"], flags, q, vgroup, gkey, gfp, ghome, gcnt, gsum, gavg, gval,
                        sim, out, cnt, state)
+
+
+def multilevel(fine: FrameResult, coarse: FrameResult, below: int):
+    """Multi-level accumulation (Section 3.3.2): a vertex whose own voxel has
+    fewer than `below` vertices (the lookup's count) takes its coarser
+    voxel's value and count when that voxel was placed; otherwise its own
+    voxel's.  Returns (out [n,3], count [n])."""
+    use = (fine.flags == 0) & (fine.cnt < below) & (coarse.flags == 0)
+    out = np.where(use[:, None], coarse.out, fine.out).astype(np.float32)
+    cnt = np.where(use, coarse.cnt, fine.cnt).astype(np.uint32)
+    return out, cnt
 
 
 def key_hashes(key, log2_slots):

@@ -29,7 +29,8 @@
  *     averages, and its temporal integration with a sample-count threshold;
  *   - the fallbacks of Section 3.3 for voxels with few vertices: the pooled
  *     average of the neighbouring voxels, or of the voxels with a similar
- *     normal in the same probe run.
+ *     normal in the same probe run; and the keys of coarser voxels for
+ *     multi-level accumulation (Section 3.3.2).
  *
  * Readings of points the paper leaves open (each stated where it is used):
  *   level_of_detail(d) = floor(log2 d) computed as floor(floor(log2 d2)/2)
@@ -167,6 +168,10 @@ static void key_hashes(uint64_t k, uint64_t mask, uint32_t *home, uint32_t *fp)
  * Flagged vertices get key = fp = home = 0.
  * Optional intermediates (each nullable): lvl[2n] = (l, l'), xj[3n] = x',
  * xq[3n] = x~.
+ * level_up > 0 quantises x' at the coarser level l' + level_up instead
+ * (x~ = floor(x' / (s * 2^(l' + level_up))), that level in the key): the
+ * enclosing voxel of multi-level accumulation (Section 3.3.2); a level above
+ * the key's range (15) flags the vertex KEYRANGE.
  */
 void orc_build_keys(uint64_t n,
                     const float *px, const float *py, const float *pz,
@@ -174,7 +179,7 @@ void orc_build_keys(uint64_t n,
                     const uint8_t *valid, const float cam[3], float s,
                     uint64_t seed, uint64_t idx_base, uint32_t log2_slots,
                     uint64_t *key, uint32_t *fp, uint32_t *home, uint8_t *flags,
-                    int32_t *lvl, float *xj, int32_t *xq)
+                    int32_t *lvl, float *xj, int32_t *xq, int32_t level_up)
 {
     const uint64_t mask = (log2_slots >= 64) ? ~0ULL : ((1ULL << log2_slots) - 1);
     for (uint64_t i = 0; i < n; ++i) {
@@ -207,8 +212,9 @@ void orc_build_keys(uint64_t n,
         /* l' <- level_of_detail(|p_cam - x'|) */
         int lp = orc_level_of_detail(cam, xp[0], xp[1], xp[2]);
 
-        /* x~ <- floor(x' / (s * 2^l')) */
-        float hp = ldexpf(s, lp);
+        /* x~ <- floor(x' / (s * 2^l')), at l' + level_up for a coarser level */
+        const int lq = lp + level_up;
+        float hp = ldexpf(s, lq);
         int32_t q[3];
         int inrange = 1;
         for (int c = 0; c < 3; ++c) {
@@ -219,14 +225,14 @@ void orc_build_keys(uint64_t n,
         if (lvl) { lvl[2 * i] = l; lvl[2 * i + 1] = lp; }
         if (xj) for (int c = 0; c < 3; ++c) xj[3 * i + c] = xp[c];
         if (xq) for (int c = 0; c < 3; ++c) xq[3 * i + c] = q[c];
-        if (!inrange) { flags[i] = ORC_KEYRANGE; continue; }
+        if (!inrange || lq > ORC_LMAX) { flags[i] = ORC_KEYRANGE; continue; }
 
         /* key: 17 bits per offset coordinate, 5 bits level, 6 bits normal */
         uint32_t code = normal_class(nr[0]) | (normal_class(nr[1]) << 2) | (normal_class(nr[2]) << 4);
         uint64_t k = (uint64_t)(uint32_t)(q[0] + ORC_QMAX)
                    | ((uint64_t)(uint32_t)(q[1] + ORC_QMAX) << 17)
                    | ((uint64_t)(uint32_t)(q[2] + ORC_QMAX) << 34)
-                   | ((uint64_t)(uint32_t)(lp - ORC_LMIN) << 51)
+                   | ((uint64_t)(uint32_t)(lq - ORC_LMIN) << 51)
                    | ((uint64_t)code << 56);
         key_hashes(k, mask, &home[i], &fp[i]);
         key[i] = k;

@@ -55,6 +55,9 @@ def parse():
     p.add_argument("--low-density", default="",
                    help="below,mode: add the low-density fallback (mode 0 neighbourhood, 1 similar normals) for "
                         "cells with fewer than `below` vertices, timed as its own stage")
+    p.add_argument("--multilevel", default="",
+                   help="below,levels: also accumulate every vertex `levels` levels coarser in a second pair of tables "
+                        "and look up the coarser cell for cells with fewer than `below` vertices, timed per stage")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -151,6 +154,16 @@ def main():
 
     fused = a.insert == "fused"
     low_density = tuple(int(x) for x in a.low_density.split(",")) if a.low_density else None
+    multilevel = tuple(int(x) for x in a.multilevel.split(",")) if a.multilevel else None
+    if multilevel:
+        ctabs = [pf.Table(view.log2_slots, wl.max_probe, wl.frac_bits, True, dev) for _ in range(2)]
+        for t in ctabs:
+            pf.table_init(t)
+        key_c = torch.empty(n, dtype=torch.int64, device=dev)
+        vflags_c = torch.empty(n, dtype=torch.uint8, device=dev)
+        slot_c = torch.empty(n, dtype=torch.int32, device=dev)
+        ws_c = flt.ws if flt.ws is not None else torch.empty(pf.insert_workspace_bytes(n, view.log2_slots),
+                                                             dtype=torch.uint8, device=dev)
 
     def stages(k):
         """(name, call) of one frame's steps, in order"""
@@ -161,7 +174,7 @@ def main():
         if fused:
             st.append(("build_keys_insert", lambda: pf.build_keys_insert_binned(
                 cur, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"], f["seed"], 0,
-                f["r"], f["g"], f["b"], key if use_mlp else None, vflags, slot, flt.ws)))
+                f["r"], f["g"], f["b"], key if (use_mlp or multilevel) else None, vflags, slot, flt.ws)))
         else:
             st.append(("build_keys", lambda: pf.build_keys(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"],
                                                            f["valid"], f["cam"], f["s"], f["seed"], 0,
@@ -175,8 +188,22 @@ def main():
         st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
         if low_density:
             st.append(("low_density", lambda: pf.low_density_fallback(cur, *low_density)))
-        st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
-                                                             outs[0], outs[1], outs[2], count if use_mlp else None)))
+        if multilevel:
+            cc, cp = ctabs[k % 2], (ctabs[(k + 1) % 2] if flt.frames else None)
+
+            def coarse_level():
+                pf.clear(cc)
+                pf.coarsen_keys(key, vflags, multilevel[1], key_c, vflags_c)
+                pf.insert_accumulate_binned(cc, key_c, f["r"], f["g"], f["b"], vflags_c, slot_c, ws_c)
+                pf.temporal_update(cc, cp, wl.alpha_old)
+            st.append(("coarse_level", coarse_level))
+            st.append(("query_multilevel", lambda: pf.query_multilevel(
+                cur, cc, slot, slot_c, f["r"], f["g"], f["b"], vflags, vflags_c, multilevel[0], True, outs[0],
+                outs[1], outs[2], count if use_mlp else None)))
+        else:
+            st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
+                                                                 outs[0], outs[1], outs[2],
+                                                                 count if use_mlp else None)))
         if use_mlp:
             def mlp():
                 geo = pf.geometry(key, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["cam"])
@@ -252,11 +279,13 @@ def main():
             o_ref = ref.filter(fk["px"], fk["py"], fk["pz"], fk["nx"], fk["ny"], fk["nz"], fk["valid"], fk["r"],
                                fk["g"], fk["b"], fk["cam"], fk["s"], fk["seed"])
         q_sparse_ref = float(torch.sqrt(((torch.stack(o_ref, 1)[sparse] - f_last["truth"][sparse]) ** 2).mean()))
-        # the paper's own fallbacks for the same cells (Section 3.3), over the same frames
+        # the paper's own fallbacks for the same cells (Sections 3.3.1, 3.2.2, 3.3.2), over the same frames
         q_ld = {}
-        for mode, name in ((pf.LD_NEIGHBOURS, "neighbours"), (pf.LD_NORMALS, "normals")):
+        for name, opt in (("neighbours", {"low_density": (4, pf.LD_NEIGHBOURS)}),
+                          ("normals", {"low_density": (4, pf.LD_NORMALS)}),
+                          ("multilevel_1", {"multilevel": (4, 1)})):
             ldf = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True,
-                                 alpha_old=wl.alpha_old, device=dev, fused=True, low_density=(4, mode))
+                                 alpha_old=wl.alpha_old, device=dev, fused=True, **opt)
             for k in range(a.frames):
                 fk = frames[(a.warmup + a.steps - a.frames + k) % len(frames)]
                 o_ld = ldf.filter(fk["px"], fk["py"], fk["pz"], fk["nx"], fk["ny"], fk["nz"], fk["valid"], fk["r"],
@@ -277,7 +306,7 @@ def main():
                     "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
                     "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),
                     "loss": float(fb.net.loss().cpu()[0]),
-                    "low_density_fallback_below_4": q_ld}
+                    "paper_fallbacks_below_4": q_ld}
     q_noisy = rmse((f_last["r"], f_last["g"], f_last["b"]), f_last)
     plain = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=False, agg_width=a.agg,
                            device=dev)
@@ -313,7 +342,7 @@ def main():
     ra = random_access(dev, (1 << view.log2_slots) * 32)
     touches = 4 * nv + cells
     t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
-    t_iq = (t_ins + per["query_average"]) * 1e-6
+    t_iq = (t_ins + per.get("query_average", per.get("query_multilevel", 0.0))) * 1e-6
     ra["insert_query_touches"] = int(touches)
     ra["achieved_G_touches_per_s"] = round(touches / t_iq / 1e9, 2)
     ra["frac_of_gather"] = round(touches / t_iq / 1e9 / ra["G_per_s"]["gather_32B"], 4)

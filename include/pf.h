@@ -311,6 +311,37 @@ pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint3
 #define PF_LD_NORMALS 1
 pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream);
 
+/* ---------------------------------------------- multi-level accumulation */
+/* Section 3.3.2: accumulating at more than one resolution at a time.
+ * pf_coarsen_keys writes, for every vertex, the key of the voxel `levels`
+ * levels coarser that encloses its own: level field l' + levels, each cell
+ * coordinate floor-divided by 2^levels, the same normal class.  This equals
+ * Algorithm 1's quantisation floor(x' / (s * 2^(l' + levels))) of the same
+ * jittered position (IEEE quotients by powers of two scale exactly).
+ * vflags_out: the vertex's flag, except that PF_V_OVERFLOW (its key is
+ * valid) becomes 0, and PF_V_KEYRANGE when l' + levels > 15; key_out is 0
+ * for flagged vertices.  The coarse keys are then inserted into a second
+ * table (pf_insert_accumulate[_binned]) and optionally blended across
+ * frames (pf_temporal_update) like the vertex's own.  levels in [1, 31].
+ * Errors: PF_EINVAL (NULL or misaligned arrays, n > PF_MAX_VERTICES),
+ * PF_ERANGE (levels). */
+pf_status pf_coarsen_keys(const uint64_t *key, const uint8_t *vflags, uint64_t n, uint32_t levels,
+                          uint64_t *key_out, uint8_t *vflags_out, void *stream);
+
+/* The lookup of multi-level accumulation: as pf_query_average through
+ * `slot` in `fine`, except that a vertex whose cell's count (the count the
+ * lookup returns: blend's count with use_blend, else the cell's) is below
+ * `below` takes the value and count of its coarse cell (slot_coarse in
+ * `coarse`) when that vertex was placed there (vflags_coarse == 0 and a
+ * valid slot).  Flagged vertices (vflags != 0) write their own contribution
+ * and count 0.  r_out.. may alias r_in..; count_out is nullable.
+ * Errors: PF_EINVAL (NULL or misaligned arrays, NULL blend with use_blend). */
+pf_status pf_query_multilevel(const pf_table *fine, const pf_table *coarse, const uint32_t *slot,
+                              const uint32_t *slot_coarse, const float *r_in, const float *g_in,
+                              const float *b_in, const uint8_t *vflags, const uint8_t *vflags_coarse,
+                              uint64_t n, uint32_t below, int use_blend, float *r_out, float *g_out,
+                              float *b_out, uint32_t *count_out, void *stream);
+
 /* ------------------------------------------------------- learned fallback */
 /* A small BF16 network that predicts the contribution of vertices whose
  * cell holds few samples, trained online on the averages of well-populated

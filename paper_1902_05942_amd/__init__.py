@@ -17,7 +17,8 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
-                   build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS)
+                   build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
+                   query_multilevel)
 
 
 class MlpFallback:
@@ -70,7 +71,7 @@ class FrameFilter:
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
-                 max_samples: "int | None" = None, fused: bool = False, low_density=None):
+                 max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -82,6 +83,18 @@ class FrameFilter:
         self.max_samples = max_samples  # None: moving average; else temporal integration with this threshold
         # (below, mode): cells with fewer vertices take the pooled value of low_density_fallback
         self.low_density = low_density
+        # (below, levels): vertices whose cell holds fewer vertices take the cell `levels` levels coarser,
+        # accumulated in a second pair of tables (multi-level accumulation)
+        self.multilevel = multilevel
+        self.coarse = None
+        if multilevel is not None:
+            self.coarse = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
+                           for _ in range(2 if temporal else 1)]
+            for t in self.coarse:
+                table_init(t)
+            self.key_c = torch.empty(n_max, dtype=torch.int64, device=device)
+            self.vflags_c = torch.empty(n_max, dtype=torch.uint8, device=device)
+            self.slot_c = torch.empty(n_max, dtype=torch.int32, device=device)
         self.agg_width = agg_width
         self.key = torch.empty(n_max, dtype=torch.int64, device=device)
         self.vflags = torch.empty(n_max, dtype=torch.uint8, device=device)
@@ -113,9 +126,10 @@ class FrameFilter:
         cnt = self.count[:n] if (with_count or self.mlp is not None) else None
         cur = self.cur
         clear(cur)
-        if self.fused:  # the keys are only written when the learned fallback reads them
+        if self.fused:  # the keys are only written when the learned fallback or the coarser level reads them
+            want_key = self.mlp is not None or self.multilevel is not None
             build_keys_insert_binned(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b,
-                                     key if self.mlp is not None else None, vflags, slot, self.ws)
+                                     key if want_key else None, vflags, slot, self.ws)
         else:
             build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, self.log2_slots, key, None, None, vflags)
             if self.ws is not None:
@@ -123,21 +137,39 @@ class FrameFilter:
             else:
                 insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
         use_blend = self.temporal or self.low_density is not None
-        if use_blend:
-            if self.max_samples is None:
-                temporal_update(cur, self.prev, self.alpha_old)
+        levels = [(cur, self.prev)]
+        if self.multilevel is not None:
+            cc = self.coarse[0]
+            key_c, vflags_c, slot_c = self.key_c[:n], self.vflags_c[:n], self.slot_c[:n]
+            clear(cc)
+            coarsen_keys(key, vflags, self.multilevel[1], key_c, vflags_c)
+            if self.ws is not None:
+                insert_accumulate_binned(cc, key_c, r, g, b, vflags_c, slot_c, self.ws)
             else:
-                temporal_integrate(cur, self.prev, self.max_samples)
+                insert_accumulate(cc, key_c, r, g, b, vflags_c, slot_c, self.agg_width)
+            levels.append((cc, self.coarse[1] if (self.temporal and self.frames > 0) else None))
+        if use_blend:
+            for t_cur, t_prev in levels:
+                if self.max_samples is None:
+                    temporal_update(t_cur, t_prev, self.alpha_old)
+                else:
+                    temporal_integrate(t_cur, t_prev, self.max_samples)
         if self.low_density is not None:
             low_density_fallback(cur, *self.low_density)
         if out is None:
             out = (torch.empty_like(r), torch.empty_like(g), torch.empty_like(b))
-        query_average(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2], cnt)
+        if self.multilevel is not None:
+            query_multilevel(cur, self.coarse[0], slot, slot_c, r, g, b, vflags, vflags_c, self.multilevel[0],
+                             use_blend, out[0], out[1], out[2], cnt)
+        else:
+            query_average(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2], cnt)
         if self.mlp is not None:
             geo = geometry(key, px, py, pz, nx, ny, nz, cam)
             self.mlp.apply(cur, geo, vflags, cnt, slot, out, seed)
         if self.temporal:
             self.tables.reverse()
+            if self.coarse is not None:
+                self.coarse.reverse()
         self.frames += 1
         return out
 

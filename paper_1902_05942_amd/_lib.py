@@ -89,6 +89,8 @@ def _load():
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_low_density_fallback": ([T, u32, i, vp], i),
+        "pf_coarsen_keys": ([vp, vp, u64, u32, vp, vp, vp], i),
+        "pf_query_multilevel": ([T, T, vp, vp, vp, vp, vp, vp, vp, u64, u32, i, vp, vp, vp, vp, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
         "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
         "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, vp], i),
@@ -118,7 +120,8 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
-            "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback")
+            "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
+            "pf_coarsen_keys", "pf_query_multilevel")
 
 
 def _ptr(t):
@@ -272,6 +275,22 @@ def low_density_fallback(t: Table, below: int, mode: int = LD_NEIGHBOURS, stream
     (after temporal_update / temporal_integrate, before query_average with
     use_blend)."""
     _check("pf_low_density_fallback", lib.pf_low_density_fallback(t.ref, int(below), int(mode), _stream(stream)))
+
+
+def coarsen_keys(key, vflags, levels: int, key_out, vflags_out, stream=None):
+    """Keys of the voxels `levels` levels coarser (multi-level accumulation)."""
+    n = vflags.numel()
+    _check("pf_coarsen_keys", lib.pf_coarsen_keys(_ptr(key), _ptr(vflags), n, int(levels), _ptr(key_out),
+                                                  _ptr(vflags_out), _stream(stream)))
+
+
+def query_multilevel(fine: Table, coarse: Table, slot, slot_coarse, r_in, g_in, b_in, vflags, vflags_coarse,
+                     below: int, use_blend, r_out, g_out, b_out, count_out=None, stream=None):
+    n = vflags.numel()
+    _check("pf_query_multilevel", lib.pf_query_multilevel(
+        fine.ref, coarse.ref, _ptr(slot), _ptr(slot_coarse), _ptr(r_in), _ptr(g_in), _ptr(b_in), _ptr(vflags),
+        _ptr(vflags_coarse), n, int(below), int(bool(use_blend)), _ptr(r_out), _ptr(g_out), _ptr(b_out),
+        _ptr(count_out), _stream(stream)))
 
 
 MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS = 0, 1, 2, 3, 4

@@ -256,6 +256,38 @@ pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, v
     return launched(pfk::launch_low_density(to_tab(t), below, mode, (hipStream_t)stream));
 }
 
+pf_status pf_coarsen_keys(const uint64_t *key, const uint8_t *vflags, uint64_t n, uint32_t levels,
+                          uint64_t *key_out, uint8_t *vflags_out, void *stream) {
+    if (n > kMaxN) return PF_EINVAL;
+    if (levels < 1 || levels > 31) return PF_ERANGE;
+    if (n == 0) return PF_OK;
+    if (!key || !vflags || !key_out || !vflags_out || !aligned(key) || !aligned(key_out)) return PF_EINVAL;
+    return launched(pfk::launch_coarsen(key, vflags, (uint32_t)n, levels, key_out, vflags_out, (hipStream_t)stream));
+}
+
+pf_status pf_query_multilevel(const pf_table *fine, const pf_table *coarse, const uint32_t *slot,
+                              const uint32_t *slot_coarse, const float *r_in, const float *g_in,
+                              const float *b_in, const uint8_t *vflags, const uint8_t *vflags_coarse,
+                              uint64_t n, uint32_t below, int use_blend, float *r_out, float *g_out,
+                              float *b_out, uint32_t *count_out, void *stream) {
+    pf_status s = check_table(fine);
+    if (s != PF_OK) return s;
+    s = check_table(coarse);
+    if (s != PF_OK) return s;
+    if (n > kMaxN) return PF_EINVAL;
+    if (use_blend && (!fine->blend || !coarse->blend)) return PF_EINVAL;
+    if (n == 0) return PF_OK;
+    if (!slot || !slot_coarse || !r_in || !g_in || !b_in || !vflags || !vflags_coarse || !r_out || !g_out ||
+        !b_out)
+        return PF_EINVAL;
+    if (!aligned(slot) || !aligned(slot_coarse) || !aligned(r_in) || !aligned(g_in) || !aligned(b_in) ||
+        !aligned(r_out) || !aligned(g_out) || !aligned(b_out) || (count_out && !aligned(count_out)))
+        return PF_EINVAL;
+    return launched(pfk::launch_query_multilevel(to_tab(fine), to_tab(coarse), slot, slot_coarse, r_in, g_in, b_in,
+                                                 vflags, vflags_coarse, (uint32_t)n, below, use_blend != 0, r_out,
+                                                 g_out, b_out, count_out, (hipStream_t)stream));
+}
+
 // ------------------------------------------------------------------ learned fallback
 namespace {
 size_t mlp_partial_floats(uint32_t max_batch) { return (size_t)(max_batch / PF_MLP_BLOCK_SAMPLES) * (PF_MLP_NPARAM + 1); }

@@ -112,6 +112,15 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE
     assert L.pf_low_density_fallback(ctypes.byref(t), 1, 0, None) == lp.PF_OK
     assert L.pf_low_density_fallback(None, 4, 0, None) == lp.PF_EINVAL
+    # multi-level: levels in [1, 31], arrays required, blend arrays with use_blend
+    assert L.pf_coarsen_keys(fake, fake, 5, 0, fake, fake, None) == lp.PF_ERANGE
+    assert L.pf_coarsen_keys(fake, fake, 5, 32, fake, fake, None) == lp.PF_ERANGE
+    assert L.pf_coarsen_keys(None, fake, 5, 1, fake, fake, None) == lp.PF_EINVAL
+    assert L.pf_coarsen_keys(None, None, 0, 1, None, None, None) == lp.PF_OK
+    assert L.pf_query_multilevel(ctypes.byref(t), ctypes.byref(t), fake, None, fake, fake, fake, fake, fake, 5, 4, 0,
+                                 fake, fake, fake, None, None) == lp.PF_EINVAL
+    assert L.pf_query_multilevel(ctypes.byref(t), ctypes.byref(t3), fake, fake, fake, fake, fake, fake, fake, 5, 4, 1,
+                                 fake, fake, fake, None, None) == lp.PF_EINVAL
     # binary32 sums: accepted by the atomic insert's checks, refused by the binned insert; unknown formats refused
     tf = lp.pf_table()
     assert L.pf_table_carve(ctypes.c_void_p(0x7C0000000000), 10, 1, 64, 24, ctypes.byref(tf)) == 0

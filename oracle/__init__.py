@@ -61,6 +61,8 @@ def lib():
         L.orc_temporal_ema.argtypes = [u64, vp, vp, u64, vp, vp, f32, vp]
         L.orc_temporal_integrate.argtypes = [u64, vp, vp, vp, u64, vp, vp, vp, u32, vp, vp]
         L.orc_key_hashes.argtypes = [u64, vp, u32, vp, vp]
+        L.orc_history_lookup.argtypes = [u64, vp, u32, vp, vp, vp, vp, vp]
+        L.orc_history_update.argtypes = [u64, vp, vp, vp, u32, u32, u32, vp, vp, vp, vp]
         L.orc_low_density.argtypes = [u64, vp, vp, vp, vp, u32, ctypes.c_int, i32, vp, vp]
         L.orc_low_density.restype = ctypes.c_int
         _lib = L
@@ -228,6 +230,47 @@ def low_density(gkey, gcnt, gsum, placed, gval, below, mode, frac_bits):
     return out[:3 * G].reshape(G, 3).copy(), pooled[:G].astype(bool)
 
 
+@dataclass
+class History:
+    """Voxel values kept across frames with eviction by priority (Section
+    3.4.3): direct-mapped, 2^log2 slots of (word, key, value (c, N), stamp);
+    an empty slot has word = all ones.  See orc_history_update."""
+    log2: int
+    max_age: int
+    word: np.ndarray
+    key: np.ndarray
+    val: np.ndarray
+    stamp: np.ndarray
+
+    @staticmethod
+    def empty(log2: int, max_age: int) -> "History":
+        m = 1 << log2
+        return History(log2, max_age, np.full(m, np.iinfo(np.uint64).max, np.uint64), np.zeros(m, np.uint64),
+                       np.zeros((m, 4), np.float32), np.zeros(m, np.uint32))
+
+    def occupied(self) -> np.ndarray:
+        return self.word != np.iinfo(np.uint64).max
+
+
+def history_lookup(H: History, gkey):
+    """(hit [G] bool, old [G,4] float32: c and N of the voxels found)."""
+    G = gkey.shape[0]
+    hit = np.zeros(max(G, 1), np.uint8)
+    old = np.zeros(4 * max(G, 1), np.float32)
+    lib().orc_history_lookup(G, _p(np.ascontiguousarray(gkey, np.uint64)), H.log2, _p(H.word), _p(H.key),
+                             _p(H.val), _p(hit), _p(old))
+    return hit[:G].astype(bool), old[:4 * G].reshape(G, 4).copy()
+
+
+def history_update(H: History, gkey, gval, gn, frame: int):
+    """Ages H to `frame` and lets this frame's voxels (values gval [G,3],
+    counts gn) compete for their slots; updates H in place."""
+    G = gkey.shape[0]
+    lib().orc_history_update(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(_f32(gval).reshape(-1)),
+                             _p(np.ascontiguousarray(gn, np.uint32)), H.log2, H.max_age, int(frame),
+                             _p(H.word), _p(H.key), _p(H.val), _p(H.stamp))
+
+
 def query(vgroup, gslot, gval, gcnt, r, g, b, flags):
     n = vgroup.shape[0]
     out = np.zeros(3 * max(n, 1), np.float32)
@@ -263,7 +306,7 @@ class FrameResult:
 
 def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
                  idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None,
-                 max_samples=None, low_density_fallback=None, level_up=0):
+                 max_samples=None, low_density_fallback=None, level_up=0, history=None, frame=0):
     """The whole hot path for one view and frame on the CPU.
 
     f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
@@ -277,7 +320,9 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     in this frame by the pooled average of low_density(); the count the
     lookup returns is unchanged.  level_up > 0 filters with the voxels
     level_up levels coarser than each vertex's own (Section 3.3.2); a vertex
-    flagged at its own level keeps that flag.
+    flagged at its own level keeps that flag.  With a History (and
+    temporal=True) the blend takes c_old from it instead of prev_state, and
+    the frame's placed voxels then update it (history_update at `frame`).
     """
     A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
          ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
@@ -310,7 +355,16 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     gavg = average(gcnt, gsum, F)
     placed = sim.gslot >= 0
     gn = gcnt
-    if temporal and max_samples is not None:
+    if temporal and history is not None:
+        pk = gkey[placed]
+        hit, old = history_lookup(history, pk)
+        if max_samples is None:
+            gval = temporal_ema(gkey, gavg, pk[hit], old[hit][:, :3], alpha_old)
+        else:
+            gval, gn = temporal_integrate(gkey, gavg, gcnt, pk[hit], old[hit][:, :3],
+                                          old[hit][:, 3].astype(np.uint32), max_samples)
+        history_update(history, pk, gval[placed], gn[placed], frame)
+    elif temporal and max_samples is not None:
         pk, pv, pc = prev_state if prev_state is not None else (np.zeros(0, np.uint64), np.zeros((0, 3), np.float32),
                                                                 np.zeros(0, np.uint32))
         gval, gn = temporal_integrate(gkey, gavg, gcnt, pk, pv, pc, max_samples)

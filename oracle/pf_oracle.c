@@ -595,3 +595,74 @@ int orc_low_density(uint64_t G, const uint64_t *gkey, const uint32_t *gcnt, cons
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* A history of voxel values kept beyond the previous frame, with eviction
+ * by priority (Section 3.4.3).  Direct-mapped: the voxel with key K lives
+ * only in slot fmix64(K) mod 2^h.  Each slot holds a 64-bit word, the key,
+ * the value (c, N) and the frame it was last written (stamp); an empty slot
+ * has word = all ones.  The word's top byte is a priority, its low 56 bits a
+ * hash of the key (SplitMix64(K) mod 2^56), so that of all voxels competing
+ * for a slot the one with the smallest word stays: a single minimum decides
+ * collisions and eviction.  Priority (smaller = kept):
+ *   (min(age, 15) << 4) | (15 - min(floor(log2 N), 15)),
+ * age = frames since the voxel was written: recent voxels first, then those
+ * with more samples.
+ * One frame:
+ *   1. orc_history_lookup: hit[g] = 1 and old[g] = the slot's (c, N) when the
+ *      slot of gkey[g] is occupied by that key; the frame's values are then
+ *      blended against old with the arithmetic used for the previous
+ *      frame's set;
+ *   2. orc_history_update, given the frame's blended values gval [G,3] and
+ *      counts gn [G]: every occupied slot whose age = frame - stamp exceeds
+ *      max_age is emptied and the others get their word recomputed with
+ *      their age; then the frame's voxels compete: a slot keeps the minimum
+ *      of its word and the words (age 0) of the voxels mapped to it, and a
+ *      voxel whose word is that minimum writes its key, value and
+ *      stamp = frame. */
+static uint32_t floor_log2_u32(uint32_t x) { uint32_t r = 0; while (x >>= 1) ++r; return r; }
+
+static uint64_t history_word(uint64_t key, uint32_t age, uint32_t count)
+{
+    const uint32_t a = age < 15 ? age : 15;
+    const uint32_t lg = floor_log2_u32(count ? count : 1);
+    const uint32_t p = (a << 4) | (15 - (lg < 15 ? lg : 15));
+    return ((uint64_t)p << 56) | (orc_splitmix64(key) & ((1ull << 56) - 1));
+}
+
+void orc_history_lookup(uint64_t G, const uint64_t *gkey, uint32_t log2_hist, const uint64_t *hword,
+                        const uint64_t *hkey, const float *hval, uint8_t *hit, float *old)
+{
+    const uint64_t mask = (1ull << log2_hist) - 1;
+    for (uint64_t g = 0; g < G; ++g) {
+        const uint64_t s = orc_fmix64(gkey[g]) & mask;
+        hit[g] = (hword[s] != ~0ull && hkey[s] == gkey[g]);
+        for (int c = 0; c < 4; ++c) old[4 * g + c] = hit[g] ? hval[4 * s + c] : 0.0f;
+    }
+}
+
+void orc_history_update(uint64_t G, const uint64_t *gkey, const float *gval, const uint32_t *gn,
+                        uint32_t log2_hist, uint32_t max_age, uint32_t frame,
+                        uint64_t *hword, uint64_t *hkey, float *hval, uint32_t *hstamp)
+{
+    const uint64_t mask = (1ull << log2_hist) - 1;
+    for (uint64_t s = 0; s <= mask; ++s) {
+        if (hword[s] == ~0ull) continue;
+        const uint32_t age = frame - hstamp[s];
+        if (age > max_age) hword[s] = ~0ull;
+        else hword[s] = history_word(hkey[s], age, (uint32_t)hval[4 * s + 3]);
+    }
+    for (uint64_t g = 0; g < G; ++g) {
+        const uint64_t s = orc_fmix64(gkey[g]) & mask;
+        const uint64_t w = history_word(gkey[g], 0, gn[g]);
+        if (w < hword[s]) hword[s] = w;
+    }
+    for (uint64_t g = 0; g < G; ++g) {
+        const uint64_t s = orc_fmix64(gkey[g]) & mask;
+        if (hword[s] != history_word(gkey[g], 0, gn[g])) continue;
+        hkey[s] = gkey[g];
+        for (int c = 0; c < 3; ++c) hval[4 * s + c] = gval[3 * g + c];
+        hval[4 * s + 3] = (float)gn[g];
+        hstamp[s] = frame;
+    }
+}

@@ -58,6 +58,9 @@ def parse():
     p.add_argument("--multilevel", default="",
                    help="below,levels: also accumulate every vertex `levels` levels coarser in a second pair of tables "
                         "and look up the coarser cell for cells with fewer than `below` vertices, timed per stage")
+    p.add_argument("--history", default="",
+                   help="log2_slots,max_age: blend against a history kept across frames with eviction by priority "
+                        "instead of the previous frame's table")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -155,6 +158,7 @@ def main():
     fused = a.insert == "fused"
     low_density = tuple(int(x) for x in a.low_density.split(",")) if a.low_density else None
     multilevel = tuple(int(x) for x in a.multilevel.split(",")) if a.multilevel else None
+    hist = pf.History(*(int(x) for x in a.history.split(","))) if a.history else None
     if multilevel:
         ctabs = [pf.Table(view.log2_slots, wl.max_probe, wl.frac_bits, True, dev) for _ in range(2)]
         for t in ctabs:
@@ -185,7 +189,12 @@ def main():
             else:
                 st.append(("insert_accumulate",
                            lambda: pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)))
-        st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
+        if hist is not None:
+            fr = flt.frames
+            st.append(("temporal_history", lambda: pf.temporal_history(cur, hist, wl.alpha_old, 0, pf.MAX_SAMPLES,
+                                                                       fr)))
+        else:
+            st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
         if low_density:
             st.append(("low_density", lambda: pf.low_density_fallback(cur, *low_density)))
         if multilevel:

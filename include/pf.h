@@ -285,6 +285,52 @@ pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float al
 pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint32_t max_samples, void *stream);
 
 
+/* ----------------------------------------------------------------- history */
+/* Voxel values kept beyond the previous frame, with eviction by priority
+ * (Section 3.4.3).  Direct-mapped: the voxel with key K lives only in slot
+ * fmix64(K) mod 2^log2_slots (MurmurHash3's finaliser of the whole key).  A
+ * slot holds a word, the key, the value (c: rgb, and N as the fourth float)
+ * and the frame it was last written.  word = priority << 56 | (SplitMix64(K)
+ * mod 2^56), priority = (min(age, 15) << 4) | (15 - min(floor(log2 N), 15)),
+ * age = frames since written: of a slot's resident and the voxels of a
+ * frame mapped to it, the smallest word stays (recent voxels first, then
+ * those with more samples), so collisions and eviction are decided by one
+ * atomic minimum and do not depend on the order of arrival.  An empty slot
+ * has word = all ones.  Memory is bounded by 2^log2_slots slots of 32 bytes;
+ * a voxel not written for more than max_age frames is dropped. */
+typedef struct pf_history {
+    uint64_t *word;      /* [2^log2_slots] */
+    uint64_t *key;       /* [2^log2_slots] */
+    float *value;        /* [4 * 2^log2_slots] rgb, N */
+    uint32_t *stamp;     /* [2^log2_slots] */
+    uint32_t log2_slots; /* 4 .. 30 */
+    uint32_t max_age;    /* frames */
+} pf_history;
+
+/* [host] bytes of an arena for one history (256-byte aligned arrays). */
+size_t pf_history_bytes(uint32_t log2_slots);
+/* [host] points h's arrays into `arena`.  Errors: PF_EINVAL (NULL),
+ * PF_ERANGE (log2_slots). */
+pf_status pf_history_carve(void *arena, uint32_t log2_slots, uint32_t max_age, pf_history *h);
+/* Empties every slot.  Errors: PF_EINVAL (NULL or misaligned arrays). */
+pf_status pf_history_init(const pf_history *h, void *stream);
+
+/* Temporal pass against the history instead of the previous frame's table,
+ * for frame number `frame` (increasing by one per call; stamps are frame
+ * numbers).  For every occupied cell of cur: c_new = sum / count as the
+ * lookup computes it; if h's slot of its key holds that key, the blend of
+ * pf_temporal_update (mode 0, alpha_old) or pf_temporal_integrate (mode 1,
+ * max_samples) with the history's (c, N) as c_old and N_old, else c_new;
+ * stored in cur->blend with its count as there.  Then h is aged to `frame`
+ * (voxels whose age exceeds max_age are dropped, the others get the word of
+ * their age), and the cells of cur compete for their slots with age 0 and
+ * their stored count: the winner of a slot writes key, value (cur->blend)
+ * and stamp.  The table's temporal-hit statistic counts the cells found.
+ * Errors: PF_EINVAL (no blend array, NULL history), PF_ERANGE (alpha_old,
+ * mode, max_samples as in pf_temporal_update / pf_temporal_integrate). */
+pf_status pf_temporal_history(const pf_table *cur, const pf_history *h, float alpha_old, int mode,
+                              uint32_t max_samples, uint32_t frame, void *stream);
+
 /* ------------------------------------------------- low-density fallbacks */
 /* Section 3.3's fallbacks for voxels with a low number of vertices.  For
  * every occupied cell of t whose count in this frame is below `below`,

@@ -18,7 +18,7 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
-                   query_multilevel)
+                   query_multilevel, History, temporal_history)
 
 
 class MlpFallback:
@@ -71,7 +71,8 @@ class FrameFilter:
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
-                 max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None):
+                 max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None,
+                 history=None):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -83,6 +84,8 @@ class FrameFilter:
         self.max_samples = max_samples  # None: moving average; else temporal integration with this threshold
         # (below, mode): cells with fewer vertices take the pooled value of low_density_fallback
         self.low_density = low_density
+        # (log2_slots, max_age): the temporal pass blends against a History kept across frames
+        self.history = History(history[0], history[1], device) if history is not None else None
         # (below, levels): vertices whose cell holds fewer vertices take the cell `levels` levels coarser,
         # accumulated in a second pair of tables (multi-level accumulation)
         self.multilevel = multilevel
@@ -148,6 +151,10 @@ class FrameFilter:
             else:
                 insert_accumulate(cc, key_c, r, g, b, vflags_c, slot_c, self.agg_width)
             levels.append((cc, self.coarse[1] if (self.temporal and self.frames > 0) else None))
+        if self.history is not None and self.temporal:
+            temporal_history(cur, self.history, self.alpha_old, 0 if self.max_samples is None else 1,
+                             self.max_samples or MAX_SAMPLES, self.frames)
+            levels = levels[1:]
         if use_blend:
             for t_cur, t_prev in levels:
                 if self.max_samples is None:

@@ -35,6 +35,11 @@ class pf_table(ctypes.Structure):
                 ("max_probe", ctypes.c_uint32), ("frac_bits", ctypes.c_int32), ("sum_format", ctypes.c_uint32)]
 
 
+class pf_history(ctypes.Structure):
+    _fields_ = [("word", ctypes.c_void_p), ("key", ctypes.c_void_p), ("value", ctypes.c_void_p),
+                ("stamp", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32), ("max_age", ctypes.c_uint32)]
+
+
 class pf_key_params(ctypes.Structure):
     _fields_ = [("cam", ctypes.c_float * 3), ("s", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("idx_base", ctypes.c_uint64)]
@@ -90,6 +95,10 @@ def _load():
         "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_low_density_fallback": ([T, u32, i, vp], i),
         "pf_coarsen_keys": ([vp, vp, u64, u32, vp, vp, vp], i),
+        "pf_history_bytes": ([u32], ctypes.c_size_t),
+        "pf_history_carve": ([vp, u32, u32, ctypes.POINTER(pf_history)], i),
+        "pf_history_init": ([ctypes.POINTER(pf_history), vp], i),
+        "pf_temporal_history": ([T, ctypes.POINTER(pf_history), f32, i, u32, u32, vp], i),
         "pf_query_multilevel": ([T, T, vp, vp, vp, vp, vp, vp, vp, u64, u32, i, vp, vp, vp, vp, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
         "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
@@ -121,7 +130,8 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
-            "pf_coarsen_keys", "pf_query_multilevel")
+            "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
+            "pf_temporal_history")
 
 
 def _ptr(t):
@@ -275,6 +285,42 @@ def low_density_fallback(t: Table, below: int, mode: int = LD_NEIGHBOURS, stream
     (after temporal_update / temporal_integrate, before query_average with
     use_blend)."""
     _check("pf_low_density_fallback", lib.pf_low_density_fallback(t.ref, int(below), int(mode), _stream(stream)))
+
+
+class History:
+    """Voxel values kept across frames with eviction by priority: one arena
+    (a torch uint8 tensor) carved into the pf_history arrays, emptied."""
+
+    def __init__(self, log2_slots: int, max_age: int, device="cuda", stream=None):
+        nbytes = lib.pf_history_bytes(log2_slots)
+        if nbytes == 0:
+            raise PfError("pf_history_bytes", PF_ERANGE)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.h = pf_history()
+        _check("pf_history_carve", lib.pf_history_carve(_ptr(self.arena), log2_slots, max_age, ctypes.byref(self.h)))
+        self.log2_slots, self.max_age = log2_slots, max_age
+        _check("pf_history_init", lib.pf_history_init(ctypes.byref(self.h), _stream(stream)))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.h)
+
+    def _view(self, addr, nbytes, dtype):
+        off = addr - self.arena.data_ptr()
+        return self.arena[off:off + nbytes].view(dtype)
+
+    def arrays(self):
+        """(word int64, key int64, value float32 [S,4], stamp int32) views."""
+        S = 1 << self.log2_slots
+        return (self._view(self.h.word, 8 * S, torch.int64), self._view(self.h.key, 8 * S, torch.int64),
+                self._view(self.h.value, 16 * S, torch.float32).view(S, 4),
+                self._view(self.h.stamp, 4 * S, torch.int32))
+
+
+def temporal_history(cur: Table, hist: History, alpha_old: float, mode: int, max_samples: int, frame: int,
+                     stream=None):
+    _check("pf_temporal_history", lib.pf_temporal_history(cur.ref, hist.ref, float(alpha_old), int(mode),
+                                                          int(max_samples), int(frame), _stream(stream)))
 
 
 def coarsen_keys(key, vflags, levels: int, key_out, vflags_out, stream=None):

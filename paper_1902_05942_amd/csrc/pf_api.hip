@@ -247,6 +247,65 @@ pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint3
     return temporal(cur, prev, 0.0f, 1, max_samples, stream);
 }
 
+size_t pf_history_bytes(uint32_t log2_slots) {
+    if (log2_slots < 4 || log2_slots > 30) return 0;
+    const size_t S = (size_t)1 << log2_slots;
+    return 256 + 2 * align_up(S * sizeof(uint64_t), 256) + align_up(S * 4 * sizeof(float), 256) +
+           align_up(S * sizeof(uint32_t), 256);
+}
+
+pf_status pf_history_carve(void *arena, uint32_t log2_slots, uint32_t max_age, pf_history *h) {
+    if (!arena || !h) return PF_EINVAL;
+    if (log2_slots < 4 || log2_slots > 30) return PF_ERANGE;
+    const size_t S = (size_t)1 << log2_slots;
+    uintptr_t p = align_up(reinterpret_cast<uintptr_t>(arena), 256);
+    h->word = reinterpret_cast<uint64_t *>(p);
+    p += align_up(S * sizeof(uint64_t), 256);
+    h->key = reinterpret_cast<uint64_t *>(p);
+    p += align_up(S * sizeof(uint64_t), 256);
+    h->value = reinterpret_cast<float *>(p);
+    p += align_up(S * 4 * sizeof(float), 256);
+    h->stamp = reinterpret_cast<uint32_t *>(p);
+    h->log2_slots = log2_slots;
+    h->max_age = max_age;
+    return PF_OK;
+}
+
+static bool history_ok(const pf_history *h) {
+    return h && h->word && h->key && h->value && h->stamp && aligned(h->word) && aligned(h->key) &&
+           (reinterpret_cast<uintptr_t>(h->value) % 16) == 0 && aligned(h->stamp) && h->log2_slots >= 4 &&
+           h->log2_slots <= 30;
+}
+
+static pfk::Hist to_hist(const pf_history *h) {
+    pfk::Hist d;
+    d.word = h->word;
+    d.key = h->key;
+    d.value = reinterpret_cast<float4 *>(h->value);
+    d.stamp = h->stamp;
+    d.mask = (uint32_t)((1ull << h->log2_slots) - 1);
+    d.max_age = h->max_age;
+    return d;
+}
+
+pf_status pf_history_init(const pf_history *h, void *stream) {
+    if (!history_ok(h)) return PF_EINVAL;
+    return launched(pfk::launch_history_init(to_hist(h), (hipStream_t)stream));
+}
+
+pf_status pf_temporal_history(const pf_table *cur, const pf_history *h, float alpha_old, int mode,
+                              uint32_t max_samples, uint32_t frame, void *stream) {
+    const pf_status s = check_table(cur);
+    if (s != PF_OK) return s;
+    if (!cur->blend || !history_ok(h)) return PF_EINVAL;
+    if (mode != 0 && mode != 1) return PF_ERANGE;
+    if (mode == 0 && !(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
+    if (mode == 1 && (max_samples < 1 || max_samples > PF_MAX_SAMPLES)) return PF_ERANGE;
+    return launched(pfk::launch_temporal_history(to_tab(cur), to_hist(h), alpha_old, mode,
+                                                 mode == 1 ? max_samples : PF_MAX_SAMPLES, frame,
+                                                 (hipStream_t)stream));
+}
+
 pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream) {
     pf_status s = check_table(t);
     if (s != PF_OK) return s;

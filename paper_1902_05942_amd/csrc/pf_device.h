@@ -130,6 +130,16 @@ struct Tab {
     }
 };
 
+// History of voxel values with eviction by priority, passed to kernels by value.
+struct Hist {
+    uint64_t *word;   // priority byte << 56 | 56-bit key hash; all ones = empty
+    uint64_t *key;
+    float4 *value;    // c (rgb) and N
+    uint32_t *stamp;  // frame last written
+    uint32_t mask;
+    uint32_t max_age;
+};
+
 // Fingerprint read while other lanes may claim slots: a relaxed atomic load.
 __device__ __forceinline__ uint32_t load_fp_probe(uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -10,6 +10,7 @@
 namespace pfk {
 
 struct Tab;
+struct Hist;
 
 struct KeyArgs {
     float cam[3];
@@ -72,6 +73,9 @@ hipError_t launch_mlp_features(const GeoArgs &g, const uint32_t *idx, uint32_t n
 hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *idx, const uint32_t *counts,
                             uint32_t n_max, float *r, float *gc, float *b, hipStream_t st);
 hipError_t launch_low_density(const Tab &t, uint32_t below, int mode, hipStream_t st);
+hipError_t launch_history_init(const Hist &h, hipStream_t st);
+hipError_t launch_temporal_history(const Tab &cur, const Hist &h, float alpha_old, int mode, uint32_t cap,
+                                   uint32_t frame, hipStream_t st);
 hipError_t launch_coarsen(const uint64_t *key, const uint8_t *flags, uint32_t n, uint32_t levels, uint64_t *key_out,
                           uint8_t *flags_out, hipStream_t st);
 hipError_t launch_query_multilevel(const Tab &fine, const Tab &coarse, const uint32_t *slot_f, const uint32_t *slot_c,

@@ -112,6 +112,20 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE
     assert L.pf_low_density_fallback(ctypes.byref(t), 1, 0, None) == lp.PF_OK
     assert L.pf_low_density_fallback(None, 4, 0, None) == lp.PF_EINVAL
+    # history: sizes, arrays, modes
+    assert L.pf_history_bytes(3) == 0 and L.pf_history_bytes(31) == 0
+    assert L.pf_history_bytes(10) >= (1 << 10) * 32
+    h = lp.pf_history()
+    assert L.pf_history_carve(ctypes.c_void_p(0x7C0000000000), 10, 3, ctypes.byref(h)) == lp.PF_OK
+    assert L.pf_history_carve(ctypes.c_void_p(0x7C0000000000), 31, 3, ctypes.byref(h)) == lp.PF_ERANGE
+    assert L.pf_history_init(None, None) == lp.PF_EINVAL
+    assert L.pf_temporal_history(ctypes.byref(t), None, ctypes.c_float(0.2), 0, 1, 0, None) == lp.PF_EINVAL
+    assert L.pf_temporal_history(ctypes.byref(t3), ctypes.byref(h), ctypes.c_float(0.2), 0, 1, 0, None) == \
+        lp.PF_EINVAL
+    assert L.pf_temporal_history(ctypes.byref(t), ctypes.byref(h), ctypes.c_float(0.2), 2, 1, 0, None) == \
+        lp.PF_ERANGE
+    assert L.pf_temporal_history(ctypes.byref(t), ctypes.byref(h), ctypes.c_float(0.2), 1, 0, 0, None) == \
+        lp.PF_ERANGE
     # multi-level: levels in [1, 31], arrays required, blend arrays with use_blend
     assert L.pf_coarsen_keys(fake, fake, 5, 0, fake, fake, None) == lp.PF_ERANGE
     assert L.pf_coarsen_keys(fake, fake, 5, 32, fake, fake, None) == lp.PF_ERANGE

@@ -64,6 +64,7 @@ def lib():
         L.orc_history_lookup.argtypes = [u64, vp, u32, vp, vp, vp, vp, vp]
         L.orc_history_update.argtypes = [u64, vp, vp, vp, u32, u32, u32, vp, vp, vp, vp]
         L.orc_low_density.argtypes = [u64, vp, vp, vp, vp, u32, ctypes.c_int, i32, vp, vp]
+        L.orc_resolve_pixels.argtypes = [u64, u32, vp, vp, vp, ctypes.c_int, vp]
         L.orc_low_density.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -390,6 +391,19 @@ def multilevel(fine: FrameResult, coarse: FrameResult, below: int):
     out = np.where(use[:, None], coarse.out, fine.out).astype(np.float32)
     cnt = np.where(use, coarse.cnt, fine.cnt).astype(np.uint32)
     return out, cnt
+
+
+def resolve_pixels(out, throughput, valid, pixels: int, verts_per_path: int, init=None):
+    """Section 3's resolve: per pixel, the sum over its path's vertices
+    (bounce-major, vertex b of pixel p at b*pixels + p; those with valid != 0)
+    of throughput * value, channel by channel in binary32, bounce 0 first;
+    starting from init [pixels,3] when given.  out, throughput: [n,3]."""
+    c3 = np.ascontiguousarray(_f32(out).reshape(-1))
+    t3 = None if throughput is None else np.ascontiguousarray(_f32(throughput).reshape(-1))
+    v = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
+    px = np.zeros(3 * max(pixels, 1), np.float32) if init is None else np.ascontiguousarray(_f32(init).reshape(-1)).copy()
+    lib().orc_resolve_pixels(pixels, verts_per_path, _p(c3), _p(t3), _p(v), int(init is not None), _p(px))
+    return px[:3 * pixels].reshape(pixels, 3)
 
 
 def key_hashes(key, log2_slots):

@@ -666,3 +666,30 @@ void orc_history_update(uint64_t G, const uint64_t *gkey, const float *gval, con
         hstamp[s] = frame;
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Pixel resolve (Section 3): after filtering, each selected vertex's value
+ * is multiplied by its throughput (the attenuation from the camera along its
+ * path up to the vertex) and accumulated in its pixel.  Vertices are stored
+ * bounce-major: vertex b of pixel p is at b * pixels + p.  Per pixel and
+ * channel, in binary32 with each product and sum rounded, over b = 0, 1, ...:
+ * acc = acc + t * c for the vertices with valid != 0 (valid NULL: all);
+ * t = 1 when throughput is NULL.  accumulate != 0 starts from the pixel's
+ * value, else from 0. */
+void orc_resolve_pixels(uint64_t pixels, uint32_t verts_per_path, const float *c3, const float *t3,
+                        const uint8_t *valid, int accumulate, float *px3)
+{
+    for (uint64_t p = 0; p < pixels; ++p) {
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = accumulate ? px3[3 * p + ch] : 0.0f;
+            for (uint32_t b = 0; b < verts_per_path; ++b) {
+                const uint64_t v = (uint64_t)b * pixels + p;
+                if (valid && valid[v] == 0) continue;
+                const float t = t3 ? t3[3 * v + ch] : 1.0f;
+                const float prod = t * c3[3 * v + ch];
+                acc = acc + prod;
+            }
+            px3[3 * p + ch] = acc;
+        }
+    }
+}

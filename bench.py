@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--history", default="",
                    help="log2_slots,max_age: blend against a history kept across frames with eviction by priority "
                         "instead of the previous frame's table")
+    p.add_argument("--resolve", action="store_true",
+                   help="add the pixel resolve (value times a synthetic throughput, summed per pixel) as a stage")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -159,6 +161,10 @@ def main():
     low_density = tuple(int(x) for x in a.low_density.split(",")) if a.low_density else None
     multilevel = tuple(int(x) for x in a.multilevel.split(",")) if a.multilevel else None
     hist = pf.History(*(int(x) for x in a.history.split(","))) if a.history else None
+    if a.resolve:
+        pixels = view.width * view.height
+        tput = synth.synthetic_throughput(n, 7, dev)
+        image = tuple(torch.empty(pixels, device=dev) for _ in range(3))
     if multilevel:
         ctabs = [pf.Table(view.log2_slots, wl.max_probe, wl.frac_bits, True, dev) for _ in range(2)]
         for t in ctabs:
@@ -213,6 +219,9 @@ def main():
             st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
                                                                  outs[0], outs[1], outs[2],
                                                                  count if use_mlp else None)))
+        if a.resolve:
+            st.append(("resolve_pixels", lambda: pf.resolve_pixels(outs[0], outs[1], outs[2], tput, f["valid"],
+                                                                   pixels, view.verts_per_path, image)))
         if use_mlp:
             def mlp():
                 geo = pf.geometry(key, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["cam"])

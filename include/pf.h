@@ -388,6 +388,22 @@ pf_status pf_query_multilevel(const pf_table *fine, const pf_table *coarse, cons
                               uint64_t n, uint32_t below, int use_blend, float *r_out, float *g_out,
                               float *b_out, uint32_t *count_out, void *stream);
 
+/* ----------------------------------------------------------- pixel resolve */
+/* Section 3: after filtering, each selected vertex's value (r, g, b: the
+ * lookup's output) is multiplied by its throughput (tr, tg, tb: the
+ * attenuation from the camera along its path up to the vertex) and
+ * accumulated in its pixel.  Vertices are bounce-major: vertex k of pixel p
+ * is at k * pixels + p, k < verts_per_path.  Per pixel and channel, in
+ * binary32 with each product and sum rounded, k = 0, 1, ...:
+ * acc = acc + t * c over the vertices with valid != 0 (valid NULL: all);
+ * t = 1 when tr, tg, tb are NULL (all three or none).  accumulate != 0
+ * starts from the pixel's current value, else from 0.
+ * Errors: PF_EINVAL (NULL or misaligned arrays, pixels * verts_per_path >
+ * PF_MAX_VERTICES, throughput arrays partly NULL). */
+pf_status pf_resolve_pixels(const float *r, const float *g, const float *b, const float *tr, const float *tg,
+                            const float *tb, const uint8_t *valid, uint64_t pixels, uint32_t verts_per_path,
+                            int accumulate, float *pr, float *pg, float *pb, void *stream);
+
 /* ------------------------------------------------------- learned fallback */
 /* A small BF16 network that predicts the contribution of vertices whose
  * cell holds few samples, trained online on the averages of well-populated

@@ -95,6 +95,7 @@ def _load():
         "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_low_density_fallback": ([T, u32, i, vp], i),
         "pf_coarsen_keys": ([vp, vp, u64, u32, vp, vp, vp], i),
+        "pf_resolve_pixels": ([vp, vp, vp, vp, vp, vp, vp, u64, u32, i, vp, vp, vp, vp], i),
         "pf_history_bytes": ([u32], ctypes.c_size_t),
         "pf_history_carve": ([vp, u32, u32, ctypes.POINTER(pf_history)], i),
         "pf_history_init": ([ctypes.POINTER(pf_history), vp], i),
@@ -131,7 +132,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
             "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
-            "pf_temporal_history")
+            "pf_temporal_history", "pf_resolve_pixels")
 
 
 def _ptr(t):
@@ -321,6 +322,15 @@ def temporal_history(cur: Table, hist: History, alpha_old: float, mode: int, max
                      stream=None):
     _check("pf_temporal_history", lib.pf_temporal_history(cur.ref, hist.ref, float(alpha_old), int(mode),
                                                           int(max_samples), int(frame), _stream(stream)))
+
+
+def resolve_pixels(r, g, b, throughput, valid, pixels: int, verts_per_path: int, out, accumulate=False, stream=None):
+    """Section 3's resolve: out (pr, pg, pb) [pixels] = (out +) sum over each
+    pixel's vertices of throughput * value; throughput (tr, tg, tb) or None."""
+    tr, tg, tb = throughput if throughput is not None else (None, None, None)
+    _check("pf_resolve_pixels", lib.pf_resolve_pixels(_ptr(r), _ptr(g), _ptr(b), _ptr(tr), _ptr(tg), _ptr(tb),
+                                                      _ptr(valid), int(pixels), int(verts_per_path), int(accumulate),
+                                                      _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(stream)))
 
 
 def coarsen_keys(key, vflags, levels: int, key_out, vflags_out, stream=None):

@@ -306,6 +306,21 @@ pf_status pf_temporal_history(const pf_table *cur, const pf_history *h, float al
                                                  (hipStream_t)stream));
 }
 
+pf_status pf_resolve_pixels(const float *r, const float *g, const float *b, const float *tr, const float *tg,
+                            const float *tb, const uint8_t *valid, uint64_t pixels, uint32_t verts_per_path,
+                            int accumulate, float *pr, float *pg, float *pb, void *stream) {
+    if (verts_per_path && pixels > kMaxN / verts_per_path) return PF_EINVAL;
+    if (pixels == 0) return PF_OK;
+    if (!r || !g || !b || !pr || !pg || !pb || !aligned(r) || !aligned(g) || !aligned(b) || !aligned(pr) ||
+        !aligned(pg) || !aligned(pb))
+        return PF_EINVAL;
+    const int nt = (tr != nullptr) + (tg != nullptr) + (tb != nullptr);
+    if (nt != 0 && nt != 3) return PF_EINVAL;
+    if (nt == 3 && (!aligned(tr) || !aligned(tg) || !aligned(tb))) return PF_EINVAL;
+    return launched(pfk::launch_resolve(r, g, b, tr, tg, tb, valid, (uint32_t)pixels, verts_per_path,
+                                        accumulate != 0, pr, pg, pb, (hipStream_t)stream));
+}
+
 pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream) {
     pf_status s = check_table(t);
     if (s != PF_OK) return s;

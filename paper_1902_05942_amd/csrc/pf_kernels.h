@@ -74,6 +74,9 @@ hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *
                             uint32_t n_max, float *r, float *gc, float *b, hipStream_t st);
 hipError_t launch_low_density(const Tab &t, uint32_t below, int mode, hipStream_t st);
 hipError_t launch_history_init(const Hist &h, hipStream_t st);
+hipError_t launch_resolve(const float *r, const float *g, const float *b, const float *tr, const float *tg,
+                          const float *tb, const uint8_t *valid, uint32_t pixels, uint32_t verts, bool accumulate,
+                          float *pr, float *pg, float *pb, hipStream_t st);
 hipError_t launch_temporal_history(const Tab &cur, const Hist &h, float alpha_old, int mode, uint32_t cap,
                                    uint32_t frame, hipStream_t st);
 hipError_t launch_coarsen(const uint64_t *key, const uint8_t *flags, uint32_t n, uint32_t levels, uint64_t *key_out,

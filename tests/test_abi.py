@@ -112,6 +112,14 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE
     assert L.pf_low_density_fallback(ctypes.byref(t), 1, 0, None) == lp.PF_OK
     assert L.pf_low_density_fallback(None, 4, 0, None) == lp.PF_EINVAL
+    # pixel resolve: arrays, throughput all or none, size limit
+    assert L.pf_resolve_pixels(*([None] * 7), 0, 3, 0, None, None, None, None) == lp.PF_OK
+    assert L.pf_resolve_pixels(fake, fake, fake, fake, None, None, None, 5, 3, 0, fake, fake, fake, None) == \
+        lp.PF_EINVAL
+    assert L.pf_resolve_pixels(fake, fake, fake, None, None, None, None, 5, 3, 0, None, fake, fake, None) == \
+        lp.PF_EINVAL
+    assert L.pf_resolve_pixels(fake, fake, fake, None, None, None, None, 1 << 30, 3, 0, fake, fake, fake,
+                               None) == lp.PF_EINVAL
     # history: sizes, arrays, modes
     assert L.pf_history_bytes(3) == 0 and L.pf_history_bytes(31) == 0
     assert L.pf_history_bytes(10) >= (1 << 10) * 32

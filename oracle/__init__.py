@@ -65,6 +65,7 @@ def lib():
         L.orc_history_update.argtypes = [u64, vp, vp, vp, u32, u32, u32, vp, vp, vp, vp]
         L.orc_low_density.argtypes = [u64, vp, vp, vp, vp, u32, ctypes.c_int, i32, vp, vp]
         L.orc_resolve_pixels.argtypes = [u64, u32, vp, vp, vp, ctypes.c_int, vp]
+        L.orc_temporal_levels.argtypes = [u64, vp, vp, vp, u64, vp, vp, vp, ctypes.c_int, f32, u32, vp, vp, vp]
         L.orc_low_density.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -231,6 +232,25 @@ def low_density(gkey, gcnt, gsum, placed, gval, below, mode, frac_bits):
     return out[:3 * G].reshape(G, 3).copy(), pooled[:G].astype(bool)
 
 
+def temporal_levels(gkey, gnew, gcnt, pkey, pold, pcnt, mode, alpha_old, max_samples):
+    """Section 3.4.2's changes of resolution across frames: the blend of
+    temporal_ema (mode 0) / temporal_integrate (mode 1), with a voxel absent
+    from the previous set taking its parent's value (N / 8 samples) or its
+    children's count-weighted mean.  Returns (values [G,3], stored counts [G],
+    how [G]: 0 none, 1 exact, 2 parent, 3 children)."""
+    G = gkey.shape[0]
+    out = np.zeros(3 * max(G, 1), np.float32)
+    outn = np.zeros(max(G, 1), np.uint32)
+    how = np.zeros(max(G, 1), np.uint8)
+    pk = np.ascontiguousarray(pkey, np.uint64)
+    assert np.all(pk[1:] > pk[:-1]), "previous keys must be strictly ascending"
+    lib().orc_temporal_levels(G, _p(np.ascontiguousarray(gkey, np.uint64)), _p(_f32(gnew).reshape(-1)),
+                              _p(np.ascontiguousarray(gcnt, np.uint32)), pk.shape[0], _p(pk),
+                              _p(_f32(pold).reshape(-1)), _p(np.ascontiguousarray(pcnt, np.uint32)), int(mode),
+                              float(np.float32(alpha_old)), int(max_samples), _p(out), _p(outn), _p(how))
+    return out[:3 * G].reshape(G, 3).copy(), outn[:G].copy(), how[:G].copy()
+
+
 @dataclass
 class History:
     """Voxel values kept across frames with eviction by priority (Section
@@ -307,7 +327,8 @@ class FrameResult:
 
 def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=True,
                  idx_base=0, s=None, seed=None, log2_slots=None, max_probe=None, frac_bits=None,
-                 max_samples=None, low_density_fallback=None, level_up=0, history=None, frame=0):
+                 max_samples=None, low_density_fallback=None, level_up=0, history=None, frame=0,
+                 across_levels=False):
     """The whole hot path for one view and frame on the CPU.
 
     f holds SoA arrays px..nz, r, g, b, valid (numpy or torch CPU) and the
@@ -324,6 +345,8 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
     flagged at its own level keeps that flag.  With a History (and
     temporal=True) the blend takes c_old from it instead of prev_state, and
     the frame's placed voxels then update it (history_update at `frame`).
+    across_levels (with prev_state): temporal_levels, so that a voxel whose
+    level changed finds its region one level coarser or finer.
     """
     A = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in f.items() if k in
          ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b", "valid")}
@@ -365,6 +388,11 @@ def filter_frame(f: dict, cam=None, prev_state=None, alpha_old=0.2, temporal=Tru
             gval, gn = temporal_integrate(gkey, gavg, gcnt, pk[hit], old[hit][:, :3],
                                           old[hit][:, 3].astype(np.uint32), max_samples)
         history_update(history, pk, gval[placed], gn[placed], frame)
+    elif temporal and across_levels:
+        pk, pv, pc = prev_state if prev_state is not None else (np.zeros(0, np.uint64), np.zeros((0, 3), np.float32),
+                                                                np.zeros(0, np.uint32))
+        gval, gn, _ = temporal_levels(gkey, gavg, gcnt, pk, pv, pc, 0 if max_samples is None else 1, alpha_old,
+                                      (1 << 24) if max_samples is None else max_samples)
     elif temporal and max_samples is not None:
         pk, pv, pc = prev_state if prev_state is not None else (np.zeros(0, np.uint64), np.zeros((0, 3), np.float32),
                                                                 np.zeros(0, np.uint32))

@@ -693,3 +693,104 @@ void orc_resolve_pixels(uint64_t pixels, uint32_t verts_per_path, const float *c
         }
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Changes of resolution across frames (Section 3.4.2).  A voxel of this
+ * frame whose key is absent from the previous set may find its region there
+ * one level coarser or finer:
+ *   coarser (the resolution increased): the parent voxel, level l' + 1 and
+ *     cell coordinates floor-divided by 2, its value distributed to the
+ *     finer voxel: c_old = the parent's value, N_old = floor(N_parent / 8)
+ *     (its samples spread over its 8 children; with N_old = 0 in
+ *     integration the parent is not used);
+ *   finer (the resolution decreased): the 8 children, level l' - 1 and cell
+ *     coordinates 2x~ + (0 or 1) per axis, added up: N_old = sum of their
+ *     counts, c_old = (float)(sum_j N_j c_j / N_old) accumulated in double in
+ *     the order j = dx + 2 dy + 4 dz.
+ * The exact key comes first, then the parent, then the children; the blend
+ * (mode 0 moving average with alpha_old, mode 1 integration with
+ * max_samples) is the arithmetic of orc_temporal_ema / orc_temporal_integrate.
+ * how[g]: 0 not found, 1 exact, 2 parent, 3 children.  pkey ascending. */
+static int64_t find_prev(uint64_t Gp, const uint64_t *pkey, uint64_t k)
+{
+    uint64_t lo = 0, hi = Gp;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (pkey[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return (lo < Gp && pkey[lo] == k) ? (int64_t)lo : -1;
+}
+
+void orc_temporal_levels(uint64_t G, const uint64_t *gkey, const float *gnew, const uint32_t *gcnt,
+                         uint64_t Gp, const uint64_t *pkey, const float *pold, const uint32_t *pcnt,
+                         int mode, float alpha_old, uint32_t max_samples, float *out, uint32_t *outn,
+                         uint8_t *how)
+{
+    for (uint64_t g = 0; g < G; ++g) {
+        const uint64_t K = gkey[g];
+        int x[3];
+        for (int c = 0; c < 3; ++c) x[c] = (int)((K >> (17 * c)) & 0x1ffffu) - 65536;
+        const int lp = (int)((K >> 51) & 31u) - 16;
+        const uint64_t code = K >> 56;
+        float cold[3] = {0, 0, 0};
+        uint64_t nold = 0;
+        how[g] = 0;
+        int64_t j = find_prev(Gp, pkey, K);
+        if (j >= 0) {
+            how[g] = 1;
+            for (int c = 0; c < 3; ++c) cold[c] = pold[3 * j + c];
+            nold = pcnt[j];
+        }
+        if (!how[g] && lp + 1 <= ORC_LMAX) {
+            uint64_t P = (code << 56) | ((uint64_t)(lp + 1 - ORC_LMIN) << 51);
+            for (int c = 0; c < 3; ++c) P |= (uint64_t)(uint32_t)((x[c] >> 1) + 65536) << (17 * c);
+            j = find_prev(Gp, pkey, P);
+            if (j >= 0 && (mode == 0 || pcnt[j] / 8 >= 1)) {
+                how[g] = 2;
+                for (int c = 0; c < 3; ++c) cold[c] = pold[3 * j + c];
+                nold = pcnt[j] / 8;
+            }
+        }
+        if (!how[g] && lp - 1 >= ORC_LMIN) {
+            double acc[3] = {0, 0, 0};
+            uint64_t n = 0;
+            for (int d = 0; d < 8; ++d) {
+                uint64_t C = (code << 56) | ((uint64_t)(lp - 1 - ORC_LMIN) << 51);
+                int ok = 1;
+                for (int c = 0; c < 3; ++c) {
+                    const int y = 2 * x[c] + ((d >> c) & 1);
+                    ok = ok && y > -65536 && y < 65536;
+                    C |= (uint64_t)(uint32_t)(y + 65536) << (17 * c);
+                }
+                if (!ok) continue;
+                j = find_prev(Gp, pkey, C);
+                if (j < 0) continue;
+                n += pcnt[j];
+                for (int c = 0; c < 3; ++c) acc[c] += (double)pcnt[j] * (double)pold[3 * j + c];
+            }
+            if (n) {
+                how[g] = 3;
+                for (int c = 0; c < 3; ++c) cold[c] = (float)(acc[c] / (double)n);
+                nold = n;
+            }
+        }
+        uint64_t nkeep = gcnt[g];
+        if (!how[g]) {
+            for (int c = 0; c < 3; ++c) out[3 * g + c] = gnew[3 * g + c];
+        } else {
+            float alpha = alpha_old;
+            if (mode == 1) {
+                const uint64_t nsum = nold + gcnt[g];
+                alpha = (float)nold / (float)nsum;
+                nkeep = nsum;
+            }
+            const float beta = 1.0f - alpha;
+            for (int c = 0; c < 3; ++c) {
+                const float a = alpha * cold[c];
+                const float b = beta * gnew[3 * g + c];
+                out[3 * g + c] = a + b;
+            }
+        }
+        outn[g] = (uint32_t)(mode == 1 ? (nkeep < max_samples ? nkeep : max_samples) : gcnt[g]);
+    }
+}

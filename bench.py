@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--history", default="",
                    help="log2_slots,max_age: blend against a history kept across frames with eviction by priority "
                         "instead of the previous frame's table")
+    p.add_argument("--across-levels", action="store_true",
+                   help="the temporal pass also searches a changed cell's region one level coarser and finer")
     p.add_argument("--resolve", action="store_true",
                    help="add the pixel resolve (value times a synthetic throughput, summed per pixel) as a stage")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -200,7 +202,8 @@ def main():
             st.append(("temporal_history", lambda: pf.temporal_history(cur, hist, wl.alpha_old, 0, pf.MAX_SAMPLES,
                                                                        fr)))
         else:
-            st.append(("temporal_update", lambda: pf.temporal_update(cur, flt.prev, wl.alpha_old)))
+            st.append(("temporal_update", lambda: pf.temporal_update(
+                cur, flt.prev, wl.alpha_old, pf.TEMPORAL_ACROSS_LEVELS if a.across_levels else 0)))
         if low_density:
             st.append(("low_density", lambda: pf.low_density_fallback(cur, *low_density)))
         if multilevel:

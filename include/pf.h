@@ -270,6 +270,16 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
  * in mode 0, unknown mode, differing sizes). */
 pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode,
                              void *stream);
+/* mode | PF_TEMPORAL_ACROSS_LEVELS: changes of resolution across frames
+ * (Section 3.4.2).  A cell whose key is absent from prev takes, in this
+ * order, its parent's value (the cell one level coarser that contains it:
+ * level + 1, cell coordinates floor-divided by 2) with an eighth of the
+ * parent's count as N_old (mode 1 skips a parent with fewer than 8), or its
+ * children's (level - 1, coordinates 2x~ + 0 or 1 per axis) count-weighted
+ * mean, (float)(sum_j N_j c_j / sum_j N_j) accumulated in double over
+ * j = dx + 2 dy + 4 dz, with the sum of their counts as N_old; then the same
+ * blend.  The temporal-hit statistic still counts exact keys only. */
+#define PF_TEMPORAL_ACROSS_LEVELS 16
 
 /* Temporal integration (Section 3.4.1): weighting the previous value by
  * alpha = N_old / (N_old + N_new), where N_old is its stored count and N_new

@@ -18,7 +18,7 @@ from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
-                   query_multilevel, History, temporal_history, resolve_pixels)
+                   query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS)
 
 
 class MlpFallback:
@@ -72,7 +72,7 @@ class FrameFilter:
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
                  max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None,
-                 history=None):
+                 history=None, across_levels: bool = False):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -86,6 +86,11 @@ class FrameFilter:
         self.low_density = low_density
         # (log2_slots, max_age): the temporal pass blends against a History kept across frames
         self.history = History(history[0], history[1], device) if history is not None else None
+        # the moving average looks for a cell whose level changed one level coarser and finer
+        self.across_levels = across_levels
+        if across_levels and max_samples is not None:
+            raise ValueError("across_levels goes with the moving average here (pf_temporal_update mode 1 | "
+                             "TEMPORAL_ACROSS_LEVELS integrates without a sample threshold)")
         # (below, levels): vertices whose cell holds fewer vertices take the cell `levels` levels coarser,
         # accumulated in a second pair of tables (multi-level accumulation)
         self.multilevel = multilevel
@@ -158,7 +163,8 @@ class FrameFilter:
         if use_blend:
             for t_cur, t_prev in levels:
                 if self.max_samples is None:
-                    temporal_update(t_cur, t_prev, self.alpha_old)
+                    temporal_update(t_cur, t_prev, self.alpha_old,
+                                    TEMPORAL_ACROSS_LEVELS if self.across_levels else 0)
                 else:
                     temporal_integrate(t_cur, t_prev, self.max_samples)
         if self.low_density is not None:

@@ -279,6 +279,7 @@ def temporal_integrate(cur: Table, prev, max_samples: int = MAX_SAMPLES, stream=
 
 
 LD_NEIGHBOURS, LD_NORMALS = 0, 1
+TEMPORAL_ACROSS_LEVELS = 16  # pf_temporal_update mode bit: resolution changes across frames
 
 
 def low_density_fallback(t: Table, below: int, mode: int = LD_NEIGHBOURS, stream=None):

@@ -237,8 +237,9 @@ static pf_status temporal(const pf_table *cur, const pf_table *prev, float alpha
 }
 
 pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode, void *stream) {
-    if (mode == 0 && !(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
-    if (mode != 0 && mode != 1) return PF_ERANGE;
+    const int base = mode & ~PF_TEMPORAL_ACROSS_LEVELS;
+    if (base == 0 && !(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
+    if (base != 0 && base != 1) return PF_ERANGE;
     return temporal(cur, prev, alpha_old, mode, PF_MAX_SAMPLES, stream);
 }
 

@@ -228,6 +228,72 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 }
 
 // Temporal values of the occupied cells recorded in occupancy word j of
+// Changes of resolution across frames (Section 3.4.2) for a key absent from
+// `prev`: its parent (level + 1, cell coordinates floor-divided by 2), whose
+// value is distributed to it with an eighth of the parent's samples (in
+// integration a parent with fewer than 8 is not used), else its 8 children
+// (level - 1, coordinates 2x~ + 0 or 1 per axis), added up: the sum of their
+// counts and their count-weighted mean, accumulated in double in the order
+// j = dx + 2 dy + 4 dz.  A candidate whose home slot is empty in prev's
+// occupancy bitmap is absent without a read of the slot.  Returns whether
+// one was found, with its value and count in old.
+__device__ __forceinline__ uint32_t find_exact_occupied(const Tab &t, uint64_t key) {
+    const uint32_t h = home_of(key, t.mask);
+    if (!((t.occ[h >> 5] >> (h & 31)) & 1u)) return kNoSlot;
+    return find_exact(t, key, fingerprint_of(key));
+}
+
+template <bool kIntegrate>
+__device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, float4 &old) {
+    int x[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = (int)((K >> (17 * c)) & 0x1ffffu) - 65536;
+    const int lp = (int)((K >> 51) & 31u) - 16;
+    const uint64_t code = K >> 56;
+    if (lp + 1 <= kLevelMax) {
+        uint64_t P = (code << 56) | ((uint64_t)(uint32_t)(lp + 17) << 51);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P |= (uint64_t)(uint32_t)((x[c] >> 1) + 65536) << (17 * c);
+        const uint32_t s = find_exact_occupied(prev, P);
+        if (s != kNoSlot) {
+            const float4 v = prev.blend[s];
+            const uint32_t n = (uint32_t)v.w / 8;
+            if (!kIntegrate || n >= 1) {
+                old = make_float4(v.x, v.y, v.z, (float)n);
+                return true;
+            }
+        }
+    }
+    if (lp - 1 >= kLevelMin) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        uint32_t n = 0;
+        for (int d = 0; d < 8; ++d) {
+            uint64_t C = (code << 56) | ((uint64_t)(uint32_t)(lp + 15) << 51);
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int y = 2 * x[c] + ((d >> c) & 1);
+                ok = ok && y > -65536 && y < 65536;
+                C |= (uint64_t)(uint32_t)(y + 65536) << (17 * c);
+            }
+            if (!ok) continue;
+            const uint32_t s = find_exact_occupied(prev, C);
+            if (s == kNoSlot) continue;
+            const float4 v = prev.blend[s];
+            const uint32_t w = (uint32_t)v.w;
+            n += w;
+            a0 += (double)w * (double)v.x;
+            a1 += (double)w * (double)v.y;
+            a2 += (double)w * (double)v.z;
+        }
+        if (n) {
+            old = make_float4((float)(a0 / (double)n), (float)(a1 / (double)n), (float)(a2 / (double)n), (float)n);
+            return true;
+        }
+    }
+    return false;
+}
+
 // `cur` (Section 3.4.1), restricted to the bits of `part`; returns how many
 // found their key in `prev`.  The
 // word's cells are taken kTB at a time, and each step of their lookups in
@@ -236,7 +302,9 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 // integration, alpha = N_old / (N_old + N_new) per cell with the stored count
 // kept at most `cap`; else the moving average with a fixed alpha (the stored
 // count is this frame's).
-template <bool kHasPrev, bool kIntegrate, int kTB = 4>  // kTB: cells of one lane looked up together
+// kLevels: a key absent from prev is searched one level coarser and finer
+// (find_across_levels); hits still count exact keys only.
+template <bool kHasPrev, bool kIntegrate, int kTB = 4, bool kLevels = false>  // kTB: cells looked up together
 __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &prev, uint32_t j, float alpha,
                                                   float beta, uint32_t cap, uint32_t part = 0xffffffffu) {
     const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
@@ -316,12 +384,19 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
                 }
             }
             float4 old[kTB];
-#pragma unroll
-            for (int k = 0; k < kTB; ++k)
-                if (found[k]) old[k] = prev.blend[p[k]];
+            bool use[kTB];
 #pragma unroll
             for (int k = 0; k < kTB; ++k) {
-                if (!found[k]) continue;
+                if (found[k]) old[k] = prev.blend[p[k]];
+                use[k] = found[k];
+            }
+            if constexpr (kLevels) {
+                for (int k = 0; k < kTB; ++k)
+                    if (has[k] && !found[k]) use[k] = find_across_levels<kIntegrate>(prev, key[k], old[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                if (!use[k]) continue;
                 float al = alpha, be = beta;
                 if constexpr (kIntegrate) {
                     // counts are exact integers in binary32 (at most 2^24)
@@ -336,7 +411,7 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
                 v[k][0] = a0 + b0;
                 v[k][1] = a1 + b1;
                 v[k][2] = a2 + b2;
-                ++hits;
+                if (found[k]) ++hits;
             }
         }
 #pragma unroll

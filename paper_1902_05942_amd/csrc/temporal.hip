@@ -6,7 +6,7 @@
 
 namespace pfk {
 
-template <bool kHasPrev, bool kIntegrate>
+template <bool kHasPrev, bool kIntegrate, bool kLevels = false>
 __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, float alpha, float beta, uint32_t cap) {
     // four lanes per occupancy word, 8 slots each: enough lanes in flight to
     // hide the chain of dependent lookups
@@ -14,7 +14,8 @@ __global__ __launch_bounds__(kBlock) void temporal_kernel(Tab cur, Tab prev, flo
     const uint32_t stride = gridDim.x * kBlock;
     uint32_t hits = 0;
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nparts; q += stride)
-        hits += temporal_word<kHasPrev, kIntegrate, 2>(cur, prev, q >> 2, alpha, beta, cap, 0xffu << (8 * (q & 3)));
+        hits += temporal_word<kHasPrev, kIntegrate, 2, kLevels>(cur, prev, q >> 2, alpha, beta, cap,
+                                                                 0xffu << (8 * (q & 3)));
     if constexpr (kHasPrev) {
         // one device atomic per block, spread over 32 partial counters
         __shared__ uint32_t s_hits;
@@ -31,7 +32,14 @@ hipError_t launch_temporal(const Tab &cur, const Tab *prev, float alpha_old, int
     const float beta = 1.0f - alpha_old;
     uint32_t blocks = (cur.nwords() * 4 + kBlock - 1) / kBlock;
     if (blocks > 16384) blocks = 16384;
-    if (mode == 1) {
+    const bool levels = (mode & PF_TEMPORAL_ACROSS_LEVELS) != 0;
+    mode &= ~PF_TEMPORAL_ACROSS_LEVELS;
+    if (levels && prev) {  // without a previous table there is nothing to search
+        if (mode == 1)
+            temporal_kernel<true, true, true><<<blocks, kBlock, 0, st>>>(cur, *prev, 0.0f, 0.0f, cap);
+        else
+            temporal_kernel<true, false, true><<<blocks, kBlock, 0, st>>>(cur, *prev, alpha_old, beta, cap);
+    } else if (mode == 1) {
         if (prev)
             temporal_kernel<true, true><<<blocks, kBlock, 0, st>>>(cur, *prev, 0.0f, 0.0f, cap);
         else

@@ -440,6 +440,25 @@ def main_multiview(a):
     for pair in mvf.tables:
         cells += int(pf.read_stats(pair[1])[pf.STAT_USED])
     words = sum((1 << l) // 8 for _, l in shapes)
+    # the same frames view by view through the single-view calls (fused insert, moving average), one stream:
+    # what the batched launch competes with
+    flts = [pf.FrameFilter(nn, l, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old, device=dev,
+                           fused=True) for nn, l in shapes]
+
+    def seq_frame(fr):
+        for flt, f in zip(flts, fr):
+            flt.filter(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["r"], f["g"], f["b"],
+                       f["cam"], f["s"], f["seed"])
+    for k in range(a.warmup):
+        seq_frame(frames[k % nfr])
+    torch.cuda.synchronize()
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sev[0].record()
+    for k in range(a.steps):
+        seq_frame(frames[(a.warmup + k) % nfr])
+    sev[1].record()
+    torch.cuda.synchronize()
+    seq_us = sev[0].elapsed_time(sev[1]) * 1e3 / a.steps
     # per slot: position/normal/valid 25 read, key/flags/slot 13 written, lookup flags+slot 5 read, output 12
     # written; per valid vertex: contribution 12, probe 4, cell update 28, temporal value 16; per invalid slot:
     # own contribution 12; per cell: clear 32, temporal 84; the occupancy bitmaps read twice
@@ -458,6 +477,7 @@ def main_multiview(a):
         "phase_us_last_launch": {"clear": phases[0], "keys_insert": phases[1], "temporal": phases[2],
                                  "lookup": phases[3]},
         "autotune_ms": {f"{b}/{g}": round(v, 4) for (b, g), v in sorted(table.items())},
+        "views_one_by_one_us": round(seq_us, 2),
         "roofline": {"bound": "hbm", "kernel": "views_kernel", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic("views_kernel", "multiview_8", "persistent"),

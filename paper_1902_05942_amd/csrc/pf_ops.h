@@ -237,12 +237,6 @@ __device__ __forceinline__ void accumulate_group(const Tab &t, AggLds<kBlockT> &
 // j = dx + 2 dy + 4 dz.  A candidate whose home slot is empty in prev's
 // occupancy bitmap is absent without a read of the slot.  Returns whether
 // one was found, with its value and count in old.
-__device__ __forceinline__ uint32_t find_exact_occupied(const Tab &t, uint64_t key) {
-    const uint32_t h = home_of(key, t.mask);
-    if (!((t.occ[h >> 5] >> (h & 31)) & 1u)) return kNoSlot;
-    return find_exact(t, key, fingerprint_of(key));
-}
-
 template <bool kIntegrate>
 __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, float4 &old) {
     int x[3];
@@ -250,11 +244,35 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
     for (int c = 0; c < 3; ++c) x[c] = (int)((K >> (17 * c)) & 0x1ffffu) - 65536;
     const int lp = (int)((K >> 51) & 31u) - 16;
     const uint64_t code = K >> 56;
-    if (lp + 1 <= kLevelMax) {
-        uint64_t P = (code << 56) | ((uint64_t)(uint32_t)(lp + 17) << 51);
+    // the parent's and the 8 children's keys, and their home slots' occupancy
+    // bits, all loaded before any is used
+    uint64_t cand[9];
+    bool ok[9];
+    ok[0] = lp + 1 <= kLevelMax;
+    cand[0] = (code << 56) | ((uint64_t)(uint32_t)(lp + 17) << 51);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) P |= (uint64_t)(uint32_t)((x[c] >> 1) + 65536) << (17 * c);
-        const uint32_t s = find_exact_occupied(prev, P);
+    for (int c = 0; c < 3; ++c) cand[0] |= (uint64_t)(uint32_t)((x[c] >> 1) + 65536) << (17 * c);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        cand[1 + d] = (code << 56) | ((uint64_t)(uint32_t)(lp + 15) << 51);
+        ok[1 + d] = lp - 1 >= kLevelMin;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int y = 2 * x[c] + ((d >> c) & 1);
+            ok[1 + d] = ok[1 + d] && y > -65536 && y < 65536;
+            cand[1 + d] |= (uint64_t)(uint32_t)(y + 65536) << (17 * c);
+        }
+    }
+    uint32_t home[9], word[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        home[q] = ok[q] ? home_of(cand[q], prev.mask) : 0u;
+        word[q] = ok[q] ? prev.occ[home[q] >> 5] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ok[q] = ok[q] && ((word[q] >> (home[q] & 31)) & 1u);
+    if (ok[0]) {
+        const uint32_t s = find_exact(prev, cand[0], fingerprint_of(cand[0]));
         if (s != kNoSlot) {
             const float4 v = prev.blend[s];
             const uint32_t n = (uint32_t)v.w / 8;
@@ -264,32 +282,22 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
             }
         }
     }
-    if (lp - 1 >= kLevelMin) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        uint32_t n = 0;
-        for (int d = 0; d < 8; ++d) {
-            uint64_t C = (code << 56) | ((uint64_t)(uint32_t)(lp + 15) << 51);
-            bool ok = true;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int y = 2 * x[c] + ((d >> c) & 1);
-                ok = ok && y > -65536 && y < 65536;
-                C |= (uint64_t)(uint32_t)(y + 65536) << (17 * c);
-            }
-            if (!ok) continue;
-            const uint32_t s = find_exact_occupied(prev, C);
-            if (s == kNoSlot) continue;
-            const float4 v = prev.blend[s];
-            const uint32_t w = (uint32_t)v.w;
-            n += w;
-            a0 += (double)w * (double)v.x;
-            a1 += (double)w * (double)v.y;
-            a2 += (double)w * (double)v.z;
-        }
-        if (n) {
-            old = make_float4((float)(a0 / (double)n), (float)(a1 / (double)n), (float)(a2 / (double)n), (float)n);
-            return true;
-        }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    uint32_t n = 0;
+    for (int d = 0; d < 8; ++d) {
+        if (!ok[1 + d]) continue;
+        const uint32_t s = find_exact(prev, cand[1 + d], fingerprint_of(cand[1 + d]));
+        if (s == kNoSlot) continue;
+        const float4 v = prev.blend[s];
+        const uint32_t w = (uint32_t)v.w;
+        n += w;
+        a0 += (double)w * (double)v.x;
+        a1 += (double)w * (double)v.y;
+        a2 += (double)w * (double)v.z;
+    }
+    if (n) {
+        old = make_float4((float)(a0 / (double)n), (float)(a1 / (double)n), (float)(a2 / (double)n), (float)n);
+        return true;
     }
     return false;
 }

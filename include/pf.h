@@ -308,13 +308,17 @@ pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint3
  * atomic minimum and do not depend on the order of arrival.  An empty slot
  * has word = all ones.  Memory is bounded by 2^log2_slots slots of 32 bytes;
  * a voxel not written for more than max_age frames is dropped. */
+typedef struct pf_history_slot {
+    uint64_t word;  /* priority << 56 | key hash; all ones = empty */
+    uint64_t key;
+    float value[4]; /* rgb, N */
+} pf_history_slot;  /* 32 bytes: one lookup reads one record */
+
 typedef struct pf_history {
-    uint64_t *word;      /* [2^log2_slots] */
-    uint64_t *key;       /* [2^log2_slots] */
-    float *value;        /* [4 * 2^log2_slots] rgb, N */
-    uint32_t *stamp;     /* [2^log2_slots] */
-    uint32_t log2_slots; /* 4 .. 30 */
-    uint32_t max_age;    /* frames */
+    pf_history_slot *slot; /* [2^log2_slots] */
+    uint32_t *stamp;       /* [2^log2_slots] frame last written */
+    uint32_t log2_slots;   /* 4 .. 30 */
+    uint32_t max_age;      /* frames */
 } pf_history;
 
 /* [host] bytes of an arena for one history (256-byte aligned arrays). */

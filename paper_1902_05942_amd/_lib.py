@@ -36,8 +36,8 @@ class pf_table(ctypes.Structure):
 
 
 class pf_history(ctypes.Structure):
-    _fields_ = [("word", ctypes.c_void_p), ("key", ctypes.c_void_p), ("value", ctypes.c_void_p),
-                ("stamp", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32), ("max_age", ctypes.c_uint32)]
+    _fields_ = [("slot", ctypes.c_void_p), ("stamp", ctypes.c_void_p), ("log2_slots", ctypes.c_uint32),
+                ("max_age", ctypes.c_uint32)]
 
 
 class pf_key_params(ctypes.Structure):
@@ -312,10 +312,11 @@ class History:
         return self.arena[off:off + nbytes].view(dtype)
 
     def arrays(self):
-        """(word int64, key int64, value float32 [S,4], stamp int32) views."""
+        """(word int64, key int64, value float32 [S,4], stamp int32) views of
+        the 32-byte slot records and the stamps."""
         S = 1 << self.log2_slots
-        return (self._view(self.h.word, 8 * S, torch.int64), self._view(self.h.key, 8 * S, torch.int64),
-                self._view(self.h.value, 16 * S, torch.float32).view(S, 4),
+        rec = self._view(self.h.slot, 32 * S, torch.int64).view(S, 4)
+        return (rec[:, 0], rec[:, 1], rec[:, 2:].contiguous().view(torch.float32).view(S, 4),
                 self._view(self.h.stamp, 4 * S, torch.int32))
 
 

@@ -2,8 +2,9 @@
 // priority (Section 3.4.3), for gfx950.
 //
 // The history is direct-mapped: the voxel with key K lives only in slot
-// fmix64(K) mod 2^h.  A slot holds a 64-bit word, the key, the value (c, N)
-// and the frame it was last written.  The word's top byte is a priority,
+// fmix64(K) mod 2^h.  A slot is a 32-byte record of a 64-bit word, the key
+// and the value (c, N), so a lookup reads one line; the frame it was last
+// written lives in a separate array read only when ageing.  The word's top byte is a priority,
 // (min(age, 15) << 4) | (15 - min(floor(log2 N), 15)) (recent voxels first,
 // then those with more samples), and its low 56 bits SplitMix64(K) mod 2^56;
 // an empty slot's word is all ones.  Of the resident and the voxels of a
@@ -11,8 +12,8 @@
 // eviction are one 64-bit atomic minimum per voxel and the outcome does not
 // depend on the order of arrival.  pf_temporal_history runs four launches:
 //   blend    per occupied slot of the frame's table: c_new, the history's
-//            (c, N) of its key (one slot: word, key and value loaded
-//            together), the blend of Section 3.4.1, stored in blend;
+//            (c, N) of its key (one record), the blend of Section 3.4.1,
+//            stored in blend;
 //   age      per history slot (a dense, coalesced pass): voxels older than
 //            max_age are dropped, the others get the word of their age;
 //   compete  per occupied slot of the frame's table: atomic minimum of its
@@ -58,9 +59,13 @@ __global__ __launch_bounds__(kBlock) void history_blend_kernel(Tab cur, Hist h, 
             float v[3] = {cur.average(c, 0), cur.average(c, 1), cur.average(c, 2)};
             uint32_t keep = kIntegrate ? min(c.count, cap) : c.count;
             const uint32_t hs = history_slot(h, key);
-            const uint64_t hw = h.word[hs];
-            const uint64_t hk = h.key[hs];
-            const float4 old = h.value[hs];
+            // the slot's word, key and value in one 32-byte record
+            const uint4 *rec = reinterpret_cast<const uint4 *>(h.slot + hs);
+            const uint4 rw = rec[0], rv = rec[1];
+            const uint64_t hw = (uint64_t)rw.x | (uint64_t)rw.y << 32;
+            const uint64_t hk = (uint64_t)rw.z | (uint64_t)rw.w << 32;
+            const float4 old = make_float4(__uint_as_float(rv.x), __uint_as_float(rv.y), __uint_as_float(rv.z),
+                                           __uint_as_float(rv.w));
             if (hw != ~0ull && hk == key) {
                 float al = alpha, be = beta;
                 if constexpr (kIntegrate) {
@@ -92,10 +97,10 @@ __global__ __launch_bounds__(kBlock) void history_blend_kernel(Tab cur, Hist h, 
 __global__ __launch_bounds__(kBlock) void history_age_kernel(Hist h, uint32_t frame, uint32_t max_age) {
     const uint64_t n = (uint64_t)h.mask + 1;
     for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t w = h.word[s];
-        if (w == ~0ull) continue;
+        pf_history_slot &r = h.slot[s];
+        if (r.word == ~0ull) continue;
         const uint32_t age = frame - h.stamp[s];
-        h.word[s] = age > max_age ? ~0ull : history_word(h.key[s], age, (uint32_t)h.value[s].w);
+        r.word = age > max_age ? ~0ull : history_word(r.key, age, (uint32_t)r.value[3]);
     }
 }
 
@@ -115,10 +120,12 @@ __global__ __launch_bounds__(kBlock) void history_offer_kernel(Tab cur, Hist h, 
             const uint64_t mine = history_word(key, 0, (uint32_t)v.w);
             const uint32_t hs = history_slot(h, key);
             if constexpr (!kOwn) {
-                atomicMin(reinterpret_cast<unsigned long long *>(&h.word[hs]), (unsigned long long)mine);
-            } else if (h.word[hs] == mine) {
-                h.key[hs] = key;
-                h.value[hs] = v;
+                atomicMin(reinterpret_cast<unsigned long long *>(&h.slot[hs].word), (unsigned long long)mine);
+            } else if (h.slot[hs].word == mine) {
+                uint4 *rec = reinterpret_cast<uint4 *>(h.slot + hs);
+                rec[0] = make_uint4((uint32_t)mine, (uint32_t)(mine >> 32), (uint32_t)key, (uint32_t)(key >> 32));
+                rec[1] = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                    __float_as_uint(v.w));
                 h.stamp[hs] = frame;
             }
         }
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void history_offer_kernel(Tab cur, Hist h, 
 __global__ __launch_bounds__(kBlock) void history_init_kernel(Hist h) {
     const uint64_t n = (uint64_t)h.mask + 1;
     for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (uint64_t)gridDim.x * kBlock)
-        h.word[s] = ~0ull;  // empty; key, value and stamp are written with the word that owns them
+        h.slot[s].word = ~0ull;  // empty; key, value and stamp are written with the word that owns them
 }
 
 hipError_t launch_history_init(const Hist &h, hipStream_t st) {

@@ -251,8 +251,7 @@ pf_status pf_temporal_integrate(const pf_table *cur, const pf_table *prev, uint3
 size_t pf_history_bytes(uint32_t log2_slots) {
     if (log2_slots < 4 || log2_slots > 30) return 0;
     const size_t S = (size_t)1 << log2_slots;
-    return 256 + 2 * align_up(S * sizeof(uint64_t), 256) + align_up(S * 4 * sizeof(float), 256) +
-           align_up(S * sizeof(uint32_t), 256);
+    return 256 + align_up(S * sizeof(pf_history_slot), 256) + align_up(S * sizeof(uint32_t), 256);
 }
 
 pf_status pf_history_carve(void *arena, uint32_t log2_slots, uint32_t max_age, pf_history *h) {
@@ -260,12 +259,8 @@ pf_status pf_history_carve(void *arena, uint32_t log2_slots, uint32_t max_age, p
     if (log2_slots < 4 || log2_slots > 30) return PF_ERANGE;
     const size_t S = (size_t)1 << log2_slots;
     uintptr_t p = align_up(reinterpret_cast<uintptr_t>(arena), 256);
-    h->word = reinterpret_cast<uint64_t *>(p);
-    p += align_up(S * sizeof(uint64_t), 256);
-    h->key = reinterpret_cast<uint64_t *>(p);
-    p += align_up(S * sizeof(uint64_t), 256);
-    h->value = reinterpret_cast<float *>(p);
-    p += align_up(S * 4 * sizeof(float), 256);
+    h->slot = reinterpret_cast<pf_history_slot *>(p);
+    p += align_up(S * sizeof(pf_history_slot), 256);
     h->stamp = reinterpret_cast<uint32_t *>(p);
     h->log2_slots = log2_slots;
     h->max_age = max_age;
@@ -273,16 +268,13 @@ pf_status pf_history_carve(void *arena, uint32_t log2_slots, uint32_t max_age, p
 }
 
 static bool history_ok(const pf_history *h) {
-    return h && h->word && h->key && h->value && h->stamp && aligned(h->word) && aligned(h->key) &&
-           (reinterpret_cast<uintptr_t>(h->value) % 16) == 0 && aligned(h->stamp) && h->log2_slots >= 4 &&
-           h->log2_slots <= 30;
+    return h && h->slot && h->stamp && (reinterpret_cast<uintptr_t>(h->slot) % 32) == 0 && aligned(h->stamp) &&
+           h->log2_slots >= 4 && h->log2_slots <= 30;
 }
 
 static pfk::Hist to_hist(const pf_history *h) {
     pfk::Hist d;
-    d.word = h->word;
-    d.key = h->key;
-    d.value = reinterpret_cast<float4 *>(h->value);
+    d.slot = h->slot;
     d.stamp = h->stamp;
     d.mask = (uint32_t)((1ull << h->log2_slots) - 1);
     d.max_age = h->max_age;

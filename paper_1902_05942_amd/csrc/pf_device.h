@@ -132,10 +132,8 @@ struct Tab {
 
 // History of voxel values with eviction by priority, passed to kernels by value.
 struct Hist {
-    uint64_t *word;   // priority byte << 56 | 56-bit key hash; all ones = empty
-    uint64_t *key;
-    float4 *value;    // c (rgb) and N
-    uint32_t *stamp;  // frame last written
+    pf_history_slot *slot;  // word (priority byte << 56 | 56-bit key hash; all ones = empty), key, c and N
+    uint32_t *stamp;        // frame last written
     uint32_t mask;
     uint32_t max_age;
 };

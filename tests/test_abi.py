@@ -122,7 +122,7 @@ def test_argument_checks_return_before_launch(pf):
                                None) == lp.PF_EINVAL
     # history: sizes, arrays, modes
     assert L.pf_history_bytes(3) == 0 and L.pf_history_bytes(31) == 0
-    assert L.pf_history_bytes(10) >= (1 << 10) * 32
+    assert L.pf_history_bytes(10) >= (1 << 10) * 36
     h = lp.pf_history()
     assert L.pf_history_carve(ctypes.c_void_p(0x7C0000000000), 10, 3, ctypes.byref(h)) == lp.PF_OK
     assert L.pf_history_carve(ctypes.c_void_p(0x7C0000000000), 31, 3, ctypes.byref(h)) == lp.PF_ERANGE

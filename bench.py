@@ -360,7 +360,7 @@ def main():
     # random-access roofline of the headline (insert + query): per valid vertex
     # the method makes a probe and a cell update when inserting and a probe and
     # a cell read when looking up, plus one claim per cell (4V + C touches)
-    ra = random_access(dev, (1 << view.log2_slots) * 32)
+    ra = random_access(dev, (1 << view.log2_slots) * pf.SLOT_BYTES)
     touches = 4 * nv + cells
     t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
     t_iq = (t_ins + per.get("query_average", per.get("query_multilevel", 0.0))) * 1e-6

@@ -92,11 +92,18 @@ typedef struct pf_cell {
 #define PF_STATS_LEN 128
 
 /* A table is a set of views into one caller-owned arena, filled in by
- * pf_table_carve().  cell, key and blend have 2^log2_slots entries. */
+ * pf_table_carve().  Its 2^log2_slots slots are records of PF_SLOT_BYTES
+ * bytes, so that a lookup reads one cache line per slot: the cell at offset
+ * 0, the key at offset 32, the temporal value at offset 48, 8 bytes of
+ * padding.  cell, key and blend point at slot 0's fields and advance by
+ * PF_SLOT_BYTES per slot (key == (char *)cell + 32, blend == (char *)cell +
+ * 48 or NULL for a table without temporal values, whose records keep the
+ * space). */
+#define PF_SLOT_BYTES 64
 typedef struct pf_table {
-    pf_cell *cell;       /* cells (fingerprint, count, fixed-point sums) */
-    uint64_t *key;       /* full key of each occupied slot, written by the slot's claimer */
-    float *blend;        /* 4 floats per slot: temporal value rgb + count; may be NULL */
+    pf_cell *cell;       /* cells (fingerprint, count, fixed-point sums), stride PF_SLOT_BYTES */
+    uint64_t *key;       /* full key of each occupied slot, written by the slot's claimer; stride PF_SLOT_BYTES */
+    float *blend;        /* 4 floats per slot: temporal value rgb + count; stride PF_SLOT_BYTES; may be NULL */
     uint32_t *occ;       /* occupancy bitmap, 2^log2_slots / 32 words (bit s%32 of word s/32) */
     uint64_t *stats;     /* PF_STATS_LEN counters */
     uint32_t log2_slots; /* 4 .. 30 */

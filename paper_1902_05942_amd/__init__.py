@@ -10,7 +10,7 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from ._lib import (STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_USED, SUMS_FIXED64,  # noqa
+from ._lib import (SLOT_BYTES, STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_USED, SUMS_FIXED64,  # noqa
                    SUMS_FLOAT32, V_INVALID, V_KEYRANGE,
                    V_OVERFLOW, V_RADRANGE, Mlp, PfError, Table, build_keys, clear, geometry, insert_accumulate,
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,

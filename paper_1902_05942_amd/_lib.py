@@ -21,6 +21,7 @@ V_INVALID, V_KEYRANGE, V_OVERFLOW, V_RADRANGE = 1, 2, 4, 8
 STAT_USED, STAT_DISP, STAT_OVERFLOW, STAT_TEMPORAL_HIT, STAT_HIST, STATS_LEN = 0, 1, 2, 3, 8, 128
 SUMS_FIXED64, SUMS_FLOAT32 = 0, 1
 CELL_BYTES = 32
+SLOT_BYTES = 64  # a slot record: cell at 0, key at 32, temporal value at 48
 
 
 class PfError(RuntimeError):
@@ -186,18 +187,19 @@ class Table:
         off = addr - base
         return self.arena[off:off + nbytes].view(dtype)
 
+    def _records(self, dtype, per):
+        S = 1 << self.log2_slots
+        return self._view(self.t.cell, S * SLOT_BYTES, dtype).view(S, per)
+
     def cells(self) -> torch.Tensor:
         """[2^m, 8] int32 view: fp, count, sum0 lo/hi, sum1 lo/hi, sum2 lo/hi."""
-        S = 1 << self.log2_slots
-        return self._view(self.t.cell, S * CELL_BYTES, torch.int32).view(S, 8)
+        return self._records(torch.int32, SLOT_BYTES // 4)[:, :CELL_BYTES // 4]
 
     def keys(self) -> torch.Tensor:
-        S = 1 << self.log2_slots
-        return self._view(self.t.key, S * 8, torch.int64)
+        return self._records(torch.int64, SLOT_BYTES // 8)[:, 4]
 
     def blend(self) -> torch.Tensor:
-        S = 1 << self.log2_slots
-        return self._view(self.t.blend, S * 16, torch.float32).view(S, 4)
+        return self._records(torch.float32, SLOT_BYTES // 4)[:, 12:16]
 
     def occupancy(self) -> torch.Tensor:
         """Occupancy bitmap as int32 words (bit s % 32 of word s // 32)."""

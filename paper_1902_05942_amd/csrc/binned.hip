@@ -101,13 +101,13 @@ Plan make_plan(uint32_t n, uint32_t log2_slots) {
 // slot s onwards.
 __device__ __forceinline__ uint32_t claim_next(const Tab &t, uint64_t key, uint32_t f, uint32_t s, uint32_t d0) {
     for (uint32_t d = d0; d < t.max_probe; ++d) {
-        uint32_t *pfp = &t.cell[s].fp;
+        uint32_t *pfp = &t.cell_at(s).fp;
         uint32_t cur = load_fp_probe(pfp);
         if (cur == 0) {
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
-                t.key[s] = key;
+                t.key_at(s) = key;
                 return s;
             }
             cur = expected;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             if (gk[v] != kEmpty) {
                 fs[v] = home_of(gk[v], t.mask);
                 ff[v] = fingerprint_of(gk[v]);
-                fcur[v] = load_fp_probe(&t.cell[fs[v]].fp);
+                fcur[v] = load_fp_probe(&t.cell_at(fs[v]).fp);
             }
         }
         bool won[kFlush];
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             won[v] = false;
             if (gk[v] != kEmpty && fcur[v] == 0) {
                 uint32_t expected = 0;
-                won[v] = __hip_atomic_compare_exchange_strong(&t.cell[fs[v]].fp, &expected, ff[v], __ATOMIC_RELAXED,
+                won[v] = __hip_atomic_compare_exchange_strong(&t.cell_at(fs[v]).fp, &expected, ff[v], __ATOMIC_RELAXED,
                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 fcur[v] = won[v] ? ff[v] : expected;
             }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             const uint32_t j = v * kT + threadIdx.x;
             uint32_t s = kNoSlot;
             if (gk[v] != kEmpty) {
-                if (won[v]) t.key[fs[v]] = gk[v];
+                if (won[v]) t.key_at(fs[v]) = gk[v];
                 // the home slot holds another key: probe on from the next
                 s = fcur[v] == ff[v] ? fs[v] : claim_next(t, gk[v], ff[v], (fs[v] + 1) & t.mask, 1);
                 if (s == kNoSlot) atomicAdd(&misc[1], lcnt[j]);
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
     }
     __syncthreads();
     // the cells of a thread's slots are all loaded before any is updated
-    uint4 *cells = reinterpret_cast<uint4 *>(t.cell + base);
+    uint4 *cells = t.words_at(base);  // 4 sixteen-byte words per slot record
     for (uint32_t kb = 0; kb < bin_slots; kb += kBatch * kReduceThreads) {
         uint32_t c[kBatch];
         uint4 lo[kBatch], hi[kBatch];
@@ -500,8 +500,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
             const uint32_t k = kb + u * kReduceThreads + threadIdx.x;
             c[u] = k < bin_slots ? cnt[k] : 0u;
             if (c[u]) {
-                lo[u] = cells[2 * k];
-                hi[u] = cells[2 * k + 1];
+                lo[u] = cells[4 * k];
+                hi[u] = cells[4 * k + 1];
             }
         }
 #pragma unroll
@@ -511,8 +511,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
                 const uint64_t s0 = ((uint64_t)lo[u].z | (uint64_t)lo[u].w << 32) + sum0[k];
                 const uint64_t s1 = ((uint64_t)hi[u].x | (uint64_t)hi[u].y << 32) + sum1[k];
                 const uint64_t s2 = ((uint64_t)hi[u].z | (uint64_t)hi[u].w << 32) + sum2[k];
-                cells[2 * k] = make_uint4(lo[u].x, lo[u].y + c[u], (uint32_t)s0, (uint32_t)(s0 >> 32));
-                cells[2 * k + 1] = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
+                cells[4 * k] = make_uint4(lo[u].x, lo[u].y + c[u], (uint32_t)s0, (uint32_t)(s0 >> 32));
+                cells[4 * k + 1] = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
             }
             // occupancy: a wavefront's 64 consecutive slots are two bitmap
             // words of this bin (bins hold >= 32 slots, or the whole table)

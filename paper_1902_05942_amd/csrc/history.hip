@@ -39,7 +39,6 @@ __device__ __forceinline__ uint32_t history_slot(const Hist &h, uint64_t key) {
 template <bool kIntegrate>
 __global__ __launch_bounds__(kBlock) void history_blend_kernel(Tab cur, Hist h, float alpha, float beta,
                                                                uint32_t cap) {
-    const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
     const uint32_t nparts = cur.nwords() * 4;
     const uint32_t stride = gridDim.x * kBlock;
     uint32_t hits = 0;
@@ -48,8 +47,9 @@ __global__ __launch_bounds__(kBlock) void history_blend_kernel(Tab cur, Hist h, 
         while (w) {
             const uint32_t s = (q >> 2) * 32 + __builtin_ctz(w);
             w &= w - 1;
-            const uint4 lo = cells[2 * s], hi = cells[2 * s + 1];
-            const uint64_t key = cur.key[s];
+            const uint4 *w4 = cur.words_at(s);  // cell and key in one record
+            const uint4 lo = w4[0], hi = w4[1], kw = w4[2];
+            const uint64_t key = (uint64_t)kw.x | (uint64_t)kw.y << 32;
             pf_cell c;
             c.fp = lo.x;
             c.count = lo.y;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void history_blend_kernel(Tab cur, Hist h, 
                 }
                 ++hits;
             }
-            cur.blend[s] = make_float4(v[0], v[1], v[2], (float)keep);
+            cur.blend_at(s) = make_float4(v[0], v[1], v[2], (float)keep);
         }
     }
     __shared__ uint32_t s_hits;
@@ -115,8 +115,8 @@ __global__ __launch_bounds__(kBlock) void history_offer_kernel(Tab cur, Hist h, 
         while (w) {
             const uint32_t s = (q >> 2) * 32 + __builtin_ctz(w);
             w &= w - 1;
-            const uint64_t key = cur.key[s];
-            const float4 v = cur.blend[s];
+            const uint64_t key = cur.key_at(s);
+            const float4 v = cur.blend_at(s);
             const uint64_t mine = history_word(key, 0, (uint32_t)v.w);
             const uint32_t hs = history_slot(h, key);
             if constexpr (!kOwn) {

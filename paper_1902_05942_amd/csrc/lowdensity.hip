@@ -42,7 +42,7 @@ __device__ __forceinline__ bool occupied(const Tab &t, uint32_t s) { return (t.o
 
 __device__ __forceinline__ void add_cell(const Tab &t, uint32_t s, uint32_t &n, uint64_t &a0, uint64_t &a1,
                                          uint64_t &a2) {
-    const uint4 *c = reinterpret_cast<const uint4 *>(t.cell + s);
+    const uint4 *c = t.words_at(s);
     const uint4 lo = c[0], hi = c[1];
     n += lo.y;
     a0 += (uint64_t)lo.z | (uint64_t)lo.w << 32;
@@ -52,7 +52,7 @@ __device__ __forceinline__ void add_cell(const Tab &t, uint32_t s, uint32_t &n, 
 
 __device__ __forceinline__ void store_pooled(const Tab &t, uint32_t s, uint32_t n, uint64_t a0, uint64_t a1,
                                              uint64_t a2) {
-    float *v = reinterpret_cast<float *>(t.blend + s);
+    float *v = reinterpret_cast<float *>(&t.blend_at(s));
     v[0] = cell_average((int64_t)a0, n, t.frac_bits);
     v[1] = cell_average((int64_t)a1, n, t.frac_bits);
     v[2] = cell_average((int64_t)a2, n, t.frac_bits);
@@ -91,9 +91,9 @@ __device__ __forceinline__ void search_cube(const Tab &t, uint32_t s, uint64_t K
         uint32_t cur[kCubePer];
         uint64_t kk[kCubePer];
 #pragma unroll
-        for (uint32_t u = 0; u < kCubePer; ++u) cur[u] = act[u] ? t.cell[p[u]].fp : 0u;
+        for (uint32_t u = 0; u < kCubePer; ++u) cur[u] = act[u] ? t.cell_at(p[u]).fp : 0u;
 #pragma unroll
-        for (uint32_t u = 0; u < kCubePer; ++u) kk[u] = (act[u] && cur[u] == f[u]) ? t.key[p[u]] : 0ull;
+        for (uint32_t u = 0; u < kCubePer; ++u) kk[u] = (act[u] && cur[u] == f[u]) ? t.key_at(p[u]) : 0ull;
 #pragma unroll
         for (uint32_t u = 0; u < kCubePer; ++u) {
             if (!act[u]) continue;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void search_normals(const Tab &t, uint64_t K, uint32_
         while (done < run) {
             const uint32_t m = min(run - done, 4u);
 #pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) kk[u] = u < m ? t.key[(p + done + u) & t.mask] : 0ull;
+            for (uint32_t u = 0; u < 4; ++u) kk[u] = u < m ? t.key_at((p + done + u) & t.mask) : 0ull;
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
                 if (u >= m) continue;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLdThreads) void low_density_kernel(Tab t, uint32_t
             const uint32_t w = (t.occ[j] >> b0) & 0xffu;
             uint32_t cnt[8];
 #pragma unroll
-            for (uint32_t b = 0; b < 8; ++b) cnt[b] = ((w >> b) & 1u) ? t.cell[j * 32 + b0 + b].count : 0u;
+            for (uint32_t b = 0; b < 8; ++b) cnt[b] = ((w >> b) & 1u) ? t.cell_at(j * 32 + b0 + b).count : 0u;
 #pragma unroll
             for (uint32_t b = 0; b < 8; ++b)
                 if (((w >> b) & 1u) && cnt[b] < below) list[atomicAdd(&nlist, 1u)] = j * 32 + b0 + b;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kLdThreads) void low_density_kernel(Tab t, uint32_t
                 const uint32_t s = list[q];
                 uint32_t n = 0;
                 uint64_t a0 = 0, a1 = 0, a2 = 0;
-                search_cube(t, s, t.key[s], lane, n, a0, a1, a2);
+                search_cube(t, s, t.key_at(s), lane, n, a0, a1, a2);
 #pragma unroll
                 for (uint32_t x = kCubeLanes / 2; x >= 1; x >>= 1) {
                     n += (uint32_t)__shfl_xor((int)n, (int)x);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kLdThreads) void low_density_kernel(Tab t, uint32_t
                 const uint32_t s = list[q];
                 uint32_t n = 0;
                 uint64_t a0 = 0, a1 = 0, a2 = 0;
-                search_normals(t, t.key[s], n, a0, a1, a2);
+                search_normals(t, t.key_at(s), n, a0, a1, a2);
                 store_pooled(t, s, n, a0, a1, a2);
             }
         }

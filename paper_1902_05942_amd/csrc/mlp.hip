@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
             L.xt[f * kBS + r0 + lr] = val;
         }
         if (lg == 0) {
-            const pf_cell c = A.t.cell[A.slot[v]];
+            const pf_cell c = A.t.cell_at(A.slot[v]);
             L.target[(r0 + lr) * 4 + 0] = A.t.average(c, 0);
             L.target[(r0 + lr) * 4 + 1] = A.t.average(c, 1);
             L.target[(r0 + lr) * 4 + 2] = A.t.average(c, 2);

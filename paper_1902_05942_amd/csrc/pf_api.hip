@@ -22,8 +22,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 pf_status check_table(const pf_table *t) {
     if (!t || !t->cell || !t->key || !t->occ || !t->stats) return PF_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(t->cell) % 32) || !aligned(t->key) || !aligned(t->occ) ||
-        !aligned(t->stats) || (t->blend && (reinterpret_cast<uintptr_t>(t->blend) % 16)))
+    const char *base = reinterpret_cast<const char *>(t->cell);
+    if ((reinterpret_cast<uintptr_t>(t->cell) % PF_SLOT_BYTES) || reinterpret_cast<const char *>(t->key) != base + 32 ||
+        (t->blend && reinterpret_cast<const char *>(t->blend) != base + 48) || !aligned(t->occ) || !aligned(t->stats))
         return PF_EINVAL;
     if (t->log2_slots < 4 || t->log2_slots > 30) return PF_ERANGE;
     if (t->max_probe < 1 || (uint64_t)t->max_probe > (1ull << t->log2_slots)) return PF_ERANGE;
@@ -34,9 +35,7 @@ pf_status check_table(const pf_table *t) {
 
 Tab to_tab(const pf_table *t) {
     Tab k;
-    k.cell = t->cell;
-    k.key = t->key;
-    k.blend = reinterpret_cast<float4 *>(t->blend);
+    k.rec = reinterpret_cast<unsigned char *>(t->cell);
     k.occ = t->occ;
     k.stats = reinterpret_cast<unsigned long long *>(t->stats);
     k.mask = (uint32_t)((1ull << t->log2_slots) - 1);
@@ -65,9 +64,8 @@ size_t pf_table_bytes(uint32_t log2_slots, int with_blend) {
     if (log2_slots < 4 || log2_slots > 30) return 0;
     const size_t S = (size_t)1 << log2_slots;
     size_t b = 256;                                      // alignment slack of the arena base
-    b += align_up(S * sizeof(pf_cell), 256);             // cells
-    b += align_up(S * sizeof(uint64_t), 256);            // keys
-    b += with_blend ? align_up(S * 4 * sizeof(float), 256) : 0;
+    b += align_up(S * PF_SLOT_BYTES, 256);               // slot records: cell, key, temporal value
+    (void)with_blend;                                    // the records always keep the value's space
     b += align_up((S + 31) / 32 * sizeof(uint32_t), 256); // occupancy bitmap
     b += align_up(PF_STATS_LEN * sizeof(uint64_t), 256);  // statistics
     return b;
@@ -83,13 +81,9 @@ pf_status pf_table_carve(void *arena, uint32_t log2_slots, int with_blend, uint3
     uintptr_t p = align_up(reinterpret_cast<uintptr_t>(arena), 256);
     memset(t, 0, sizeof(*t));
     t->cell = reinterpret_cast<pf_cell *>(p);
-    p += align_up(S * sizeof(pf_cell), 256);
-    t->key = reinterpret_cast<uint64_t *>(p);
-    p += align_up(S * sizeof(uint64_t), 256);
-    if (with_blend) {
-        t->blend = reinterpret_cast<float *>(p);
-        p += align_up(S * 4 * sizeof(float), 256);
-    }
+    t->key = reinterpret_cast<uint64_t *>(p + 32);
+    t->blend = with_blend ? reinterpret_cast<float *>(p + 48) : nullptr;
+    p += align_up(S * PF_SLOT_BYTES, 256);
     t->occ = reinterpret_cast<uint32_t *>(p);
     p += align_up((S + 31) / 32 * sizeof(uint32_t), 256);
     t->stats = reinterpret_cast<uint64_t *>(p);

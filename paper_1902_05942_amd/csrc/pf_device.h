@@ -109,16 +109,30 @@ __device__ __forceinline__ float *float_sum(pf_cell *c, int k) { return reinterp
 __device__ __forceinline__ float float_sum_value(int64_t word) { return __uint_as_float((uint32_t)(uint64_t)word); }
 
 // Table handle passed to kernels by value.
+static_assert(sizeof(pf_cell) == 32 && PF_SLOT_BYTES == 64, "slot record layout");
+
 struct Tab {
-    pf_cell *cell;
-    uint64_t *key;
-    float4 *blend;
+    unsigned char *rec;  // slot records of PF_SLOT_BYTES: cell at 0, key at 32, temporal value at 48
     uint32_t *occ;
     unsigned long long *stats;
     uint32_t mask;
     uint32_t max_probe;
     int32_t frac_bits;
     uint32_t fsum;  // 1: binary32 sums in the low word of each sum (PF_SUMS_FLOAT32)
+
+    __device__ __forceinline__ pf_cell &cell_at(uint32_t s) const {
+        return *reinterpret_cast<pf_cell *>(rec + (size_t)s * PF_SLOT_BYTES);
+    }
+    __device__ __forceinline__ uint64_t &key_at(uint32_t s) const {
+        return *reinterpret_cast<uint64_t *>(rec + (size_t)s * PF_SLOT_BYTES + 32);
+    }
+    __device__ __forceinline__ float4 &blend_at(uint32_t s) const {
+        return *reinterpret_cast<float4 *>(rec + (size_t)s * PF_SLOT_BYTES + 48);
+    }
+    // slot s as 16-byte words: [0], [1] the cell, [2] the key (and padding), [3] the temporal value
+    __device__ __forceinline__ uint4 *words_at(uint32_t s) const {
+        return reinterpret_cast<uint4 *>(rec + (size_t)s * PF_SLOT_BYTES);
+    }
 
     // occupancy bitmap words (at least one; tables have >= 16 slots)
     __host__ __device__ __forceinline__ uint32_t nwords() const { return (uint32_t)(((uint64_t)mask + 32) >> 5); }

@@ -98,7 +98,7 @@ __device__ __forceinline__ uint8_t float_contribution(float c0, float c1, float 
 
 // One binary32 atomic add per component (the hardware's global_atomic_add_f32).
 __device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, float v0, float v1, float v2) {
-    pf_cell *c = t.cell + slot;
+    pf_cell *c = &t.cell_at(slot);
     add_u32(&c->count, cnt);
     unsafeAtomicAdd(float_sum(c, 0), v0);
     unsafeAtomicAdd(float_sum(c, 1), v1);
@@ -107,7 +107,7 @@ __device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t
 
 __device__ __forceinline__ void accumulate(const Tab &t, uint32_t slot, uint32_t cnt, int64_t q0, int64_t q1,
                                            int64_t q2) {
-    pf_cell *c = t.cell + slot;
+    pf_cell *c = &t.cell_at(slot);
     add_u32(&c->count, cnt);
     add_u64(reinterpret_cast<unsigned long long *>(&c->sum[0]), (unsigned long long)q0);
     add_u64(reinterpret_cast<unsigned long long *>(&c->sum[1]), (unsigned long long)q1);
@@ -122,13 +122,13 @@ __device__ __forceinline__ uint32_t find_or_claim(const Tab &t, uint64_t key) {
     const uint32_t f = fingerprint_of(key);
     uint32_t s = home_of(key, t.mask);
     for (uint32_t d = 0; d < t.max_probe; ++d) {
-        uint32_t *pfp = &t.cell[s].fp;
+        uint32_t *pfp = &t.cell_at(s).fp;
         uint32_t cur = load_fp_probe(pfp);
         if (cur == 0) {
             uint32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(pfp, &expected, f, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
-                t.key[s] = key;
+                t.key_at(s) = key;
                 __hip_atomic_fetch_or(&t.occ[s >> 5], 1u << (s & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return s;
             }
@@ -145,7 +145,7 @@ __device__ __forceinline__ uint32_t find_slot(const Tab &t, uint64_t key) {
     const uint32_t f = fingerprint_of(key);
     uint32_t s = home_of(key, t.mask);
     for (uint32_t d = 0; d < t.max_probe; ++d) {
-        const uint32_t cur = t.cell[s].fp;
+        const uint32_t cur = t.cell_at(s).fp;
         if (cur == f) return s;
         if (cur == 0) return kNoSlot;
         s = (s + 1) & t.mask;
@@ -157,9 +157,9 @@ __device__ __forceinline__ uint32_t find_slot(const Tab &t, uint64_t key) {
 __device__ __forceinline__ uint32_t find_exact(const Tab &t, uint64_t key, uint32_t f) {
     uint32_t s = home_of(key, t.mask);
     for (uint32_t d = 0; d < t.max_probe; ++d) {
-        const uint32_t cur = t.cell[s].fp;
+        const uint32_t cur = t.cell_at(s).fp;
         if (cur == 0) return kNoSlot;
-        if (cur == f && t.key[s] == key) return s;
+        if (cur == f && t.key_at(s) == key) return s;
         s = (s + 1) & t.mask;
     }
     return kNoSlot;
@@ -274,7 +274,7 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
     if (ok[0]) {
         const uint32_t s = find_exact(prev, cand[0], fingerprint_of(cand[0]));
         if (s != kNoSlot) {
-            const float4 v = prev.blend[s];
+            const float4 v = prev.blend_at(s);
             const uint32_t n = (uint32_t)v.w / 8;
             if (!kIntegrate || n >= 1) {
                 old = make_float4(v.x, v.y, v.z, (float)n);
@@ -288,7 +288,7 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
         if (!ok[1 + d]) continue;
         const uint32_t s = find_exact(prev, cand[1 + d], fingerprint_of(cand[1 + d]));
         if (s == kNoSlot) continue;
-        const float4 v = prev.blend[s];
+        const float4 v = prev.blend_at(s);
         const uint32_t w = (uint32_t)v.w;
         n += w;
         a0 += (double)w * (double)v.x;
@@ -315,7 +315,6 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
 template <bool kHasPrev, bool kIntegrate, int kTB = 4, bool kLevels = false>  // kTB: cells looked up together
 __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &prev, uint32_t j, float alpha,
                                                   float beta, uint32_t cap, uint32_t part = 0xffffffffu) {
-    const uint4 *cells = reinterpret_cast<const uint4 *>(cur.cell);
     uint32_t hits = 0;
     uint32_t w = cur.occ[j] & part;  // the slots of the word this lane takes
     while (w) {
@@ -332,9 +331,9 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
 #pragma unroll
         for (int k = 0; k < kTB; ++k) {
             if (has[k]) {
-                lo[k] = cells[2 * s[k]];
-                hi[k] = cells[2 * s[k] + 1];
-                if constexpr (kHasPrev) key[k] = cur.key[s[k]];
+                lo[k] = cur.words_at(s[k])[0];
+                hi[k] = cur.words_at(s[k])[1];
+                if constexpr (kHasPrev) key[k] = cur.key_at(s[k]);
             }
         }
         float v[kTB][3];
@@ -372,11 +371,11 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
                 uint32_t pf[kTB];
                 uint64_t pk[kTB];
 #pragma unroll
-                for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell[p[k]].fp : 0u;
+                for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell_at(p[k]).fp : 0u;
 #pragma unroll
                 for (int k = 0; k < kTB; ++k) {
                     pk[k] = 0;
-                    if (active[k] && pf[k] == lo[k].x) pk[k] = prev.key[p[k]];
+                    if (active[k] && pf[k] == lo[k].x) pk[k] = prev.key_at(p[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < kTB; ++k) {
@@ -395,7 +394,7 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
             bool use[kTB];
 #pragma unroll
             for (int k = 0; k < kTB; ++k) {
-                if (found[k]) old[k] = prev.blend[p[k]];
+                if (found[k]) old[k] = prev.blend_at(p[k]);
                 use[k] = found[k];
             }
             if constexpr (kLevels) {
@@ -424,7 +423,7 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
         }
 #pragma unroll
         for (int k = 0; k < kTB; ++k)
-            if (has[k]) cur.blend[s[k]] = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
+            if (has[k]) cur.blend_at(s[k]) = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
     }
     return hits;
 }
@@ -435,8 +434,8 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
 __device__ __forceinline__ float4 lookup_value(const Tab &t, uint32_t slot, uint32_t i, const float *r, const float *g,
                                                const float *b, bool blend) {
     if (slot == kNoSlot) return make_float4(r[i], g[i], b[i], 0.0f);
-    if (blend) return t.blend[slot];
-    const pf_cell c = t.cell[slot];
+    if (blend) return t.blend_at(slot);
+    const pf_cell c = t.cell_at(slot);
     return make_float4(t.average(c, 0), t.average(c, 1), t.average(c, 2), (float)c.count);
 }
 
@@ -458,13 +457,13 @@ __device__ __forceinline__ void query_vertex(const Tab &t, uint32_t slot, uint32
     float a0, a1, a2;
     uint32_t cnt;
     if constexpr (kBlend) {
-        const float4 v = t.blend[slot];
+        const float4 v = t.blend_at(slot);
         a0 = v.x;
         a1 = v.y;
         a2 = v.z;
         cnt = (uint32_t)v.w;
     } else {
-        const pf_cell c = t.cell[slot];
+        const pf_cell c = t.cell_at(slot);
         cnt = c.count;
         a0 = t.average(c, 0);
         a1 = t.average(c, 1);

@@ -25,10 +25,10 @@ __global__ __launch_bounds__(kBlock) void table_init_kernel(uint4 *__restrict__ 
 static_assert(PF_STATS_LEN <= kBlock, "one block zeroes the statistics");
 
 hipError_t launch_table_init(const Tab &t, hipStream_t st) {
-    const uint64_t n16 = ((uint64_t)t.mask + 1) * sizeof(pf_cell) / sizeof(uint4);
+    const uint64_t n16 = ((uint64_t)t.mask + 1) * PF_SLOT_BYTES / sizeof(uint4);
     uint64_t blocks = (n16 + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
-    table_init_kernel<<<(uint32_t)blocks, kBlock, 0, st>>>(reinterpret_cast<uint4 *>(t.cell), n16, t.occ,
+    table_init_kernel<<<(uint32_t)blocks, kBlock, 0, st>>>(reinterpret_cast<uint4 *>(t.rec), n16, t.occ,
                                                            t.nwords(), t.stats);
     return hipGetLastError();
 }
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) {
         while (w) {
             const uint32_t b = __builtin_ctz(w);
             w &= w - 1;
-            uint4 *c = reinterpret_cast<uint4 *>(t.cell + (j * 32 + b));
+            uint4 *c = t.words_at(j * 32 + b);
             c[0] = make_uint4(0, 0, 0, 0);
             c[1] = make_uint4(0, 0, 0, 0);
         }
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(Tab t) {
         while (w) {
             const uint32_t s = j * 32 + __builtin_ctz(w);
             w &= w - 1;
-            const uint32_t d = (s - home_of(t.key[s], t.mask)) & t.mask;
+            const uint32_t d = (s - home_of(t.key_at(s), t.mask)) & t.mask;
             atomicAdd(&s_disp, (unsigned long long)d);
             atomicAdd(&s_hist[d < 64 ? d : 64], 1ull);
         }

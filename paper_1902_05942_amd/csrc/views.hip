@@ -37,9 +37,7 @@ __device__ __forceinline__ uint32_t poll(uint32_t *p) {
 
 __device__ __forceinline__ Tab to_tab(const pf_table &t) {
     Tab k;
-    k.cell = t.cell;
-    k.key = t.key;
-    k.blend = reinterpret_cast<float4 *>(t.blend);
+    k.rec = reinterpret_cast<unsigned char *>(t.cell);
     k.occ = t.occ;
     k.stats = reinterpret_cast<unsigned long long *>(t.stats);
     k.mask = (uint32_t)((1ull << t.log2_slots) - 1);
@@ -193,7 +191,7 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
             while (w) {
                 const uint32_t b = __builtin_ctz(w);
                 w &= w - 1;
-                uint4 *c = reinterpret_cast<uint4 *>(t.cell + (j * 32 + b));
+                uint4 *c = t.words_at(j * 32 + b);
                 c[0] = make_uint4(0, 0, 0, 0);
                 c[1] = make_uint4(0, 0, 0, 0);
             }

@@ -43,13 +43,16 @@ def test_table_sizing_and_carving(pf):
     assert L.pf_table_bytes(3, 1) == 0 and L.pf_table_bytes(31, 1) == 0
     b22 = L.pf_table_bytes(22, 1)
     S = 1 << 22
-    assert b22 >= S * (32 + 8 + 16) + S // 8
-    assert L.pf_table_bytes(22, 0) == b22 - S * 16
+    assert b22 >= S * 64 + S // 8                # 64-byte slot records and the bitmap
+    assert L.pf_table_bytes(22, 0) == b22         # the records keep the temporal value's space
     t = pf._lib.pf_table()
     base = 0x7F0000000010                       # never dereferenced: carving is arithmetic
     assert L.pf_table_carve(ctypes.c_void_p(base), 22, 1, 64, 24, ctypes.byref(t)) == 0
     assert t.cell % 256 == 0 and t.cell >= base and t.stats + 128 * 8 <= base + b22
-    assert t.key - t.cell == S * 32 and t.blend - t.key == S * 8
+    assert t.key - t.cell == 32 and t.blend - t.cell == 48   # fields of slot 0, stride 64
+    assert pf._lib.SLOT_BYTES == 64
+    t0 = pf._lib.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(base), 22, 0, 64, 24, ctypes.byref(t0)) == 0 and not t0.blend
     for bad in [(3, 64, 24), (31, 64, 24), (10, 0, 24), (10, 1025, 24), (10, 64, 7), (10, 64, 41)]:
         assert L.pf_table_carve(ctypes.c_void_p(base), bad[0], 1, bad[1], bad[2], ctypes.byref(t)) == pf._lib.PF_ERANGE
     assert L.pf_table_carve(None, 10, 1, 64, 24, ctypes.byref(t)) == pf._lib.PF_EINVAL

@@ -282,6 +282,10 @@ def main():
                           "insert": a.insert, "steps": a.steps}), flush=True)
         return
 
+    # the random-access denominators, measured at the table's footprint right
+    # after the timed frames, in the state the frames ran in
+    ra = random_access(dev, (1 << view.log2_slots) * pf.SLOT_BYTES)
+
     # quality: RMSE against the noise-free radiance over valid vertices (evaluation only)
     def rmse(x, f):
         v = f["valid"].bool()
@@ -360,7 +364,6 @@ def main():
     # random-access roofline of the headline (insert + query): per valid vertex
     # the method makes a probe and a cell update when inserting and a probe and
     # a cell read when looking up, plus one claim per cell (4V + C touches)
-    ra = random_access(dev, (1 << view.log2_slots) * pf.SLOT_BYTES)
     touches = 4 * nv + cells
     t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
     t_iq = (t_ins + per.get("query_average", per.get("query_multilevel", 0.0))) * 1e-6

@@ -140,7 +140,7 @@ pf_status pf_table_init(const pf_table *t, void *stream);
 
 /* Empties a table for the next frame: zeroes the cells whose occupancy bit
  * is set (work proportional to the occupancy bitmap, 2^log2_slots / 8
- * bytes, plus the cells of the last frame, not to the cell array), the
+ * bytes, plus the cells of the last frame, not to the table size), the
  * bitmap and the statistics.  The table must have been initialised and only
  * modified through this library since. */
 pf_status pf_clear(const pf_table *t, void *stream);
@@ -272,8 +272,8 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
  * and c = c_new when the key is absent or prev is NULL.  Cells of prev that
  * do not occur in cur are dropped (prev holds the previous frame only).
  * The lookup with use_blend returns c and N as the vertex's count.
- * cur and prev must have the same log2_slots and both carry blend arrays.
- * Errors: PF_EINVAL (no blend array), PF_ERANGE (alpha_old outside [0, 1]
+ * cur and prev must have the same log2_slots and both carry temporal values (blend not NULL).
+ * Errors: PF_EINVAL (blend NULL), PF_ERANGE (alpha_old outside [0, 1]
  * in mode 0, unknown mode, differing sizes). */
 pf_status pf_temporal_update(const pf_table *cur, const pf_table *prev, float alpha_old, int mode,
                              void *stream);
@@ -347,7 +347,7 @@ pf_status pf_history_init(const pf_history *h, void *stream);
  * their age), and the cells of cur compete for their slots with age 0 and
  * their stored count: the winner of a slot writes key, value (cur->blend)
  * and stamp.  The table's temporal-hit statistic counts the cells found.
- * Errors: PF_EINVAL (no blend array, NULL history), PF_ERANGE (alpha_old,
+ * Errors: PF_EINVAL (blend NULL, NULL history), PF_ERANGE (alpha_old,
  * mode, max_samples as in pf_temporal_update / pf_temporal_integrate). */
 pf_status pf_temporal_history(const pf_table *cur, const pf_history *h, float alpha_old, int mode,
                               uint32_t max_samples, uint32_t frame, void *stream);
@@ -373,7 +373,7 @@ pf_status pf_temporal_history(const pf_table *cur, const pf_history *h, float al
  * input within PF_V_RADRANGE reaches).  The stored count (blend's fourth
  * float) is kept, so the lookup still reports the cell's own count.
  * below <= 1 changes nothing.  Fixed-point tables only.
- * Errors: PF_EINVAL (no blend array, binary32 sums), PF_ERANGE (mode). */
+ * Errors: PF_EINVAL (blend NULL, binary32 sums), PF_ERANGE (mode). */
 #define PF_LD_NEIGHBOURS 0
 #define PF_LD_NORMALS 1
 pf_status pf_low_density_fallback(const pf_table *t, uint32_t below, int mode, void *stream);
@@ -545,7 +545,7 @@ typedef struct pf_view {
     pf_key_params kp;
     uint32_t n;               /* vertices (at most PF_MAX_VERTICES) */
     float alpha_old;          /* moving-average weight of the previous value */
-    int32_t temporal;         /* 1: lookup returns the moving average (cur needs a blend array) */
+    int32_t temporal;         /* 1: lookup returns the moving average (cur needs temporal values: blend not NULL) */
     uint32_t reserved;
 } pf_view;
 

@@ -1,9 +1,11 @@
 """Benchmark: hashed path space filtering of the 1080p x3 workload on one GPU.
 
 One step filters one frame of the orbiting camera (1920x1080 pixels, 3 path
-vertices per pixel, 6,220,800 vertex slots): clear the current table, build
-keys, insert-accumulate, temporal moving average against the previous
-frame's table, look up.  Sixteen frames are generated on the GPU before
+vertices per pixel, 6,220,800 vertex slots): build keys and insert-accumulate
+into the current table, temporal moving average against the previous
+frame's table, look up, emptying the previous frame's table in the lookup's
+launch for the next frame (--separate-clear: a clear launch of its own at
+the start of each frame instead).  Sixteen frames are generated on the GPU before
 timing (inputs resident in HBM) and steps cycle through them.
 
 Prints one JSON line.  `value` is vertices filtered per second (valid
@@ -65,6 +67,8 @@ def parse():
                    help="the temporal pass also searches a changed cell's region one level coarser and finer")
     p.add_argument("--resolve", action="store_true",
                    help="add the pixel resolve (value times a synthetic throughput, summed per pixel) as a stage")
+    p.add_argument("--separate-clear", action="store_true",
+                   help="clear each frame's table in its own launch instead of in the previous frame's lookup")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="only run an elementwise copy of this many MiB 4 times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -177,12 +181,18 @@ def main():
         ws_c = flt.ws if flt.ws is not None else torch.empty(pf.insert_workspace_bytes(n, view.log2_slots),
                                                              dtype=torch.uint8, device=dev)
 
+    clear_in_lookup = not multilevel and not a.separate_clear
+
     def stages(k):
         """(name, call) of one frame's steps, in order"""
         f = frames[k % len(frames)]
         key, vflags, slot = flt.key[:n], flt.vflags[:n], flt.slot[:n]
         cur = flt.cur
-        st = [("clear", lambda: pf.clear(cur))]
+        # the plain lookup empties the other table in its launch (it was read
+        # for the last time by the temporal pass), so the next frame's table
+        # starts empty and no clear stage runs; the first frame's table is
+        # empty from its initialisation
+        st = [] if clear_in_lookup else [("clear", lambda: pf.clear(cur))]
         if fused:
             st.append(("build_keys_insert", lambda: pf.build_keys_insert_binned(
                 cur, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"], f["seed"], 0,
@@ -218,6 +228,11 @@ def main():
             st.append(("query_multilevel", lambda: pf.query_multilevel(
                 cur, cc, slot, slot_c, f["r"], f["g"], f["b"], vflags, vflags_c, multilevel[0], True, outs[0],
                 outs[1], outs[2], count if use_mlp else None)))
+        elif clear_in_lookup:
+            other = flt.tables[1]
+            st.append(("query_average_clear", lambda: pf.query_average_clear(
+                cur, key, slot, f["r"], f["g"], f["b"], vflags, True, outs[0], outs[1], outs[2], other,
+                count if use_mlp else None)))
         else:
             st.append(("query_average", lambda: pf.query_average(cur, key, slot, f["r"], f["g"], f["b"], vflags, True,
                                                                  outs[0], outs[1], outs[2],
@@ -348,6 +363,7 @@ def main():
         "insert_accumulate": n * (1 + 4) + nv * (8 + 12 + 4 + 28),
         "temporal_update": cells * (32 + 8 + 4 + 8 + 16 + 16) + (1 << view.log2_slots) // 8,
         "query_average": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12,
+        "query_average_clear": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12 + cells * 32 + (1 << view.log2_slots) // 8,
         # fused: positions, normals, valid in; flags and slot out; contribution, probe, cell update per valid vertex
         "build_keys_insert": n * (6 * 4 + 1 + 1 + 4) + nv * (12 + 4 + 28),
     }
@@ -366,7 +382,8 @@ def main():
     # a cell read when looking up, plus one claim per cell (4V + C touches)
     touches = 4 * nv + cells
     t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
-    t_iq = (t_ins + per.get("query_average", per.get("query_multilevel", 0.0))) * 1e-6
+    t_q = per.get("query_average", per.get("query_average_clear", per.get("query_multilevel", 0.0)))
+    t_iq = (t_ins + t_q) * 1e-6   # with the fused clear, the lookup's time includes emptying the other table
     ra["insert_query_touches"] = int(touches)
     ra["achieved_G_touches_per_s"] = round(touches / t_iq / 1e9, 2)
     ra["frac_of_gather"] = round(touches / t_iq / 1e9 / ra["G_per_s"]["gather_32B"], 4)

@@ -259,6 +259,21 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
                            float *r_out, float *g_out, float *b_out, uint32_t *count_out,
                            void *stream);
 
+/* pf_query_average on t and pf_clear on another table `clear` in ONE launch:
+ * a renderer alternating two tables across frames empties the table of the
+ * frame before (read for the last time by the temporal pass) while it looks
+ * up the current one, so the next frame's insert needs no clear of its own.
+ * Results are those of the two calls.  `clear` must be another table whose
+ * slots do not overlap t's, initialised and only modified through this
+ * library; it is neither read nor written by the lookup.  Errors: those of
+ * the two calls; PF_EINVAL also when clear is NULL or its slots overlap t's.
+ * With n == 0 only the clear runs. */
+pf_status pf_query_average_clear(const pf_table *t, const uint64_t *key, const uint32_t *slot,
+                                 const float *r_in, const float *g_in, const float *b_in,
+                                 const uint8_t *vflags, uint64_t n, int use_blend,
+                                 float *r_out, float *g_out, float *b_out, uint32_t *count_out,
+                                 const pf_table *clear, void *stream);
+
 /* --------------------------------------------------------------- temporal */
 /* Two sets of averages (Section 3.4.1).  For every occupied cell of `cur`
  * (found through its occupancy bitmap), computes c_new = sum / count as in

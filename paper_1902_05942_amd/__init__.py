@@ -18,7 +18,8 @@ from ._lib import (SLOT_BYTES, STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORA
                    filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
-                   query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS)
+                   query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS,
+                   query_average_clear)
 
 
 class MlpFallback:
@@ -65,14 +66,17 @@ class FrameFilter:
     filter() runs one frame: clear the current table, build keys, insert,
     temporal blend against the previous frame's table, the low-density
     fallback when asked for, look up, then swap the tables.  Every step is
-    one library call on the current stream.
+    one library call on the current stream.  With two tables and the plain
+    lookup, clear_in_lookup empties the previous frame's table (read for the
+    last time by the temporal blend) in the lookup's launch
+    (pf_query_average_clear), so the next frame starts without a clear.
     """
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
                  max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None,
-                 history=None, across_levels: bool = False):
+                 history=None, across_levels: bool = False, clear_in_lookup: bool = True):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -109,6 +113,8 @@ class FrameFilter:
         self.slot = torch.empty(n_max, dtype=torch.int32, device=device)
         self.count = torch.empty(n_max, dtype=torch.int32, device=device)
         self.frames = 0
+        self.clear_in_lookup = clear_in_lookup
+        self._cur_clean = False  # the current table was emptied by the last frame's lookup
         self.mlp = mlp
         self.ws = None
         self.fused = fused  # keys built inside the binned insert (implies binned)
@@ -133,7 +139,9 @@ class FrameFilter:
         key, vflags, slot = self.key[:n], self.vflags[:n], self.slot[:n]
         cnt = self.count[:n] if (with_count or self.mlp is not None) else None
         cur = self.cur
-        clear(cur)
+        if not self._cur_clean:
+            clear(cur)
+        self._cur_clean = False
         if self.fused:  # the keys are only written when the learned fallback or the coarser level reads them
             want_key = self.mlp is not None or self.multilevel is not None
             build_keys_insert_binned(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b,
@@ -174,6 +182,11 @@ class FrameFilter:
         if self.multilevel is not None:
             query_multilevel(cur, self.coarse[0], slot, slot_c, r, g, b, vflags, vflags_c, self.multilevel[0],
                              use_blend, out[0], out[1], out[2], cnt)
+        elif self.temporal and self.clear_in_lookup:
+            # the other table becomes the current one after the swap below
+            query_average_clear(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2],
+                                self.tables[1], cnt)
+            self._cur_clean = True
         else:
             query_average(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2], cnt)
         if self.mlp is not None:

@@ -92,6 +92,7 @@ def _load():
         "pf_build_keys_insert_binned": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp, vp, vp,
                                                           vp, ctypes.c_size_t, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
+        "pf_query_average_clear": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, T, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_low_density_fallback": ([T, u32, i, vp], i),
@@ -133,7 +134,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
             "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
-            "pf_temporal_history", "pf_resolve_pixels")
+            "pf_temporal_history", "pf_resolve_pixels", "pf_query_average_clear")
 
 
 def _ptr(t):
@@ -265,6 +266,15 @@ def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_ou
     _check("pf_query_average", lib.pf_query_average(t.ref, _ptr(key), _ptr(slot), _ptr(r_in), _ptr(g_in),
                                                     _ptr(b_in), _ptr(vflags), n, int(bool(use_blend)), _ptr(r_out),
                                                     _ptr(g_out), _ptr(b_out), _ptr(count_out), _stream(stream)))
+
+
+def query_average_clear(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_out, g_out, b_out,
+                        clear: Table, count_out=None, stream=None):
+    """query_average on t and clear() of another table in one launch."""
+    n = vflags.numel()
+    _check("pf_query_average_clear", lib.pf_query_average_clear(
+        t.ref, _ptr(key), _ptr(slot), _ptr(r_in), _ptr(g_in), _ptr(b_in), _ptr(vflags), n, int(bool(use_blend)),
+        _ptr(r_out), _ptr(g_out), _ptr(b_out), _ptr(count_out), clear.ref, _stream(stream)))
 
 
 def temporal_update(cur: Table, prev, alpha_old: float, mode: int = 0, stream=None):

@@ -214,6 +214,32 @@ pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_
                                       r_out, g_out, b_out, count_out, (hipStream_t)stream));
 }
 
+pf_status pf_query_average_clear(const pf_table *t, const uint64_t *key, const uint32_t *slot, const float *r_in,
+                                 const float *g_in, const float *b_in, const uint8_t *vflags, uint64_t n,
+                                 int use_blend, float *r_out, float *g_out, float *b_out, uint32_t *count_out,
+                                 const pf_table *clear, void *stream) {
+    pf_status s = check_table(t);
+    if (s != PF_OK) return s;
+    if (!clear) return PF_EINVAL;
+    s = check_table(clear);
+    if (s != PF_OK) return s;
+    {  // the two tables' slot records must not overlap
+        const uintptr_t a0 = (uintptr_t)t->cell, a1 = a0 + ((uintptr_t)PF_SLOT_BYTES << t->log2_slots);
+        const uintptr_t c0 = (uintptr_t)clear->cell, c1 = c0 + ((uintptr_t)PF_SLOT_BYTES << clear->log2_slots);
+        if (a0 < c1 && c0 < a1) return PF_EINVAL;
+    }
+    if (n > kMaxN) return PF_EINVAL;
+    if (use_blend && !t->blend) return PF_EINVAL;
+    if (n == 0) return launched(pfk::launch_clear(to_tab(clear), (hipStream_t)stream));
+    if ((!key && !slot) || !r_in || !g_in || !b_in || !vflags || !r_out || !g_out || !b_out) return PF_EINVAL;
+    if ((key && !aligned(key)) || (slot && !aligned(slot)) || !aligned(r_in) || !aligned(g_in) || !aligned(b_in) ||
+        !aligned(r_out) || !aligned(g_out) || !aligned(b_out) || (count_out && !aligned(count_out)))
+        return PF_EINVAL;
+    return launched(pfk::launch_query_clear(to_tab(t), key, slot, r_in, g_in, b_in, vflags, (uint32_t)n,
+                                            use_blend != 0, r_out, g_out, b_out, count_out, to_tab(clear),
+                                            (hipStream_t)stream));
+}
+
 static pf_status temporal(const pf_table *cur, const pf_table *prev, float alpha_old, int mode, uint32_t cap,
                           void *stream) {
     pf_status s = check_table(cur);

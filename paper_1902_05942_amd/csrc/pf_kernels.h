@@ -34,6 +34,9 @@ hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, cons
 hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
                         const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
                         float *bo, uint32_t *count_out, hipStream_t st);
+hipError_t launch_query_clear(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
+                              const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
+                              float *bo, uint32_t *count_out, const Tab &clr, hipStream_t st);
 hipError_t launch_stats(const Tab &t, hipStream_t st);
 
 struct MlpArgs {

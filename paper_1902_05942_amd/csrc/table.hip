@@ -34,12 +34,13 @@ hipError_t launch_table_init(const Tab &t, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------- clear
-// Zeroes the cells whose occupancy bit is set and the bitmap words; block 0
-// zeroes the statistics (no kernel reads them here).
-__global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) {
+// Zeroes the cells whose occupancy bit is set and the bitmap words, as
+// workgroup `blk` of `nblk` taking every nblk-th range of bitmap words;
+// workgroup 0 zeroes the statistics (no kernel reads them here).
+__device__ __forceinline__ void clear_part(const Tab &t, uint32_t blk, uint32_t nblk) {
     const uint32_t nwords = t.nwords();
-    const uint32_t stride = gridDim.x * kBlock;
-    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nwords; j += stride) {
+    const uint32_t stride = nblk * kBlock;
+    for (uint32_t j = blk * kBlock + threadIdx.x; j < nwords; j += stride) {
         uint32_t w = t.occ[j];
         if (w == 0) continue;
         t.occ[j] = 0;
@@ -51,8 +52,10 @@ __global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) {
             c[1] = make_uint4(0, 0, 0, 0);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < PF_STATS_LEN) t.stats[threadIdx.x] = 0;
+    if (blk == 0 && threadIdx.x < PF_STATS_LEN) t.stats[threadIdx.x] = 0;
 }
+
+__global__ __launch_bounds__(kBlock) void clear_kernel(Tab t) { clear_part(t, blockIdx.x, gridDim.x); }
 
 static uint32_t scan_blocks(uint32_t items) {
     const uint32_t b = (items + kBlock - 1) / kBlock;
@@ -121,14 +124,10 @@ hipError_t launch_insert(const Tab &t, const uint64_t *key, const float *r, cons
 
 // ----------------------------------------------------------------- query
 template <bool kBlend>
-__global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__restrict__ key,
-                                                       const uint32_t *__restrict__ slot_in, const float *r,
-                                                       const float *g, const float *b,
-                                                       const uint8_t *__restrict__ flags, uint32_t n, float *ro,
-                                                       float *go, float *bo, uint32_t *__restrict__ count_out,
-                                                       bool inplace) {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void query_one(const Tab &t, uint32_t i, const uint64_t *__restrict__ key,
+                                          const uint32_t *__restrict__ slot_in, const float *r, const float *g,
+                                          const float *b, const uint8_t *__restrict__ flags, float *ro, float *go,
+                                          float *bo, uint32_t *__restrict__ count_out, bool inplace) {
     // the flag and the slot are loaded together; the flag decides
     const uint8_t fl = flags[i];
     uint32_t slot = slot_in ? slot_in[i] : kNoSlot;
@@ -137,6 +136,38 @@ __global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__
     else if (!slot_in)
         slot = find_slot(t, key[i]);
     query_vertex<kBlend>(t, slot, i, r, g, b, ro, go, bo, count_out, inplace);
+}
+
+template <bool kBlend>
+__global__ __launch_bounds__(kBlock) void query_kernel(Tab t, const uint64_t *__restrict__ key,
+                                                       const uint32_t *__restrict__ slot_in, const float *r,
+                                                       const float *g, const float *b,
+                                                       const uint8_t *__restrict__ flags, uint32_t n, float *ro,
+                                                       float *go, float *bo, uint32_t *__restrict__ count_out,
+                                                       bool inplace) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    query_one<kBlend>(t, i, key, slot_in, r, g, b, flags, ro, go, bo, count_out, inplace);
+}
+
+// The lookup in t and, in the same launch, the clear of another table: the
+// first `cblocks` workgroups empty `clr` (dispatched first, their scattered
+// stores overlap the lookup's gathers), the others look up one vertex per
+// lane.
+template <bool kBlend>
+__global__ __launch_bounds__(kBlock) void query_clear_kernel(Tab t, const uint64_t *__restrict__ key,
+                                                             const uint32_t *__restrict__ slot_in, const float *r,
+                                                             const float *g, const float *b,
+                                                             const uint8_t *__restrict__ flags, uint32_t n, float *ro,
+                                                             float *go, float *bo, uint32_t *__restrict__ count_out,
+                                                             bool inplace, Tab clr, uint32_t cblocks) {
+    if (blockIdx.x < cblocks) {
+        clear_part(clr, blockIdx.x, cblocks);
+        return;
+    }
+    const uint32_t i = (blockIdx.x - cblocks) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    query_one<kBlend>(t, i, key, slot_in, r, g, b, flags, ro, go, bo, count_out, inplace);
 }
 
 hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
@@ -148,6 +179,21 @@ hipError_t launch_query(const Tab &t, const uint64_t *key, const uint32_t *slot,
         query_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
     else
         query_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out, inplace);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_clear(const Tab &t, const uint64_t *key, const uint32_t *slot, const float *r, const float *g,
+                              const float *b, const uint8_t *flags, uint32_t n, bool use_blend, float *ro, float *go,
+                              float *bo, uint32_t *count_out, const Tab &clr, hipStream_t st) {
+    const uint32_t cblocks = scan_blocks(clr.nwords());
+    const uint32_t blocks = cblocks + (n + kBlock - 1) / kBlock;
+    const bool inplace = (ro == r) && (go == g) && (bo == b);
+    if (use_blend)
+        query_clear_kernel<true><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out,
+                                                           inplace, clr, cblocks);
+    else
+        query_clear_kernel<false><<<blocks, kBlock, 0, st>>>(t, key, slot, r, g, b, flags, n, ro, go, bo, count_out,
+                                                            inplace, clr, cblocks);
     return hipGetLastError();
 }
 

@@ -32,8 +32,11 @@ def table_contents(t: pf.Table):
 
 
 def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=False, alpha=0.2,
-              idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None, low_density=None):
-    """One frame through the C ABI; returns per-vertex results and stats."""
+              idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None, low_density=None,
+              clear_in_lookup=None):
+    """One frame through the C ABI; returns per-vertex results and stats.
+    clear_in_lookup: a table that the lookup's launch empties
+    (pf_query_average_clear) instead of the plain lookup."""
     n = g["px"].numel()
     dev = g["px"].device
     key = torch.empty(n, dtype=torch.int64, device=dev)
@@ -71,11 +74,15 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
         temporal = True  # the lookup returns the temporal value
     if in_place:
         out = (g["r"].clone(), g["g"].clone(), g["b"].clone())
-        pf.query_average(cur, key, slot if use_slot else None, out[0], out[1], out[2], vflags, temporal,
-                         out[0], out[1], out[2], cnt)
+        src = out
     else:
         out = (torch.empty_like(g["r"]), torch.empty_like(g["g"]), torch.empty_like(g["b"]))
-        pf.query_average(cur, key, slot if use_slot else None, g["r"], g["g"], g["b"], vflags, temporal,
+        src = (g["r"], g["g"], g["b"])
+    if clear_in_lookup is not None:
+        pf.query_average_clear(cur, key, slot if use_slot else None, src[0], src[1], src[2], vflags, temporal,
+                               out[0], out[1], out[2], clear_in_lookup, cnt)
+    else:
+        pf.query_average(cur, key, slot if use_slot else None, src[0], src[1], src[2], vflags, temporal,
                          out[0], out[1], out[2], cnt)
     torch.cuda.synchronize()
     res = {

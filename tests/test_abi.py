@@ -110,6 +110,21 @@ def test_argument_checks_return_before_launch(pf):
     assert L.pf_temporal_update(ctypes.byref(t3), None, ctypes.c_float(0.2), 0, None) == lp.PF_EINVAL
     assert L.pf_query_average(ctypes.byref(t3), fake, None, fake, fake, fake, fake, 5, 1, fake, fake, fake, None,
                               None) == lp.PF_EINVAL
+    # the lookup with the clear of another table: that table is required and
+    # its slots may not overlap the looked-up table's
+    qc = L.pf_query_average_clear
+    assert qc(ctypes.byref(t), fake, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None, None,
+              None) == lp.PF_EINVAL
+    assert qc(ctypes.byref(t), fake, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None, ctypes.byref(t),
+              None) == lp.PF_EINVAL
+    t4 = lp.pf_table()   # starts inside t's slot records
+    assert L.pf_table_carve(ctypes.c_void_p(0x7F0000000000 + 256 * 64), 10, 1, 64, 24, ctypes.byref(t4)) == 0
+    assert qc(ctypes.byref(t), fake, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None, ctypes.byref(t4),
+              None) == lp.PF_EINVAL
+    assert qc(ctypes.byref(t3), fake, None, fake, fake, fake, fake, 5, 1, fake, fake, fake, None, ctypes.byref(t2),
+              None) == lp.PF_EINVAL   # no temporal values to look up
+    assert qc(ctypes.byref(t), None, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None, ctypes.byref(t2),
+              None) == lp.PF_EINVAL   # neither key nor slot
     # low-density fallback: needs the blend array and fixed-point sums, a known mode; below <= 1 is a no-op
     assert L.pf_low_density_fallback(ctypes.byref(t3), 4, 0, None) == lp.PF_EINVAL
     assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE

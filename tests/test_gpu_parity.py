@@ -125,6 +125,48 @@ def test_clear_reuses_table_across_frames(gpu):
         check_frame_against_oracle(res, oracle.filter_frame(_host(f), temporal=False), t)
 
 
+@pytest.mark.parametrize("agg,in_place", [("fused", False), (64, True)])
+def test_lookup_clears_the_other_table(gpu, agg, in_place):
+    """pf_query_average_clear: twelve frames with double-buffered tables where
+    each frame's lookup empties the other table and no frame calls pf_clear
+    (the first frame's tables are freshly initialised).  Every frame equals
+    the oracle's, and right after each lookup the other table holds no cell,
+    bitmap bit or statistic."""
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(19), pf.Table(19)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(12):
+        f = synth.generate(wl, frame=frame, width=400 + 3 * frame, height=230)
+        f["log2_slots"] = 19
+        cur, other = tabs[frame % 2], tabs[(frame + 1) % 2]
+        print(f"[lookup+clear] {agg} in_place={in_place} frame {frame} n={f['px'].numel()}", flush=True)
+        res = gpu_frame(f, to_dev(f), cur, prev=other if frame else None, agg=agg, temporal=True,
+                        alpha=wl.alpha_old, clear=False, in_place=in_place, clear_in_lookup=other)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old)
+        check_frame_against_oracle(res, R, cur)
+        assert int(other.cells().abs().sum()) == 0
+        assert int(other.occupancy().abs().sum()) == 0
+        assert int(other._view(other.t.stats, 8 * pf._lib.STATS_LEN, torch.int64).abs().sum()) == 0
+        state = R.state
+
+
+def test_lookup_clear_with_no_vertices(gpu):
+    """n == 0: only the other table is emptied."""
+    wl, f = _frame("hd_1080p_x3", frame=0, width=160, height=90)
+    f["log2_slots"] = 16
+    a, b = pf.Table(16), pf.Table(16)
+    pf.table_init(a); pf.table_init(b)
+    gpu_frame(f, to_dev(f), b, agg=64)
+    assert int(b.occupancy().abs().sum()) > 0
+    e = torch.empty(0, device="cuda")
+    pf.query_average_clear(a, torch.empty(0, dtype=torch.int64, device="cuda"), None, e, e, e,
+                           torch.empty(0, dtype=torch.uint8, device="cuda"), False, e, e, e, b)
+    torch.cuda.synchronize()
+    assert int(b.cells().abs().sum()) == 0 and int(b.occupancy().abs().sum()) == 0
+
+
 def test_in_place_query(gpu):
     wl, f = _frame("hd_1080p_x3", frame=1, width=300, height=200)
     g = to_dev(f)

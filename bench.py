@@ -1,12 +1,14 @@
 """Benchmark: hashed path space filtering of the 1080p x3 workload on one GPU.
 
 One step filters one frame of the orbiting camera (1920x1080 pixels, 3 path
-vertices per pixel, 6,220,800 vertex slots): build keys and insert-accumulate
-into the current table, temporal moving average against the previous
-frame's table, look up, emptying the previous frame's table in the lookup's
-launch for the next frame (--separate-clear: a clear launch of its own at
-the start of each frame instead).  Sixteen frames are generated on the GPU before
-timing (inputs resident in HBM) and steps cycle through them.
+vertex slots per pixel, 6,220,800 vertex slots): build keys and
+insert-accumulate into the current table with the temporal moving average
+against the previous frame's table done where the insert finalises each
+cell (--separate-temporal: a temporal pass of its own), then look up,
+emptying the previous frame's table in the lookup's launch for the next
+frame (--separate-clear: a clear launch at the start of each frame).
+Sixteen frames are generated on the GPU before timing (inputs resident in
+HBM) and steps cycle through them.
 
 Prints one JSON line.  `value` is vertices filtered per second (valid
 vertices, i.e. those with a hit, over the whole timed region); per-kernel
@@ -67,6 +69,8 @@ def parse():
                    help="the temporal pass also searches a changed cell's region one level coarser and finer")
     p.add_argument("--resolve", action="store_true",
                    help="add the pixel resolve (value times a synthetic throughput, summed per pixel) as a stage")
+    p.add_argument("--separate-temporal", action="store_true",
+                   help="run the temporal pass as a launch of its own instead of inside the fused insert")
     p.add_argument("--separate-clear", action="store_true",
                    help="clear each frame's table in its own launch instead of in the previous frame's lookup")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -182,6 +186,8 @@ def main():
                                                              dtype=torch.uint8, device=dev)
 
     clear_in_lookup = not multilevel and not a.separate_clear
+    # the temporal blend done where the fused insert finalises each cell
+    temporal_in_insert = fused and not (multilevel or hist is not None or a.across_levels or a.separate_temporal)
 
     def stages(k):
         """(name, call) of one frame's steps, in order"""
@@ -193,7 +199,12 @@ def main():
         # starts empty and no clear stage runs; the first frame's table is
         # empty from its initialisation
         st = [] if clear_in_lookup else [("clear", lambda: pf.clear(cur))]
-        if fused:
+        if temporal_in_insert:
+            prev = flt.prev
+            st.append(("build_keys_insert_temporal", lambda: pf.build_keys_insert_binned_temporal(
+                cur, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"], f["seed"], 0,
+                f["r"], f["g"], f["b"], key if use_mlp else None, vflags, slot, flt.ws, prev, wl.alpha_old)))
+        elif fused:
             st.append(("build_keys_insert", lambda: pf.build_keys_insert_binned(
                 cur, f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["cam"], f["s"], f["seed"], 0,
                 f["r"], f["g"], f["b"], key if (use_mlp or multilevel) else None, vflags, slot, flt.ws)))
@@ -207,7 +218,9 @@ def main():
             else:
                 st.append(("insert_accumulate",
                            lambda: pf.insert_accumulate(cur, key, f["r"], f["g"], f["b"], vflags, slot, a.agg)))
-        if hist is not None:
+        if temporal_in_insert:
+            pass
+        elif hist is not None:
             fr = flt.frames
             st.append(("temporal_history", lambda: pf.temporal_history(cur, hist, wl.alpha_old, 0, pf.MAX_SAMPLES,
                                                                        fr)))
@@ -366,12 +379,16 @@ def main():
         "query_average_clear": n * (1 + 12) + nv * (4 + 16) + (n - nv) * 12 + cells * 32 + (1 << view.log2_slots) // 8,
         # fused: positions, normals, valid in; flags and slot out; contribution, probe, cell update per valid vertex
         "build_keys_insert": n * (6 * 4 + 1 + 1 + 4) + nv * (12 + 4 + 28),
+        # the same and the temporal pass's per-cell bytes (no bitmap scan: the owner of each cell blends it)
+        "build_keys_insert_temporal": n * (6 * 4 + 1 + 1 + 4) + nv * (12 + 4 + 28) + cells * (32 + 8 + 4 + 8 + 16 + 16),
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
     launches = {"insert_accumulate": ("aggregate, colscan, binscan, scatter, reduce" if a.insert == "binned"
                                       else "insert"),
-                "build_keys_insert": "aggregate (keys built in it), colscan, binscan, scatter, reduce"}
+                "build_keys_insert": "aggregate (keys built in it), colscan, binscan, scatter, reduce",
+                "build_keys_insert_temporal": "aggregate (keys built in it), colscan, binscan, scatter, "
+                                              "reduce (temporal blend in it)"}
     roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, a.workload, a.insert),
@@ -381,7 +398,9 @@ def main():
     # the method makes a probe and a cell update when inserting and a probe and
     # a cell read when looking up, plus one claim per cell (4V + C touches)
     touches = 4 * nv + cells
-    t_ins = per["build_keys_insert"] if fused else per["insert_accumulate"]   # fused: keys counted in the insert
+    # fused: keys counted in the insert (and the temporal pass, when it is done there)
+    t_ins = (per.get("build_keys_insert", per.get("build_keys_insert_temporal")) if fused
+             else per["insert_accumulate"])
     t_q = per.get("query_average", per.get("query_average_clear", per.get("query_multilevel", 0.0)))
     t_iq = (t_ins + t_q) * 1e-6   # with the fused clear, the lookup's time includes emptying the other table
     ra["insert_query_touches"] = int(touches)

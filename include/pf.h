@@ -243,6 +243,28 @@ pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const 
                                       uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
                                       void *workspace, size_t workspace_bytes, void *stream);
 
+/* pf_build_keys_insert_binned followed by the temporal pass of the frame
+ * (Section 3.4.1) in the same five launches: the workgroup that owns a bin
+ * of slots, once it has added the bin's records to its cells, computes each
+ * cell's average and blends it with the value of the same key in prev (NULL:
+ * no previous frame, the temporal value is the average), storing the
+ * temporal value as pf_temporal_update (max_samples == 0: moving average with
+ * alpha_old, mode 0) or pf_temporal_integrate (max_samples > 0) would; the
+ * temporal-hit statistic is counted the same way.  Only the cells this call
+ * inserts into get a temporal value, so t must be empty (initialised or
+ * cleared) before the call: the frame's vertices are one batch.  prev must
+ * be another table with the same log2_slots and temporal values.  Errors:
+ * those of pf_build_keys_insert_binned; PF_EINVAL (t or prev without
+ * temporal values, prev == t); PF_ERANGE (log2_slots differ, alpha_old
+ * outside [0, 1] with max_samples == 0, max_samples > PF_MAX_SAMPLES). */
+pf_status pf_build_keys_insert_binned_temporal(const pf_table *t, const float *px, const float *py,
+                                               const float *pz, const float *nx, const float *ny,
+                                               const float *nz, const uint8_t *valid, const pf_key_params *kp,
+                                               const float *r, const float *g, const float *b, uint64_t n,
+                                               uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                               void *workspace, size_t workspace_bytes, const pf_table *prev,
+                                               float alpha_old, uint32_t max_samples, void *stream);
+
 /* ------------------------------------------------------------------ query */
 /* Lookup (Sections 3.2, 3.3.1): for each vertex with vflags == 0, finds its
  * cell (from slot[i] when slot is non-NULL, else by probing with key[i]) and

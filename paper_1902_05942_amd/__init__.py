@@ -19,7 +19,7 @@ from ._lib import (SLOT_BYTES, STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORA
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
                    query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS,
-                   query_average_clear)
+                   query_average_clear, build_keys_insert_binned_temporal)
 
 
 class MlpFallback:
@@ -70,13 +70,19 @@ class FrameFilter:
     lookup, clear_in_lookup empties the previous frame's table (read for the
     last time by the temporal blend) in the lookup's launch
     (pf_query_average_clear), so the next frame starts without a clear.
+    With keys built in the binned insert, the moving average or integration
+    against the previous frame's table, and no history, coarser level or
+    search across levels, temporal_in_insert blends each cell where the
+    insert finalises it (pf_build_keys_insert_binned_temporal) instead of in
+    a pass of its own.
     """
 
     def __init__(self, n_max: int, log2_slots: int, max_probe: int = 64, frac_bits: int = 24,
                  temporal: bool = True, alpha_old: float = 0.2, agg_width: int = 0, device="cuda",
                  mlp: "MlpFallback | None" = None, binned: bool = False, float_sums: bool = False,
                  max_samples: "int | None" = None, fused: bool = False, low_density=None, multilevel=None,
-                 history=None, across_levels: bool = False, clear_in_lookup: bool = True):
+                 history=None, across_levels: bool = False, clear_in_lookup: bool = True,
+                 temporal_in_insert: bool = True):
         fmt = SUMS_FLOAT32 if float_sums else SUMS_FIXED64
         self.tables = [Table(log2_slots, max_probe, frac_bits, True, device, sum_format=fmt)
                        for _ in range(2 if temporal else 1)]
@@ -114,6 +120,8 @@ class FrameFilter:
         self.count = torch.empty(n_max, dtype=torch.int32, device=device)
         self.frames = 0
         self.clear_in_lookup = clear_in_lookup
+        self.temporal_in_insert = (temporal_in_insert and fused and temporal and history is None
+                                   and multilevel is None and not across_levels)
         self._cur_clean = False  # the current table was emptied by the last frame's lookup
         self.mlp = mlp
         self.ws = None
@@ -144,8 +152,13 @@ class FrameFilter:
         self._cur_clean = False
         if self.fused:  # the keys are only written when the learned fallback or the coarser level reads them
             want_key = self.mlp is not None or self.multilevel is not None
-            build_keys_insert_binned(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b,
-                                     key if want_key else None, vflags, slot, self.ws)
+            if self.temporal_in_insert:  # the current table is empty here (cleared, or by the last lookup)
+                build_keys_insert_binned_temporal(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g,
+                                                  b, key if want_key else None, vflags, slot, self.ws, self.prev,
+                                                  self.alpha_old, self.max_samples or 0)
+            else:
+                build_keys_insert_binned(cur, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b,
+                                         key if want_key else None, vflags, slot, self.ws)
         else:
             build_keys(px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, self.log2_slots, key, None, None, vflags)
             if self.ws is not None:
@@ -153,7 +166,7 @@ class FrameFilter:
             else:
                 insert_accumulate(cur, key, r, g, b, vflags, slot, self.agg_width)
         use_blend = self.temporal or self.low_density is not None
-        levels = [(cur, self.prev)]
+        levels = [] if self.temporal_in_insert else [(cur, self.prev)]
         if self.multilevel is not None:
             cc = self.coarse[0]
             key_c, vflags_c, slot_c = self.key_c[:n], self.vflags_c[:n], self.slot_c[:n]

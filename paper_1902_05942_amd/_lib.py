@@ -93,6 +93,8 @@ def _load():
                                                           vp, ctypes.c_size_t, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_query_average_clear": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, T, vp], i),
+        "pf_build_keys_insert_binned_temporal": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp,
+                                                                   vp, vp, vp, ctypes.c_size_t, T, f32, u32, vp], i),
         "pf_temporal_update": ([T, T, f32, i, vp], i),
         "pf_temporal_integrate": ([T, T, u32, vp], i),
         "pf_low_density_fallback": ([T, u32, i, vp], i),
@@ -134,7 +136,8 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
             "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
-            "pf_temporal_history", "pf_resolve_pixels", "pf_query_average_clear")
+            "pf_temporal_history", "pf_resolve_pixels", "pf_query_average_clear",
+            "pf_build_keys_insert_binned_temporal")
 
 
 def _ptr(t):
@@ -258,6 +261,25 @@ def build_keys_insert_binned(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, se
         t.ref, _ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(valid), ctypes.byref(kp), _ptr(r),
         _ptr(g), _ptr(b), vflags.numel(), _ptr(key), _ptr(vflags), _ptr(slot_out), _ptr(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def build_keys_insert_binned_temporal(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b, key,
+                                      vflags, slot_out, workspace, prev, alpha_old: float = 0.2,
+                                      max_samples: int = 0, stream=None):
+    """build_keys_insert_binned and the frame's temporal pass (moving
+    average with alpha_old, or integration when max_samples > 0) in the same
+    launches; t must be empty before the call."""
+    kp = pf_key_params()
+    for c in range(3):
+        kp.cam[c] = float(cam[c])
+    kp.s = float(s)
+    kp.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    kp.idx_base = int(idx_base)
+    _check("pf_build_keys_insert_binned_temporal", lib.pf_build_keys_insert_binned_temporal(
+        t.ref, _ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(valid), ctypes.byref(kp), _ptr(r),
+        _ptr(g), _ptr(b), vflags.numel(), _ptr(key), _ptr(vflags), _ptr(slot_out), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), None if prev is None else prev.ref, float(alpha_old),
+        int(max_samples), _stream(stream)))
 
 
 def query_average(t: Table, key, slot, r_in, g_in, b_in, vflags, use_blend, r_out, g_out, b_out, count_out=None,

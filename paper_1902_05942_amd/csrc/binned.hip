@@ -20,7 +20,10 @@
 //   scatter    per tile: staged records moved to their bin's range
 //   reduce     per bin (a contiguous slot range): records summed in LDS, then
 //              count and sums added to the cells with plain loads and stores
-//              by the workgroup that owns them, occupancy bits set
+//              by the workgroup that owns them, occupancy bits set; with a
+//              temporal blend (Section 3.4.1) in the same launch, the owner
+//              also blends each cell's final average with the previous
+//              table's value of its key and stores the temporal value
 // Integer sums make the result identical to the atomic insert.
 #include "pf_kernels.h"
 #include "pf_merge.h"
@@ -447,12 +450,24 @@ __global__ __launch_bounds__(kT) void scatter_kernel(const Rec *__restrict__ tre
     }
 }
 
+// The temporal blend done by reduce: the previous table (has_prev) and the
+// blend's parameters as pf_temporal_update / pf_temporal_integrate take them.
+struct Blend {
+    Tab prev;
+    float alpha, beta;
+    uint32_t cap;
+};
+
 // One workgroup per bin: LDS sums over its records, then the exclusive
 // owner adds them to the cells and sets the occupancy bits of its words.
+// kBlend: the owner then computes the temporal values of its cells (the
+// cells are final: every record of a slot is in the slot's bin), as
+// temporal_word does for one bitmap word.
+template <bool kBlend = false, bool kHasPrev = false, bool kIntegrate = false>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec *__restrict__ rec,
                                                                 const uint32_t *__restrict__ start,
                                                                 const uint32_t *__restrict__ total,
-                                                                uint32_t bin_slots) {
+                                                                uint32_t bin_slots, Blend bl) {
     extern __shared__ unsigned long long lred[];
     unsigned long long *sum0 = lred, *sum1 = lred + bin_slots, *sum2 = lred + 2 * bin_slots;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(lred + 3 * bin_slots);
@@ -492,6 +507,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
     __syncthreads();
     // the cells of a thread's slots are all loaded before any is updated
     uint4 *cells = t.words_at(base);  // 4 sixteen-byte words per slot record
+    uint32_t hits = 0;
     for (uint32_t kb = 0; kb < bin_slots; kb += kBatch * kReduceThreads) {
         uint32_t c[kBatch];
         uint4 lo[kBatch], hi[kBatch];
@@ -524,6 +540,46 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
             }
         }
     }
+    if constexpr (kBlend) {
+        // the bin's cells are final: listed in LDS (the sums' space is free
+        // now), then blended one per lane, so that every lane has a cell
+        // while the list lasts
+        __shared__ uint32_t nlist, s_hits;
+        uint32_t *list = reinterpret_cast<uint32_t *>(sum0);
+        if (threadIdx.x == 0) {
+            nlist = 0;
+            s_hits = 0;
+        }
+        __syncthreads();  // the cells are written, the sums no longer read
+        for (uint32_t k = threadIdx.x; k < bin_slots; k += kReduceThreads)
+            if (cnt[k]) list[atomicAdd(&nlist, 1u)] = k;
+        __syncthreads();
+        const uint32_t m = nlist;
+        for (uint32_t q = threadIdx.x; q < m; q += kReduceThreads) {
+            const uint32_t sl[1] = {base + list[q]};
+            const uint4 *w4 = t.words_at(sl[0]);  // written above by this workgroup
+            const uint4 lo = w4[0], hi = w4[1], kw = w4[2];
+            pf_cell cl;
+            cl.fp = lo.x;
+            cl.count = lo.y;
+            cl.sum[0] = (int64_t)((uint64_t)lo.z | (uint64_t)lo.w << 32);
+            cl.sum[1] = (int64_t)((uint64_t)hi.x | (uint64_t)hi.y << 32);
+            cl.sum[2] = (int64_t)((uint64_t)hi.z | (uint64_t)hi.w << 32);
+            const bool has[1] = {true};
+            const uint64_t key[1] = {(uint64_t)kw.x | (uint64_t)kw.y << 32};
+            const uint32_t fp[1] = {cl.fp}, n[1] = {cl.count};
+            uint32_t keep[1] = {kIntegrate ? min(cl.count, bl.cap) : cl.count};
+            float v[1][3] = {{t.average(cl, 0), t.average(cl, 1), t.average(cl, 2)}};
+            hits += blend_cells<kHasPrev, kIntegrate, 1, false>(t, bl.prev, sl, has, key, fp, v, n, keep, bl.alpha,
+                                                                bl.beta, bl.cap);
+        }
+        if constexpr (kHasPrev) {
+            // one device atomic per workgroup, spread over 32 partial counters
+            if (hits) atomicAdd(&s_hits, hits);
+            __syncthreads();
+            if (threadIdx.x == 0 && s_hits) add_u64(&t.stats[PF_STAT_PART_HIT + (blockIdx.x & 31)], s_hits);
+        }
+    }
 }
 
 }  // namespace binned
@@ -535,9 +591,20 @@ size_t binned_workspace_bytes(uint32_t n, uint32_t log2_slots) {
 
 namespace binned {
 
+// the reduce kernels of every blend variant, for their LDS attribute
+static const void *const kReduceKernels[] = {
+    reinterpret_cast<const void *>(reduce_kernel<false, false, false>),
+    reinterpret_cast<const void *>(reduce_kernel<true, false, false>),
+    reinterpret_cast<const void *>(reduce_kernel<true, true, false>),
+    reinterpret_cast<const void *>(reduce_kernel<true, false, true>),
+    reinterpret_cast<const void *>(reduce_kernel<true, true, true>)};
+
+// blend: NULL for the insert alone; else the temporal blend in reduce
+// (has_prev: blend->prev is a table; integrate: temporal integration).
 template <bool kKeys>
 static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
-                      uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, const FusedKeys &fk, hipStream_t st) {
+                      uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, const FusedKeys &fk,
+                      const Blend *blend, bool has_prev, bool integrate, hipStream_t st) {
     const uint32_t log2_slots = 32 - __builtin_clz(t.mask + 1) - 1;
     const Plan p = make_plan(n, log2_slots);
     char *base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ws) + 255) / 256 * 256);
@@ -554,9 +621,9 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(aggregate_kernel<true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(reduce_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4096 * 28));
+        for (const void *f : kReduceKernels)
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4096 * 28));
         if (e != hipSuccess) return e;
         attrs = true;
     }
@@ -567,7 +634,22 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
     binscan_kernel<<<1, 1024, 0, st>>>(tot, p.nbins, start);
     scatter_kernel<<<p.ntiles, kT, (size_t)p.nbins * 4, st>>>(trec, ntr, p.tile, p.nbins, p.bin_shift, H, start,
                                                               rec);
-    reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot, p.bin_slots);
+    const Blend none{};
+    const Blend &bl = blend ? *blend : none;
+    if (!blend)
+        reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot, p.bin_slots, bl);
+    else if (!has_prev && !integrate)
+        reduce_kernel<true, false, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
+                                                                                       p.bin_slots, bl);
+    else if (has_prev && !integrate)
+        reduce_kernel<true, true, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
+                                                                                      p.bin_slots, bl);
+    else if (!has_prev)
+        reduce_kernel<true, false, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
+                                                                                      p.bin_slots, bl);
+    else
+        reduce_kernel<true, true, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
+                                                                                     p.bin_slots, bl);
     return hipGetLastError();
 }
 
@@ -576,7 +658,7 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
 hipError_t launch_insert_binned(const Tab &t, const uint64_t *key, const float *r, const float *g, const float *b,
                                 uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws, hipStream_t st) {
     binned::FusedKeys none{};
-    return binned::run<false>(t, key, r, g, b, flags, slot_out, n, ws, none, st);
+    return binned::run<false>(t, key, r, g, b, flags, slot_out, n, ws, none, nullptr, false, false, st);
 }
 
 hipError_t launch_keys_insert_binned(const Tab &t, const float *px, const float *py, const float *pz,
@@ -585,7 +667,22 @@ hipError_t launch_keys_insert_binned(const Tab &t, const float *px, const float 
                                      const float *b, uint8_t *flags, uint32_t *slot_out, uint32_t n, void *ws,
                                      hipStream_t st) {
     const binned::FusedKeys fk{px, py, pz, nx, ny, nz, valid, a, key_out};
-    return binned::run<true>(t, nullptr, r, g, b, flags, slot_out, n, ws, fk, st);
+    return binned::run<true>(t, nullptr, r, g, b, flags, slot_out, n, ws, fk, nullptr, false, false, st);
+}
+
+hipError_t launch_keys_insert_binned_temporal(const Tab &t, const float *px, const float *py, const float *pz,
+                                              const float *nx, const float *ny, const float *nz,
+                                              const uint8_t *valid, const KeyArgs &a, uint64_t *key_out,
+                                              const float *r, const float *g, const float *b, uint8_t *flags,
+                                              uint32_t *slot_out, uint32_t n, void *ws, const Tab *prev,
+                                              float alpha_old, int mode, uint32_t cap, hipStream_t st) {
+    const binned::FusedKeys fk{px, py, pz, nx, ny, nz, valid, a, key_out};
+    binned::Blend bl{};
+    if (prev) bl.prev = *prev;
+    bl.alpha = alpha_old;
+    bl.beta = 1.0f - alpha_old;
+    bl.cap = cap;
+    return binned::run<true>(t, nullptr, r, g, b, flags, slot_out, n, ws, fk, &bl, prev != nullptr, mode == 1, st);
 }
 
 }  // namespace pfk

@@ -166,11 +166,13 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
                                               (hipStream_t)stream));
 }
 
-pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const float *py, const float *pz,
-                                      const float *nx, const float *ny, const float *nz, const uint8_t *valid,
-                                      const pf_key_params *kp, const float *r, const float *g, const float *b,
-                                      uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
-                                      void *workspace, size_t workspace_bytes, void *stream) {
+// The checks of pf_build_keys_insert_binned; fills a.  PF_OK with *empty
+// set when n == 0 (nothing to launch).
+static pf_status check_keys_insert(const pf_table *t, const float *px, const float *py, const float *pz,
+                                   const float *nx, const float *ny, const float *nz, const pf_key_params *kp,
+                                   const float *r, const float *g, const float *b, uint64_t n, const uint64_t *key,
+                                   const uint8_t *vflags, const uint32_t *slot_out, const void *workspace,
+                                   size_t workspace_bytes, pfk::KeyArgs &a, bool &empty) {
     const pf_status s = check_table(t);
     if (s != PF_OK) return s;
     if (!kp) return PF_EINVAL;
@@ -181,21 +183,65 @@ pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const 
         return PF_ERANGE;
     const size_t need = pf_insert_workspace_bytes(n, t->log2_slots);
     if (need == 0) return PF_ERANGE;
-    if (n == 0) return PF_OK;
+    empty = n == 0;
+    if (empty) return PF_OK;
     if (!px || !py || !pz || !nx || !ny || !nz || !r || !g || !b || !vflags || !slot_out || !workspace ||
         workspace_bytes < need)
         return PF_EINVAL;
     if (!aligned(px) || !aligned(py) || !aligned(pz) || !aligned(nx) || !aligned(ny) || !aligned(nz) ||
         !aligned(r) || !aligned(g) || !aligned(b) || !aligned(slot_out) || (key && !aligned(key)))
         return PF_EINVAL;
-    pfk::KeyArgs a;
     for (int c = 0; c < 3; ++c) a.cam[c] = kp->cam[c];
     a.s = kp->s;
     a.seed = kp->seed;
     a.idx_base = kp->idx_base;
     a.mask = (uint32_t)((1ull << t->log2_slots) - 1);
+    return PF_OK;
+}
+
+pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const float *py, const float *pz,
+                                      const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                      const pf_key_params *kp, const float *r, const float *g, const float *b,
+                                      uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                      void *workspace, size_t workspace_bytes, void *stream) {
+    pfk::KeyArgs a;
+    bool empty = false;
+    const pf_status s = check_keys_insert(t, px, py, pz, nx, ny, nz, kp, r, g, b, n, key, vflags, slot_out, workspace,
+                                          workspace_bytes, a, empty);
+    if (s != PF_OK || empty) return s;
     return launched(pfk::launch_keys_insert_binned(to_tab(t), px, py, pz, nx, ny, nz, valid, a, key, r, g, b, vflags,
                                                    slot_out, (uint32_t)n, workspace, (hipStream_t)stream));
+}
+
+pf_status pf_build_keys_insert_binned_temporal(const pf_table *t, const float *px, const float *py, const float *pz,
+                                               const float *nx, const float *ny, const float *nz,
+                                               const uint8_t *valid, const pf_key_params *kp, const float *r,
+                                               const float *g, const float *b, uint64_t n, uint64_t *key,
+                                               uint8_t *vflags, uint32_t *slot_out, void *workspace,
+                                               size_t workspace_bytes, const pf_table *prev, float alpha_old,
+                                               uint32_t max_samples, void *stream) {
+    pfk::KeyArgs a;
+    bool empty = false;
+    pf_status s = check_keys_insert(t, px, py, pz, nx, ny, nz, kp, r, g, b, n, key, vflags, slot_out, workspace,
+                                    workspace_bytes, a, empty);
+    if (s != PF_OK) return s;
+    if (!t->blend) return PF_EINVAL;
+    if (prev) {
+        s = check_table(prev);
+        if (s != PF_OK) return s;
+        if (!prev->blend) return PF_EINVAL;
+        if (prev->log2_slots != t->log2_slots) return PF_ERANGE;
+        if (prev->cell == t->cell) return PF_EINVAL;
+    }
+    if (max_samples > PF_MAX_SAMPLES) return PF_ERANGE;
+    if (max_samples == 0 && !(alpha_old >= 0.0f && alpha_old <= 1.0f)) return PF_ERANGE;
+    if (empty) return PF_OK;
+    pfk::Tab p;
+    if (prev) p = to_tab(prev);
+    return launched(pfk::launch_keys_insert_binned_temporal(
+        to_tab(t), px, py, pz, nx, ny, nz, valid, a, key, r, g, b, vflags, slot_out, (uint32_t)n, workspace,
+        prev ? &p : nullptr, alpha_old, max_samples ? 1 : 0, max_samples ? max_samples : PF_MAX_SAMPLES,
+        (hipStream_t)stream));
 }
 
 pf_status pf_query_average(const pf_table *t, const uint64_t *key, const uint32_t *slot, const float *r_in,

@@ -302,11 +302,99 @@ __device__ __forceinline__ bool find_across_levels(const Tab &prev, uint64_t K, 
     return false;
 }
 
-// `cur` (Section 3.4.1), restricted to the bits of `part`; returns how many
-// found their key in `prev`.  The
-// word's cells are taken kTB at a time, and each step of their lookups in
-// the previous table (cell and key, fingerprint probe, key check, old value)
-// is issued for all of them before any result is used.  kIntegrate: temporal
+// The temporal values of kTB cells of cur: slots s (has: in use), keys,
+// fingerprints fp, this frame's averages v and counts cnt, stored counts
+// keep.  Each key is searched in prev (fingerprint probe confirmed by the
+// stored key) and, where found, blended by the moving average or by
+// integration (kIntegrate; keep then becomes min(N_old + N_new, cap)); the
+// values are stored in cur's records.  Returns the keys found in prev.
+template <bool kHasPrev, bool kIntegrate, int kTB, bool kLevels>
+__device__ __forceinline__ uint32_t blend_cells(const Tab &cur, const Tab &prev, const uint32_t (&s)[kTB],
+                                                const bool (&has)[kTB], const uint64_t (&key)[kTB],
+                                                const uint32_t (&fp)[kTB], float (&v)[kTB][3],
+                                                const uint32_t (&cnt)[kTB], uint32_t (&keep)[kTB], float alpha,
+                                                float beta, uint32_t cap) {
+    uint32_t hits = 0;
+    if constexpr (kHasPrev) {
+        // search each key in prev: fingerprint probe confirmed by the stored key
+        uint32_t p[kTB];
+        bool active[kTB], found[kTB];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            active[k] = has[k];
+            found[k] = false;
+            p[k] = has[k] ? home_of(key[k], prev.mask) : 0u;
+        }
+        for (uint32_t d = 0; d < prev.max_probe; ++d) {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) any |= active[k];
+            if (!any) break;
+            uint32_t pf[kTB];
+            uint64_t pk[kTB];
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell_at(p[k]).fp : 0u;
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                pk[k] = 0;
+                if (active[k] && pf[k] == fp[k]) pk[k] = prev.key_at(p[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kTB; ++k) {
+                if (!active[k]) continue;
+                if (pf[k] == 0) {
+                    active[k] = false;  // empty slot: not in prev
+                } else if (pf[k] == fp[k] && pk[k] == key[k]) {
+                    active[k] = false;
+                    found[k] = true;
+                } else {
+                    p[k] = (p[k] + 1) & prev.mask;
+                }
+            }
+        }
+        float4 old[kTB];
+        bool use[kTB];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            if (found[k]) old[k] = prev.blend_at(p[k]);
+            use[k] = found[k];
+        }
+        if constexpr (kLevels) {
+            for (int k = 0; k < kTB; ++k)
+                if (has[k] && !found[k]) use[k] = find_across_levels<kIntegrate>(prev, key[k], old[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+            if (!use[k]) continue;
+            float al = alpha, be = beta;
+            if constexpr (kIntegrate) {
+                // counts are exact integers in binary32 (at most 2^24)
+                const float nsum = old[k].w + (float)cnt[k];
+                al = old[k].w / nsum;
+                be = 1.0f - al;
+                const uint32_t n = (uint32_t)nsum;
+                keep[k] = n < cap ? n : cap;
+            }
+            const float a0 = al * old[k].x, a1 = al * old[k].y, a2 = al * old[k].z;
+            const float b0 = be * v[k][0], b1 = be * v[k][1], b2 = be * v[k][2];
+            v[k][0] = a0 + b0;
+            v[k][1] = a1 + b1;
+            v[k][2] = a2 + b2;
+            if (found[k]) ++hits;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTB; ++k)
+        if (has[k]) cur.blend_at(s[k]) = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
+    return hits;
+}
+
+// The temporal blend of the occupied cells of bitmap word j of `cur`
+// (Section 3.4.1), restricted to the bits of `part`; returns how many found
+// their key in `prev`.  The word's cells are taken kTB at a time, and each
+// step of their lookups in the previous table (cell and key, fingerprint
+// probe, key check, old value) is issued for all of them before any result
+// is used (blend_cells).  kIntegrate: temporal
 // integration, alpha = N_old / (N_old + N_new) per cell with the stored count
 // kept at most `cap`; else the moving average with a fixed alpha (the stored
 // count is this frame's).
@@ -353,77 +441,11 @@ __device__ __forceinline__ uint32_t temporal_word(const Tab &cur, const Tab &pre
             v[k][1] = cur.average(c, 1);
             v[k][2] = cur.average(c, 2);
         }
-        if constexpr (kHasPrev) {
-            // search each key in prev: fingerprint probe confirmed by the stored key
-            uint32_t p[kTB];
-            bool active[kTB], found[kTB];
+        uint32_t fp[kTB];
 #pragma unroll
-            for (int k = 0; k < kTB; ++k) {
-                active[k] = has[k];
-                found[k] = false;
-                p[k] = has[k] ? home_of(key[k], prev.mask) : 0u;
-            }
-            for (uint32_t d = 0; d < prev.max_probe; ++d) {
-                bool any = false;
-#pragma unroll
-                for (int k = 0; k < kTB; ++k) any |= active[k];
-                if (!any) break;
-                uint32_t pf[kTB];
-                uint64_t pk[kTB];
-#pragma unroll
-                for (int k = 0; k < kTB; ++k) pf[k] = active[k] ? prev.cell_at(p[k]).fp : 0u;
-#pragma unroll
-                for (int k = 0; k < kTB; ++k) {
-                    pk[k] = 0;
-                    if (active[k] && pf[k] == lo[k].x) pk[k] = prev.key_at(p[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < kTB; ++k) {
-                    if (!active[k]) continue;
-                    if (pf[k] == 0) {
-                        active[k] = false;  // empty slot: not in prev
-                    } else if (pf[k] == lo[k].x && pk[k] == key[k]) {
-                        active[k] = false;
-                        found[k] = true;
-                    } else {
-                        p[k] = (p[k] + 1) & prev.mask;
-                    }
-                }
-            }
-            float4 old[kTB];
-            bool use[kTB];
-#pragma unroll
-            for (int k = 0; k < kTB; ++k) {
-                if (found[k]) old[k] = prev.blend_at(p[k]);
-                use[k] = found[k];
-            }
-            if constexpr (kLevels) {
-                for (int k = 0; k < kTB; ++k)
-                    if (has[k] && !found[k]) use[k] = find_across_levels<kIntegrate>(prev, key[k], old[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < kTB; ++k) {
-                if (!use[k]) continue;
-                float al = alpha, be = beta;
-                if constexpr (kIntegrate) {
-                    // counts are exact integers in binary32 (at most 2^24)
-                    const float nsum = old[k].w + (float)cnt[k];
-                    al = old[k].w / nsum;
-                    be = 1.0f - al;
-                    const uint32_t n = (uint32_t)nsum;
-                    keep[k] = n < cap ? n : cap;
-                }
-                const float a0 = al * old[k].x, a1 = al * old[k].y, a2 = al * old[k].z;
-                const float b0 = be * v[k][0], b1 = be * v[k][1], b2 = be * v[k][2];
-                v[k][0] = a0 + b0;
-                v[k][1] = a1 + b1;
-                v[k][2] = a2 + b2;
-                if (found[k]) ++hits;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kTB; ++k)
-            if (has[k]) cur.blend_at(s[k]) = make_float4(v[k][0], v[k][1], v[k][2], (float)keep[k]);
+        for (int k = 0; k < kTB; ++k) fp[k] = has[k] ? lo[k].x : 0u;
+        hits += blend_cells<kHasPrev, kIntegrate, kTB, kLevels>(cur, prev, s, has, key, fp, v, cnt, keep, alpha, beta,
+                                                                cap);
     }
     return hits;
 }

@@ -33,10 +33,12 @@ def table_contents(t: pf.Table):
 
 def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=False, alpha=0.2,
               idx_base=0, in_place=False, clear=True, want_fp_home=True, max_samples=None, low_density=None,
-              clear_in_lookup=None):
+              clear_in_lookup=None, temporal_in_insert=False):
     """One frame through the C ABI; returns per-vertex results and stats.
     clear_in_lookup: a table that the lookup's launch empties
-    (pf_query_average_clear) instead of the plain lookup."""
+    (pf_query_average_clear) instead of the plain lookup.
+    temporal_in_insert (with agg == "fused" and temporal): the temporal pass
+    inside the insert (pf_build_keys_insert_binned_temporal)."""
     n = g["px"].numel()
     dev = g["px"].device
     key = torch.empty(n, dtype=torch.int64, device=dev)
@@ -51,8 +53,14 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
         fp = home = None
         want_fp_home = False
         ws = torch.empty(pf.insert_workspace_bytes(n, cur.log2_slots), dtype=torch.uint8, device=dev)
-        pf.build_keys_insert_binned(cur, g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"],
-                                    f["s"], f["seed"], idx_base, g["r"], g["g"], g["b"], key, vflags, slot, ws)
+        if temporal_in_insert:
+            pf.build_keys_insert_binned_temporal(cur, g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"],
+                                                 f["cam"], f["s"], f["seed"], idx_base, g["r"], g["g"], g["b"], key,
+                                                 vflags, slot, ws, prev, alpha, max_samples or 0)
+        else:
+            pf.build_keys_insert_binned(cur, g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"],
+                                        f["cam"], f["s"], f["seed"], idx_base, g["r"], g["g"], g["b"], key, vflags,
+                                        slot, ws)
         flags_keys = None
     else:
         pf.build_keys(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], f["cam"], f["s"], f["seed"],
@@ -65,7 +73,9 @@ def gpu_frame(f, g, cur: pf.Table, prev=None, agg=0, use_slot=True, temporal=Fal
         pf.insert_accumulate_binned(cur, key, g["r"], g["g"], g["b"], vflags, slot, ws)
     else:
         pf.insert_accumulate(cur, key, g["r"], g["g"], g["b"], vflags, slot if use_slot else None, agg)
-    if temporal and max_samples is not None:
+    if temporal_in_insert:
+        assert agg == "fused" and temporal
+    elif temporal and max_samples is not None:
         pf.temporal_integrate(cur, prev, max_samples)
     elif temporal or low_density is not None:
         pf.temporal_update(cur, prev if temporal else None, alpha)

@@ -125,6 +125,25 @@ def test_argument_checks_return_before_launch(pf):
               None) == lp.PF_EINVAL   # no temporal values to look up
     assert qc(ctypes.byref(t), None, None, fake, fake, fake, fake, 5, 0, fake, fake, fake, None, ctypes.byref(t2),
               None) == lp.PF_EINVAL   # neither key nor slot
+    # the insert with the temporal pass in it: the checks of the insert, then
+    # those of the temporal pass, all before any launch
+    kt = L.pf_build_keys_insert_binned_temporal
+    big = 1 << 40
+
+    def kit(cur, prev, alpha=0.2, max_samples=0, s=0.01):
+        kp.s = s
+        return kt(ctypes.byref(cur), *([fake] * 6), None, ctypes.byref(kp), fake, fake, fake, 5, None, fake, fake,
+                  fake, big, None if prev is None else ctypes.byref(prev), ctypes.c_float(alpha), max_samples, None)
+    t5 = lp.pf_table()
+    assert L.pf_table_carve(ctypes.c_void_p(0x7C0000000000), 10, 1, 64, 24, ctypes.byref(t5)) == 0
+    assert kit(t, t5, s=0.0) == lp.PF_ERANGE                       # the insert's own checks come first
+    assert kit(t3, None) == lp.PF_EINVAL                           # no temporal values in t
+    assert kit(t, t3) == lp.PF_EINVAL                              # nor in prev
+    assert kit(t, t) == lp.PF_EINVAL                               # prev is t
+    assert kit(t, t2) == lp.PF_ERANGE                              # log2_slots differ
+    assert kit(t, t5, alpha=1.5) == lp.PF_ERANGE
+    assert kit(t, t5, max_samples=(1 << 24) + 1) == lp.PF_ERANGE
+    kp.s = 0.01
     # low-density fallback: needs the blend array and fixed-point sums, a known mode; below <= 1 is a no-op
     assert L.pf_low_density_fallback(ctypes.byref(t3), 4, 0, None) == lp.PF_EINVAL
     assert L.pf_low_density_fallback(ctypes.byref(t), 4, 2, None) == lp.PF_ERANGE

@@ -220,6 +220,53 @@ def test_temporal_integration_sixteen_frames_bit_exact(gpu, agg, max_samples):
         assert int(state[2].max()) == 40
 
 
+@pytest.mark.parametrize("max_samples", [None, 40])
+def test_temporal_in_the_insert_sixteen_frames_bit_exact(gpu, max_samples):
+    """pf_build_keys_insert_binned_temporal: the moving average (None) or
+    integration (40) done by the workgroups that finalise the cells, over
+    16 frames with double-buffered tables, each frame's table emptied by the
+    previous lookup.  Outputs, tables, temporal values and temporal-hit
+    counts equal the oracle's every frame."""
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(20), pf.Table(20)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(16):
+        f = synth.generate(wl, frame=frame, width=480 + frame, height=270)
+        f["log2_slots"] = 20
+        cur, other = tabs[frame % 2], tabs[(frame + 1) % 2]
+        print(f"[temporal in insert] max_samples={max_samples} frame {frame} n={f['px'].numel()}", flush=True)
+        res = gpu_frame(f, to_dev(f), cur, prev=other if frame else None, agg="fused", temporal=True,
+                        alpha=wl.alpha_old, max_samples=max_samples, clear=False, clear_in_lookup=other,
+                        temporal_in_insert=True)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old,
+                                max_samples=max_samples)
+        check_frame_against_oracle(res, R, cur)
+        if frame:
+            assert int(res["stats"][pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, state[0]).sum())
+        state = R.state
+
+
+def test_temporal_in_the_insert_full_hd(gpu):
+    """The same at 1080p x3 with 2^22-slot tables (the benchmark's launch),
+    three frames of the moving average."""
+    wl = synth.get("hd_1080p_x3")
+    tabs = [pf.Table(22), pf.Table(22)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(3):
+        f = synth.generate(wl, frame=frame, device="cuda")
+        cur, other = tabs[frame % 2], tabs[(frame + 1) % 2]
+        print(f"[temporal in insert] 1080p frame {frame}", flush=True)
+        res = gpu_frame(f, to_dev(f), cur, prev=other if frame else None, agg="fused", temporal=True,
+                        alpha=wl.alpha_old, clear=False, clear_in_lookup=other, temporal_in_insert=True)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=wl.alpha_old)
+        check_frame_against_oracle(res, R, cur)
+        state = R.state
+
+
 def test_temporal_full_hd_three_frames(gpu):
     wl = synth.get("hd_1080p_x3")
     tabs = [pf.Table(22), pf.Table(22)]

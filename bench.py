@@ -297,6 +297,11 @@ def main():
     spread = {nm: [round(float(np.percentile([events[k][j].elapsed_time(events[k][j + 1]) * 1e3
                                               for k in range(a.steps)], q)), 2) for q in (10, 50, 90)]
               for j, nm in enumerate(names)}
+    # the slowest timed frame of each stage and its index (0 = first timed frame)
+    slowest = {}
+    for j, nm in enumerate(names):
+        t = [events[k][j].elapsed_time(events[k][j + 1]) * 1e3 for k in range(a.steps)]
+        slowest[nm] = [round(float(max(t)), 2), int(np.argmax(t))]
     valid_total = sum(n_valid[(a.warmup + k) % len(frames)] for k in range(a.steps))
     ms_per_step = wall * 1e3 / a.steps
     value = valid_total / wall
@@ -426,6 +431,7 @@ def main():
         "insert_query_vertices_per_s": round(nv / t_iq, 1),
         "kernel_us": {k: round(v, 2) for k, v in per.items()},
         "kernel_us_p10_p50_p90": spread,
+        "kernel_us_max_at_frame": slowest,
         "segments": segments(dev, frames[(a.warmup + a.steps - 1) % len(frames)], view, wl),
         "cells_last_frame": cells,
         "rmse": {"unfiltered": round(q_noisy, 5), "filtered": round(q_plain, 5), "filtered_temporal": round(q_temporal, 5)},

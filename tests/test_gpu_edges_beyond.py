@@ -1,6 +1,7 @@
 """Edge cases of the entry points beyond the hot path, on the GPU against the
 oracle: a 16-slot table whose probe runs wrap from the last slot to the first
-(low-density fallbacks, both modes), a 16-slot history fought over for four
+(low-density fallbacks, both modes, and the temporal blend done in the insert
+with the lookup that empties the other table), a 16-slot history fought over for four
 frames, and empty or single-vertex inputs of the multi-level calls and the
 pixel resolve."""
 import numpy as np
@@ -99,3 +100,52 @@ def test_multilevel_and_resolve_empty_and_single(gpu):
     pf.resolve_pixels(one, one, one, None, None, 5, 0, img, accumulate=False)
     torch.cuda.synchronize()
     assert all(bool((x == 0.0).all()) for x in img)
+
+
+def test_temporal_in_the_insert_and_lookup_clear_in_16_slot_tables(gpu):
+    """The fused insert with the temporal blend, and the lookup that empties
+    the other table, on two 16-slot tables whose probe runs wrap: four frames
+    (clouds A, A, B, A) against the oracle, frame 1 finding every key of
+    frame 0 in the previous table."""
+    clouds = []
+    for seed in range(200):
+        f = synth.mixed_normals_frame(12, seed, 0.4, spread=0.3, log2_slots=4)
+        f["max_probe"] = 16
+        R = oracle.filter_frame(f, temporal=False)
+        if len(R.gkey) <= 14 and R.table.order_free:
+            clouds.append(f)
+        if len(clouds) == 2:
+            break
+    assert len(clouds) == 2
+    tabs = [pf.Table(4, max_probe=16), pf.Table(4, max_probe=16)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame, which in enumerate((0, 0, 1, 0)):
+        f = clouds[which]
+        cur, other = tabs[frame % 2], tabs[(frame + 1) % 2]
+        print(f"[16-slot temporal in insert] frame {frame} cloud {which}", flush=True)
+        res = gpu_frame(f, to_dev(f), cur, prev=other if frame else None, agg="fused", temporal=True, alpha=0.2,
+                        clear=False, clear_in_lookup=other, temporal_in_insert=True)
+        R = oracle.filter_frame(f, prev_state=state, temporal=True, alpha_old=0.2)
+        check_frame_against_oracle(res, R, cur)
+        if frame == 1:
+            assert int(res["stats"][pf.STAT_TEMPORAL_HIT]) == len(R.gkey) > 0
+        assert int(other.occupancy().abs().sum()) == 0
+        state = R.state
+
+
+def test_temporal_in_the_insert_with_no_vertices(gpu):
+    """n == 0: nothing is launched and the table keeps its contents."""
+    f, _ = _small_cloud()
+    t, p = pf.Table(4, max_probe=16), pf.Table(4, max_probe=16)
+    pf.table_init(t); pf.table_init(p)
+    gpu_frame(f, to_dev(f), t, agg=64)
+    before = t.arena.clone()
+    e = torch.empty(0, device="cuda")
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    pf.build_keys_insert_binned_temporal(t, e, e, e, e, e, e, None, f["cam"], f["s"], f["seed"], 0, e, e, e, None,
+                                         torch.empty(0, dtype=torch.uint8, device="cuda"),
+                                         torch.empty(0, dtype=torch.int32, device="cuda"), ws, p, 0.2)
+    torch.cuda.synchronize()
+    assert torch.equal(t.arena, before)

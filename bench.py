@@ -389,10 +389,10 @@ def main():
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
-    launches = {"insert_accumulate": ("aggregate, colscan, binscan, scatter, reduce" if a.insert == "binned"
-                                      else "insert"),
-                "build_keys_insert": "aggregate (keys built in it), colscan, binscan, scatter, reduce",
-                "build_keys_insert_temporal": "aggregate (keys built in it), colscan, binscan, scatter, "
+    launches = {"insert_accumulate": ("aggregate, colscan, scatter (bin starts scanned in it), reduce"
+                                      if a.insert == "binned" else "insert"),
+                "build_keys_insert": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), reduce",
+                "build_keys_insert_temporal": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), "
                                               "reduce (temporal blend in it)"}
     roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -244,7 +244,7 @@ pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const 
                                       void *workspace, size_t workspace_bytes, void *stream);
 
 /* pf_build_keys_insert_binned followed by the temporal pass of the frame
- * (Section 3.4.1) in the same five launches: the workgroup that owns a bin
+ * (Section 3.4.1) in the same four launches: the workgroup that owns a bin
  * of slots, once it has added the bin's records to its cells, computes each
  * cell's average and blends it with the value of the same key in prev (NULL:
  * no previous frame, the temporal value is the average), storing the

@@ -16,8 +16,9 @@
 //              in the tile's histogram of slot bins; every vertex receives
 //              its group's slot
 //   colscan    per bin: running record offsets over the tiles, bin totals
-//   binscan    start offset of every bin (one workgroup)
-//   scatter    per tile: staged records moved to their bin's range
+//   scatter    per tile: the start offset of every bin (each workgroup scans
+//              the bin totals itself), then staged records moved to their
+//              bin's range
 //   reduce     per bin (a contiguous slot range): records summed in LDS, then
 //              count and sums added to the cells with plain loads and stores
 //              by the workgroup that owns them, occupancy bits set; with a
@@ -379,39 +380,15 @@ __global__ __launch_bounds__(kScanBins *kScanRows) void colscan_kernel(uint32_t 
     if (cy == kScanRows - 1 && bin < nbins) total[bin] = run;
 }
 
-// Exclusive scan of the bin totals (one workgroup).
-__global__ __launch_bounds__(1024) void binscan_kernel(const uint32_t *__restrict__ total, uint32_t nbins,
-                                                       uint32_t *__restrict__ start) {
-    __shared__ uint32_t part[1024];
-    const uint32_t per = (nbins + 1023) / 1024;
-    const uint32_t b0 = threadIdx.x * per;
-    uint32_t local = 0;
-    for (uint32_t k = 0; k < per; ++k)
-        if (b0 + k < nbins) local += total[b0 + k];
-    part[threadIdx.x] = local;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - local;  // exclusive
-    for (uint32_t k = 0; k < per; ++k)
-        if (b0 + k < nbins) {
-            start[b0 + k] = run;
-            run += total[b0 + k];
-        }
-}
-
 constexpr uint32_t kBatch = 4;  // records per thread loaded before any is moved
 
 __global__ __launch_bounds__(kT) void scatter_kernel(const Rec *__restrict__ trec, const uint32_t *__restrict__ ntr,
                                                      uint32_t tile, uint32_t nbins, uint32_t bin_shift,
                                                      const uint32_t *__restrict__ H,
-                                                     const uint32_t *__restrict__ start, Rec *__restrict__ rec) {
+                                                     const uint32_t *__restrict__ total, uint32_t *__restrict__ start,
+                                                     Rec *__restrict__ rec) {
     extern __shared__ uint32_t cursor[];
+    __shared__ uint32_t part[kT];
     const uint4 *in = reinterpret_cast<const uint4 *>(trec + (size_t)blockIdx.x * tile);
     const uint32_t m = ntr[blockIdx.x];
     uint4 lo[kBatch], hi[kBatch];
@@ -423,8 +400,31 @@ __global__ __launch_bounds__(kT) void scatter_kernel(const Rec *__restrict__ tre
             hi[u] = in[2 * j + 1];
         }
     }
+    // every workgroup scans the bin totals itself (a few KB, L2-resident)
+    // instead of waiting for a launch of its own; workgroup 0 stores the
+    // bins' start offsets for reduce.  Each lane takes `per` consecutive
+    // bins; a Hillis-Steele scan runs over the lanes' partial sums.
     const uint32_t *row = H + (size_t)blockIdx.x * nbins;
-    for (uint32_t k = threadIdx.x; k < nbins; k += kT) cursor[k] = start[k] + row[k];
+    const uint32_t per = (nbins + kT - 1) / kT;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nbins) local += total[b0 + k];
+    part[threadIdx.x] = local;
+    __syncthreads();
+    for (uint32_t off = 1; off < kT; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - local;  // exclusive
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nbins) {
+            cursor[b0 + k] = run + row[b0 + k];
+            if (blockIdx.x == 0) start[b0 + k] = run;
+            run += total[b0 + k];
+        }
     __syncthreads();
     for (uint32_t j0 = 0; j0 < m; j0 += kBatch * kT) {
         if (j0) {
@@ -631,9 +631,8 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
                                                                    p.nbins, p.bin_shift, H, ntr, trec, fk);
     colscan_kernel<<<(p.nbins + kScanBins - 1) / kScanBins, kScanBins * kScanRows, 0, st>>>(H, p.ntiles, p.nbins,
                                                                                           tot);
-    binscan_kernel<<<1, 1024, 0, st>>>(tot, p.nbins, start);
-    scatter_kernel<<<p.ntiles, kT, (size_t)p.nbins * 4, st>>>(trec, ntr, p.tile, p.nbins, p.bin_shift, H, start,
-                                                              rec);
+    scatter_kernel<<<p.ntiles, kT, (size_t)p.nbins * 4, st>>>(trec, ntr, p.tile, p.nbins, p.bin_shift, H, tot,
+                                                              start, rec);
     const Blend none{};
     const Blend &bl = blend ? *blend : none;
     if (!blend)

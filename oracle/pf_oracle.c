@@ -219,7 +219,9 @@ void orc_build_keys(uint64_t n,
         int inrange = 1;
         for (int c = 0; c < 3; ++c) {
             float f = floorf(xp[c] / hp);
-            if (!(f >= -(float)ORC_QMAX && f < (float)ORC_QMAX)) { inrange = 0; q[c] = 0; }
+            /* |x~| < 2^16 on both sides: -2^16 would fit the 17-bit field, but
+             * no neighbour or child search could then reach that voxel */
+            if (!(f > -(float)ORC_QMAX && f < (float)ORC_QMAX)) { inrange = 0; q[c] = 0; }
             else q[c] = (int32_t)f;
         }
         if (lvl) { lvl[2 * i] = l; lvl[2 * i + 1] = lp; }

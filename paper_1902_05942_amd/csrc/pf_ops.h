@@ -49,7 +49,7 @@ __device__ __forceinline__ uint8_t vertex_key(const float x[3], const float nr[3
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float f = floorf(xp[c] / hp);
-        inrange = inrange && (f >= -kCellIndexLimit) && (f < kCellIndexLimit);
+        inrange = inrange && (f > -kCellIndexLimit) && (f < kCellIndexLimit);  // |x~| < 2^16
         q[c] = inrange ? (int32_t)f : 0;
     }
     if (!inrange) return PF_V_KEYRANGE;

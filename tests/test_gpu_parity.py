@@ -89,6 +89,31 @@ def test_build_keys_edge_cases(gpu):
     assert seen == {0, pf.V_INVALID, pf.V_KEYRANGE}
 
 
+@pytest.mark.parametrize("agg", [0, "fused"])
+def test_key_range_boundary(gpu, agg):
+    """x'/h on either side of +-2^16: the GPU flags exactly the vertices the
+    oracle flags (|x~| >= 2^16), through the key kernel and the fused insert,
+    and filters the extreme cells -65535 and 65535 like any other."""
+    from test_oracle_keys import key_range_boundary_frame
+    pos, nrm, s, want = key_range_boundary_frame()
+    n = len(pos)
+    f = {"px": pos[:, 0].copy(), "py": pos[:, 1].copy(), "pz": pos[:, 2].copy(),
+         "nx": nrm[:, 0].copy(), "ny": nrm[:, 1].copy(), "nz": nrm[:, 2].copy(),
+         "r": np.linspace(0.1, 2.0, n).astype(np.float32), "g": np.ones(n, np.float32),
+         "b": np.full(n, 0.5, np.float32), "valid": np.ones(n, np.uint8), "cam": (0.0, 0.0, 0.0), "s": s,
+         "seed": 0x1902, "log2_slots": 10, "max_probe": 64, "frac_bits": 24}
+    print(f"[keyrange] agg={agg} n={n}", flush=True)
+    g = to_dev(f)
+    t = pf.Table(10)
+    pf.table_init(t)
+    res = gpu_frame(f, g, t, agg=agg)
+    R = oracle.filter_frame(f, temporal=False)
+    check_frame_against_oracle(res, R, t)
+    ok = np.array([q is not None for q in want])
+    assert np.array_equal(res["flags"] == pf.V_KEYRANGE, ~ok)
+    assert np.all(res["flags"][ok] == 0) and np.all(res["cnt"][ok] >= 1)
+
+
 @pytest.mark.parametrize("case,agg,use_slot", [
     ("tiny", 0, True), ("tiny", 64, False), ("tiny", 256, True),
     ("scaled_ragged", 0, False), ("scaled_ragged", 4, True), ("scaled_ragged", 64, True),

@@ -197,6 +197,45 @@ def test_keyrange_flag():
     assert k["key"][2] == 0 and k["fp"][2] == 0
 
 
+def key_range_boundary_frame():
+    """Vertices whose x'/h lands exactly on either side of +-2^16 (x~ = floor(x'/h)).
+
+    With s = 1.5 * 2^-16, a vertex at X = m * s * 2^k on the x axis (camera at
+    the origin) lies at distance 1.5 * 2^k * m / 2^16, so its level is k for
+    m near 2^16; its normal +x makes the jitter's x component exactly zero, so
+    x'/h = m exactly and x~ = floor(m).  Returns (pos, nrm, s, expected x~ or
+    None where the key cannot hold it, |x~| >= 2^16)."""
+    s = 1.5 * 2.0 ** -16
+    ms = [-65536.5, -65536.0, -65535.5, -65535.0, -65534.5, 65534.5, 65535.0, 65535.5, 65536.0, 65536.5]
+    pos, want = [], []
+    for k in (-3, 0, 5):
+        for m in ms:
+            x = m * s * 2.0 ** k
+            assert float(np.float32(x)) == x           # exact: at most 19 significant bits
+            pos.append([x, 0.0, 0.0])
+            q = int(np.floor(m))
+            want.append(q if -65536 < q < 65536 else None)
+    nrm = np.tile(np.array([[1.0, 0.0, 0.0]], np.float32), (len(pos), 1))
+    return np.array(pos, np.float32), nrm, s, want
+
+
+def test_key_range_boundary_is_symmetric():
+    """|x~| < 2^16 (reading of Algorithm 1's quantisation with a 17-bit field
+    per coordinate): x'/h in [-2^16, -2^16 + 1) is out of range like
+    [2^16, 2^16 + 1), while -65535 and 65535 are the extreme cells kept."""
+    pos, nrm, s, want = key_range_boundary_frame()
+    k = _keys(pos, nrm, cam=(0.0, 0.0, 0.0), s=s)
+    lv = np.repeat([-3, 0, 5], len(want) // 3)
+    assert np.array_equal(k["lvl"][:, 0], lv) and np.array_equal(k["lvl"][:, 1], lv)
+    for i, q in enumerate(want):
+        if q is None:
+            assert k["flags"][i] == oracle.KEYRANGE and k["key"][i] == 0, (i, pos[i, 0])
+        else:
+            assert k["flags"][i] == 0, (i, pos[i, 0])
+            assert _unpack(k["key"][i])[0] == q and _unpack(k["key"][i])[3] == lv[i]
+    assert sum(q is None for q in want) == 15 and {-65535, 65535} <= {q for q in want if q is not None}
+
+
 def test_invalid_inputs_are_flagged():
     pos = np.array([[0.5, 0, 0.5], [np.nan, 0, 0], [0.5, 0, 0.5], [0.5, 0, np.inf]], np.float32)
     nrm = np.array([[0, 1, 0], [0, 1, 0], [0, np.nan, 0], [0, 1, 0]], np.float32)

@@ -243,6 +243,27 @@ pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const 
                                       uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
                                       void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * keys, flags, slots and table as pf_build_keys_insert_binned, without a
+ * workspace argument.  Its workspace is the library's own device array of
+ * PF_NOALLOC_SCRATCH_BYTES, set up once per device at the first call on it
+ * and held until the process ends; vertices go through it in consecutive
+ * batches of at most PF_NOALLOC_BATCH (the insert accumulates, so the table
+ * is the one a single call gives).  Never allocates or frees.  All calls on
+ * one device share the array: calls that overlap in time on one device
+ * (different streams, or host threads without ordering) race.
+ * Errors: those of pf_build_keys_insert_binned except the workspace's;
+ * PF_ERANGE (log2_slots > 25); PF_ELAUNCH (the array's address could not be
+ * obtained, or a launch failed). */
+#define PF_NOALLOC_SCRATCH_BYTES (80ull << 20)
+#define PF_NOALLOC_BATCH (1u << 20)
+pf_status pf_build_keys_insert_binned_noalloc(const pf_table *t, const float *px, const float *py, const float *pz,
+                                              const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                              const pf_key_params *kp, const float *r, const float *g, const float *b,
+                                              uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                              void *stream);
+
 /* pf_build_keys_insert_binned followed by the temporal pass of the frame
  * (Section 3.4.1) in the same four launches: the workgroup that owns a bin
  * of slots, once it has added the bin's records to its cells, computes each

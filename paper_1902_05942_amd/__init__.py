@@ -19,7 +19,8 @@ from ._lib import (SLOT_BYTES, STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORA
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
                    query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS,
-                   query_average_clear, build_keys_insert_binned_temporal)
+                   query_average_clear, build_keys_insert_binned_temporal,
+                   build_keys_insert_binned_noalloc, NOALLOC_SCRATCH_BYTES, NOALLOC_BATCH)
 
 
 class MlpFallback:

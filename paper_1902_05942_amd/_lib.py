@@ -91,6 +91,8 @@ def _load():
         "pf_insert_accumulate_binned": ([T, vp, vp, vp, vp, vp, vp, u64, vp, ctypes.c_size_t, vp], i),
         "pf_build_keys_insert_binned": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp, vp, vp,
                                                           vp, ctypes.c_size_t, vp], i),
+        "pf_build_keys_insert_binned_noalloc": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp,
+                                                                  vp, vp, vp], i),
         "pf_query_average": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, vp], i),
         "pf_query_average_clear": ([T, vp, vp, vp, vp, vp, vp, u64, i, vp, vp, vp, vp, T, vp], i),
         "pf_build_keys_insert_binned_temporal": ([T] + [vp] * 7 + [ctypes.POINTER(pf_key_params), vp, vp, vp, u64, vp,
@@ -137,7 +139,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
             "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
             "pf_temporal_history", "pf_resolve_pixels", "pf_query_average_clear",
-            "pf_build_keys_insert_binned_temporal")
+            "pf_build_keys_insert_binned_temporal", "pf_build_keys_insert_binned_noalloc")
 
 
 def _ptr(t):
@@ -261,6 +263,24 @@ def build_keys_insert_binned(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, se
         t.ref, _ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(valid), ctypes.byref(kp), _ptr(r),
         _ptr(g), _ptr(b), vflags.numel(), _ptr(key), _ptr(vflags), _ptr(slot_out), _ptr(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES, NOALLOC_BATCH = 80 << 20, 1 << 20
+
+
+def build_keys_insert_binned_noalloc(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b, key,
+                                     vflags, slot_out, stream=None):
+    """build_keys_insert_binned without a workspace argument: the library's
+    own device scratch (shared by every call on the device) serves as it."""
+    kp = pf_key_params()
+    for c in range(3):
+        kp.cam[c] = float(cam[c])
+    kp.s = float(s)
+    kp.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    kp.idx_base = int(idx_base)
+    _check("pf_build_keys_insert_binned_noalloc", lib.pf_build_keys_insert_binned_noalloc(
+        t.ref, _ptr(px), _ptr(py), _ptr(pz), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(valid), ctypes.byref(kp), _ptr(r),
+        _ptr(g), _ptr(b), vflags.numel(), _ptr(key), _ptr(vflags), _ptr(slot_out), _stream(stream)))
 
 
 def build_keys_insert_binned_temporal(t: Table, px, py, pz, nx, ny, nz, valid, cam, s, seed, idx_base, r, g, b, key,

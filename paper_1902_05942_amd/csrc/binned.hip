@@ -26,6 +26,8 @@
 //              also blends each cell's final average with the previous
 //              table's value of its key and stores the temporal value
 // Integer sums make the result identical to the atomic insert.
+#include <mutex>
+
 #include "pf_kernels.h"
 #include "pf_merge.h"
 #include "pf_ops.h"
@@ -682,6 +684,72 @@ hipError_t launch_keys_insert_binned_temporal(const Tab &t, const float *px, con
     bl.beta = 1.0f - alpha_old;
     bl.cap = cap;
     return binned::run<true>(t, nullptr, r, g, b, flags, slot_out, n, ws, fk, &bl, prev != nullptr, mode == 1, st);
+}
+
+// ---- the insert without a workspace argument, for callers that cannot
+// allocate.  Its workspace is a file-scope device array; on the host the
+// array's name is not a device address, so every use goes through the
+// address hipGetSymbolAddress returns for the current device (kept per
+// device).  All calls on one device share the array: calls that overlap in
+// time on one device (different streams, or host threads) race.
+
+namespace binned {
+
+constexpr uint32_t kNoAllocBatch = PF_NOALLOC_BATCH;  // vertices per pass over the scratch
+constexpr size_t kScratchBytes = PF_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex scratch_mutex;
+static void *scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch`, looked up once per device.
+static hipError_t scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace binned
+
+bool noalloc_fits(uint32_t log2_slots) {
+    return log2_slots <= binned::kMaxLog2Slots &&
+           binned::make_plan(binned::kNoAllocBatch, log2_slots).bytes + 256 <= binned::kScratchBytes;
+}
+
+hipError_t launch_keys_insert_binned_noalloc(const Tab &t, const float *px, const float *py, const float *pz,
+                                             const float *nx, const float *ny, const float *nz,
+                                             const uint8_t *valid, const KeyArgs &a, uint64_t *key_out,
+                                             const float *r, const float *g, const float *b, uint8_t *flags,
+                                             uint32_t *slot_out, uint32_t n, hipStream_t st) {
+    void *ws = nullptr;
+    hipError_t e = binned::scratch_address(&ws);
+    if (e != hipSuccess) return e;
+    // the insert accumulates, so consecutive batches give the table one
+    // call would; each batch's workspace is written before it is read
+    for (uint32_t i0 = 0; i0 < n; i0 += binned::kNoAllocBatch) {
+        const uint32_t m = n - i0 < binned::kNoAllocBatch ? n - i0 : binned::kNoAllocBatch;
+        KeyArgs ab = a;
+        ab.idx_base = a.idx_base + i0;
+        const binned::FusedKeys fk{px + i0, py + i0, pz + i0, nx + i0, ny + i0, nz + i0,
+                                   valid ? valid + i0 : nullptr, ab, key_out ? key_out + i0 : nullptr};
+        e = binned::run<true>(t, nullptr, r + i0, g + i0, b + i0, flags + i0, slot_out + i0, m, ws, fk, nullptr,
+                              false, false, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pfk

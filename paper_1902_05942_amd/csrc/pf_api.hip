@@ -166,6 +166,9 @@ pf_status pf_insert_accumulate_binned(const pf_table *t, const uint64_t *key, co
                                               (hipStream_t)stream));
 }
 
+// workspace_bytes of check_keys_insert for a call without a workspace
+constexpr size_t kNoWorkspace = ~(size_t)0;
+
 // The checks of pf_build_keys_insert_binned; fills a.  PF_OK with *empty
 // set when n == 0 (nothing to launch).
 static pf_status check_keys_insert(const pf_table *t, const float *px, const float *py, const float *pz,
@@ -181,13 +184,16 @@ static pf_status check_keys_insert(const pf_table *t, const float *px, const flo
     if (!(kp->s > 0.0f) || !isfinite(kp->s) || !isfinite(kp->cam[0]) || !isfinite(kp->cam[1]) ||
         !isfinite(kp->cam[2]))
         return PF_ERANGE;
+    // no_workspace: the no-allocation variant, whose workspace is the
+    // library's own scratch (checked by the caller)
+    const bool no_workspace = workspace == nullptr && workspace_bytes == kNoWorkspace;
     const size_t need = pf_insert_workspace_bytes(n, t->log2_slots);
     if (need == 0) return PF_ERANGE;
     empty = n == 0;
     if (empty) return PF_OK;
-    if (!px || !py || !pz || !nx || !ny || !nz || !r || !g || !b || !vflags || !slot_out || !workspace ||
-        workspace_bytes < need)
+    if (!px || !py || !pz || !nx || !ny || !nz || !r || !g || !b || !vflags || !slot_out)
         return PF_EINVAL;
+    if (!no_workspace && (!workspace || workspace_bytes < need)) return PF_EINVAL;
     if (!aligned(px) || !aligned(py) || !aligned(pz) || !aligned(nx) || !aligned(ny) || !aligned(nz) ||
         !aligned(r) || !aligned(g) || !aligned(b) || !aligned(slot_out) || (key && !aligned(key)))
         return PF_EINVAL;
@@ -211,6 +217,22 @@ pf_status pf_build_keys_insert_binned(const pf_table *t, const float *px, const 
     if (s != PF_OK || empty) return s;
     return launched(pfk::launch_keys_insert_binned(to_tab(t), px, py, pz, nx, ny, nz, valid, a, key, r, g, b, vflags,
                                                    slot_out, (uint32_t)n, workspace, (hipStream_t)stream));
+}
+
+pf_status pf_build_keys_insert_binned_noalloc(const pf_table *t, const float *px, const float *py, const float *pz,
+                                              const float *nx, const float *ny, const float *nz, const uint8_t *valid,
+                                              const pf_key_params *kp, const float *r, const float *g, const float *b,
+                                              uint64_t n, uint64_t *key, uint8_t *vflags, uint32_t *slot_out,
+                                              void *stream) {
+    pfk::KeyArgs a;
+    bool empty = false;
+    const pf_status s = check_keys_insert(t, px, py, pz, nx, ny, nz, kp, r, g, b, n, key, vflags, slot_out, nullptr,
+                                          kNoWorkspace, a, empty);
+    if (s != PF_OK) return s;
+    if (!pfk::noalloc_fits(t->log2_slots)) return PF_ERANGE;
+    if (empty) return PF_OK;
+    return launched(pfk::launch_keys_insert_binned_noalloc(to_tab(t), px, py, pz, nx, ny, nz, valid, a, key, r, g, b,
+                                                           vflags, slot_out, (uint32_t)n, (hipStream_t)stream));
 }
 
 pf_status pf_build_keys_insert_binned_temporal(const pf_table *t, const float *px, const float *py, const float *pz,

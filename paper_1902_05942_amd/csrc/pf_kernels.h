@@ -67,6 +67,12 @@ hipError_t launch_keys_insert_binned_temporal(const Tab &t, const float *px, con
                                               const float *r, const float *g, const float *b, uint8_t *flags,
                                               uint32_t *slot_out, uint32_t n, void *ws, const Tab *prev,
                                               float alpha_old, int mode, uint32_t cap, hipStream_t st);
+bool noalloc_fits(uint32_t log2_slots);
+hipError_t launch_keys_insert_binned_noalloc(const Tab &t, const float *px, const float *py, const float *pz,
+                                             const float *nx, const float *ny, const float *nz,
+                                             const uint8_t *valid, const KeyArgs &a, uint64_t *key_out,
+                                             const float *r, const float *g, const float *b, uint8_t *flags,
+                                             uint32_t *slot_out, uint32_t n, hipStream_t st);
 hipError_t launch_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint64_t accesses, uint64_t seed,
                              uint32_t *sink, hipStream_t st);
 hipError_t launch_views(const pf_view *views_dev, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,

@@ -265,7 +265,7 @@ pf_status pf_build_keys_insert_binned_noalloc(const pf_table *t, const float *px
                                               void *stream);
 
 /* pf_build_keys_insert_binned followed by the temporal pass of the frame
- * (Section 3.4.1) in the same four launches: the workgroup that owns a bin
+ * (Section 3.4.1) in the same launches: the workgroup that owns a bin
  * of slots, once it has added the bin's records to its cells, computes each
  * cell's average and blends it with the value of the same key in prev (NULL:
  * no previous frame, the temporal value is the average), storing the
@@ -617,17 +617,19 @@ size_t pf_views_workspace_bytes(uint32_t nviews);
  * resident workgroups of `block` threads): per view it clears `cur`, builds
  * the keys and inserts every vertex (as pf_build_keys + pf_insert_accumulate;
  * agg_width 0: one claim and one set of device atomics per vertex; nonzero:
- * each workgroup merges sub-chunks of 2 x block consecutive vertices by key
- * in LDS -- runs of equal keys across a wavefront first -- and each group
+ * each workgroup merges windows of agg_width consecutive vertices by key in
+ * an LDS table of min(agg_width, 4 x block, 1536) entries, and each group
  * claims its cell once and adds its count and sums with one set of device
- * atomics), computes the temporal values when
+ * atomics; a vertex that finds no room goes alone), computes the temporal
+ * values when
  * temporal is set (as pf_temporal_update, mode 0), and looks up every vertex
  * (as pf_query_average with the slots).  Phases are separated by grid-wide
  * barriers; the work items of all views are spread over all workgroups.
  * Results equal those of the single-view calls.
  * views: [host] array of nviews descriptors, validated on the host and
  * copied into the workspace before the call returns.  block in
- * {64, 128, 256, 512, 1024}; agg_width 0 or a power of two <= block;
+ * {64, 128, 256, 512, 1024}; agg_width 0 or a power of two from block to
+ * 8 x block;
  * grid_per_cu: workgroups per compute unit (0 = as many as fit).
  * workspace: pf_views_workspace_bytes(nviews) device bytes, 256-byte
  * aligned; its first uint32 is a status word, non-zero if a barrier wait

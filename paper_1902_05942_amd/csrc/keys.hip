@@ -13,13 +13,14 @@ __global__ __launch_bounds__(kBlock) void build_keys_kernel(
     uint32_t *__restrict__ fp_out, uint32_t *__restrict__ home_out, uint8_t *__restrict__ flags_out) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const PcgJump jp(a.seed, a.idx_base);
     uint64_t key = 0;
     uint32_t fp = 0, home = 0;
     uint8_t flags = PF_V_INVALID;
     if (valid == nullptr || valid[i] != 0) {  // masked vertices read nothing more
         const float x[3] = {px[i], py[i], pz[i]};
         const float nr[3] = {nx[i], ny[i], nz[i]};
-        flags = vertex_key(x, nr, true, a.cam, a.s, a.seed, a.idx_base + i, a.mask, key, fp, home);
+        flags = vertex_key(x, nr, true, a.cam, a.s, a.inv_s, jp, i, a.mask, key, fp, home);
     }
     key_out[i] = key;
     flags_out[i] = flags;

@@ -123,6 +123,7 @@ pf_status pf_build_keys(const float *px, const float *py, const float *pz, const
     pfk::KeyArgs a;
     for (int c = 0; c < 3; ++c) a.cam[c] = kp->cam[c];
     a.s = kp->s;
+    a.inv_s = 1.0f / kp->s;
     a.seed = kp->seed;
     a.idx_base = kp->idx_base;
     a.mask = (uint32_t)((1ull << log2_slots) - 1);
@@ -199,6 +200,7 @@ static pf_status check_keys_insert(const pf_table *t, const float *px, const flo
         return PF_EINVAL;
     for (int c = 0; c < 3; ++c) a.cam[c] = kp->cam[c];
     a.s = kp->s;
+    a.inv_s = 1.0f / kp->s;
     a.seed = kp->seed;
     a.idx_base = kp->idx_base;
     a.mask = (uint32_t)((1ull << t->log2_slots) - 1);
@@ -614,7 +616,10 @@ pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block,
     if (!views || !workspace || (reinterpret_cast<uintptr_t>(workspace) % 256)) return PF_EINVAL;
     if (nviews == 0 || nviews > PF_MAX_VIEWS) return PF_ERANGE;
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return PF_ERANGE;
-    if (agg_width > block || (agg_width > 1 && (agg_width & (agg_width - 1)))) return PF_ERANGE;
+    // aggregation width: 0, or a power of two from block to 8 x block (the
+    // vertices of one work item), at most 8192
+    if (agg_width != 0 && (agg_width < block || agg_width > 8 * block || (agg_width & (agg_width - 1))))
+        return PF_ERANGE;
     for (uint32_t v = 0; v < nviews; ++v) {
         const pf_status s = check_view(views[v]);
         if (s != PF_OK) return s;

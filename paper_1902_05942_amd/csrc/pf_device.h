@@ -66,6 +66,52 @@ struct Pcg32 {
     }
 };
 
+// The first three outputs of PCG32 seeded with (initstate, base + i) for the
+// vertices i of a launch, by jumping the LCG ahead instead of stepping it
+// (Brown 1994, random number generation with arbitrary strides: k steps of
+// x -> M x + c give M^k x + c (M^(k-1) + ... + 1) mod 2^64).  The standard
+// seeding leaves the state S_0 = (inc + initstate) M + inc with
+// inc = 2 (base + i) + 1, and output k is the XSH-RR permutation of
+//   S_k = initstate M^(k+1) + G_(k+1) (2 (base + i) + 1),  G_j = 1 + M + .. + M^j,
+// an affine function F_k + E_k i of i whose coefficients are the same for
+// every vertex of the launch.  The outputs equal Pcg32's exactly.
+struct PcgJump {
+    static constexpr uint64_t kM = 6364136223846793005ull;
+    static constexpr uint64_t kM2 = kM * kM, kM3 = kM2 * kM, kM4 = kM3 * kM;
+    static constexpr uint64_t kG1 = 1ull + kM, kG2 = kG1 + kM2, kG3 = kG2 + kM3;
+    uint64_t F[3], E[3];
+
+    __host__ __device__ __forceinline__ PcgJump(uint64_t initstate, uint64_t base) {
+        const uint64_t Mk[3] = {kM, kM2, kM3}, Gk[3] = {kG1, kG2, kG3};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            E[k] = 2ull * Gk[k];
+            F[k] = initstate * Mk[k] + Gk[k] * (2ull * base + 1ull);
+        }
+    }
+
+    __device__ __forceinline__ uint32_t output(int k, uint32_t i) const {
+        const uint64_t old = F[k] + E[k] * (uint64_t)i;
+        const uint32_t xs = (uint32_t)(((old >> 18) ^ old) >> 27);
+        const uint32_t rot = (uint32_t)(old >> 59);
+        return (xs >> rot) | (xs << ((32u - rot) & 31u));
+    }
+};
+
+// floor of the binary32 quotient RN(x / h) that Algorithm 1 quantises, for
+// h = s 2^l, given r = RN(1/s) 2^-l.  t = RN(x r) is within 2.0001 u |t| of
+// the exact quotient y (u = 2^-24) and RN(y) within u |y| of y, so when no
+// integer lies within 4 u |t| of t, floor(RN(y)) = floor(t); otherwise (or
+// when t is not finite) the IEEE division decides.
+__device__ __forceinline__ float floor_quotient(float x, float h, float r) {
+    const float t = x * r;
+    const float f = floorf(t);
+    const float frac = t - f;
+    const float m = 2.38418579e-7f * fabsf(t);  // 4 u |t|
+    if (frac > m && 1.0f - frac > m) return f;
+    return floorf(x / h);
+}
+
 // MurmurHash3 64-bit finaliser: the home index hash.
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
     k ^= k >> 33;

@@ -15,6 +15,7 @@ struct Hist;
 struct KeyArgs {
     float cam[3];
     float s;
+    float inv_s;  // RN(1 / s)
     uint64_t seed;
     uint64_t idx_base;
     uint32_t mask;

@@ -11,9 +11,11 @@ namespace pfk {
 
 // Key construction of Algorithm 1 for one vertex.  Returns the vertex flags
 // (0, PF_V_INVALID or PF_V_KEYRANGE); key/fp/home are 0 for flagged vertices.
+// jp holds the launch's PCG32 streams (seed, idx_base) and i is the vertex's
+// index within the launch (stream idx_base + i); inv_s = RN(1 / s).
 __device__ __forceinline__ uint8_t vertex_key(const float x[3], const float nr[3], bool valid, const float cam[3],
-                                              float s, uint64_t seed, uint64_t stream, uint32_t mask, uint64_t &key,
-                                              uint32_t &fp, uint32_t &home) {
+                                              float s, float inv_s, const PcgJump &jp, uint32_t i, uint32_t mask,
+                                              uint64_t &key, uint32_t &fp, uint32_t &home) {
     key = 0;
     fp = 0;
     home = 0;
@@ -23,10 +25,9 @@ __device__ __forceinline__ uint8_t vertex_key(const float x[3], const float nr[3
     // l <- level_of_detail(|p_cam - x|)
     const int l = level_of_detail(cam[0], cam[1], cam[2], x[0], x[1], x[2]);
     // jitter(n): cube sample projected onto the tangent plane
-    Pcg32 g(seed, stream);
     float r[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = ldexpf((float)(g.next() >> 8), -24) - 0.5f;
+    for (int c = 0; c < 3; ++c) r[c] = ldexpf((float)(jp.output(c, i) >> 8), -24) - 0.5f;
     const float t0 = r[0] * nr[0];
     const float t1 = r[1] * nr[1];
     const float t2 = r[2] * nr[2];
@@ -44,11 +45,12 @@ __device__ __forceinline__ uint8_t vertex_key(const float x[3], const float nr[3
     // l' <- level_of_detail(|p_cam - x'|); x~ <- floor(x' / (s * 2^l'))
     const int lp = level_of_detail(cam[0], cam[1], cam[2], xp[0], xp[1], xp[2]);
     const float hp = ldexpf(s, lp);
+    const float rp = ldexpf(inv_s, -lp);
     bool inrange = true;
     int32_t q[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float f = floorf(xp[c] / hp);
+        const float f = floor_quotient(xp[c], hp, rp);
         inrange = inrange && (f > -kCellIndexLimit) && (f < kCellIndexLimit);  // |x~| < 2^16
         q[c] = inrange ? (int32_t)f : 0;
     }

@@ -397,3 +397,93 @@ def test_nonfinite_and_out_of_range_radiance(gpu):
     R = oracle.filter_frame(_host(f), temporal=False)
     check_frame_against_oracle(res, R, t)
     assert set(np.unique(R.flags[10:15])) <= {0, pf.V_INVALID, pf.V_RADRANGE}
+
+
+@pytest.mark.parametrize("temporal", [False, True])
+def test_binned_bucket_parts_overflow_into_atomics(gpu, temporal):
+    """Groups whose bin's bucket part is full go to their cell by device
+    atomics.  700 cells whose slots all lie in one bin, repeated over 600
+    chunks of 4096 vertices: every chunk sends 700 records to that bin,
+    far beyond a part's share, so most groups spill.  The table, counts and
+    averages must still be the oracle's group-by bit for bit (and the
+    temporal variant must blend spilled-only cells too)."""
+    m, n, cells = 16, 600 * 4096, 700
+    cand = np.arange(1, 400000, dtype=np.uint64) * np.uint64(2654435761)
+    home, _ = oracle.key_hashes(cand, m)
+    # distinct home slots, every other one below 1900: no probe runs
+    hs, first = np.unique(home, return_index=True)
+    chosen = cand[first[hs < 1900][::2]][:cells]
+    assert len(chosen) == cells
+    idx = np.arange(n)
+    key = chosen[(idx * 7919) % cells]
+    rng = np.random.default_rng(5)
+    rgb = rng.random((3, n), dtype=np.float32)
+    valid = np.ones(n, np.uint8)
+    R = oracle.filter_keys(key, rgb[0], rgb[1], rgb[2], valid, m)
+    assert R.table.order_free and int(R.table.gslot.max()) < 2048     # every cell in bin 0
+    t = pf.Table(m, with_blend=True)
+    pf.table_init(t)
+    k = torch.from_numpy(key.view(np.int64)).cuda()
+    r, g, b = (torch.from_numpy(x).cuda() for x in rgb)
+    fl = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    slot = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(pf.insert_workspace_bytes(n, m), dtype=torch.uint8, device="cuda")
+    pf.insert_accumulate_binned(t, k, r, g, b, fl, slot, ws)
+    if temporal:
+        pf.temporal_update(t, None, 0.2)
+    out = [torch.empty(n, device="cuda") for _ in range(3)]
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    pf.query_average(t, k, slot, r, g, b, fl, temporal, out[0], out[1], out[2], cnt)
+    torch.cuda.synchronize()
+    tc = table_contents(t)
+    order = np.argsort(tc["key"])
+    assert_bits_equal(tc["key"][order], R.gkey, "table keys")
+    assert_bits_equal(tc["count"][order], R.gcnt, "table counts")
+    assert_bits_equal(tc["sum"][order], R.gsum, "table sums")
+    assert_bits_equal(tc["occupied"], R.table.occupied, "occupied slots")
+    assert_bits_equal(cnt.cpu().numpy().view(np.uint32), R.cnt, "lookup counts")
+    assert_bits_equal(np.stack([o.cpu().numpy() for o in out], 1), R.out, "lookup averages")
+
+
+def test_fused_temporal_insert_with_spilled_cells(gpu):
+    """The temporal blend done in the insert must also blend cells that only
+    spilled groups reached.  Vertices sit at the centres of 600 voxels whose
+    home slots all lie in the first bin of a 2^16-slot table (level 9 for
+    every vertex: the camera is 690 .. 912 units away), repeated over 600
+    chunks, so the bin's bucket parts overflow; two frames, against the
+    oracle bit for bit."""
+    m, n, cells = 16, 600 * 4096, 600
+    s, lvl = 0.01, 9
+    h = float(np.ldexp(np.float32(s), lvl))
+    g = np.arange(-20, 21)
+    q = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.int64)
+    code = 1 << 2                                    # normal (0, 1, 0): class 1 on y
+    key = ((q[:, 0] + 65536) | ((q[:, 1] + 65536) << 17) | ((q[:, 2] + 65536) << 34) | ((lvl + 16) << 51)
+           | (code << 56)).astype(np.uint64)
+    home, _ = oracle.key_hashes(key, m)
+    # distinct home slots, every other one below 1900: no probe runs
+    hs, first = np.unique(home, return_index=True)
+    pick = first[hs < 1900][::2][:cells]
+    assert len(pick) == cells
+    qc = q[pick][(np.arange(n) * 7919) % cells]
+    pos = ((qc.astype(np.float64) + 0.5) * h).astype(np.float32)
+    rng = np.random.default_rng(9)
+    tabs = [pf.Table(m), pf.Table(m)]
+    for t in tabs:
+        pf.table_init(t)
+    state = None
+    for frame in range(2):
+        rgb = rng.random((3, n), dtype=np.float32)
+        f = {"px": torch.from_numpy(pos[:, 0].copy()), "py": torch.from_numpy(pos[:, 1].copy()),
+             "pz": torch.from_numpy(pos[:, 2].copy()), "nx": torch.zeros(n), "ny": torch.ones(n),
+             "nz": torch.zeros(n), "r": torch.from_numpy(rgb[0]), "g": torch.from_numpy(rgb[1]),
+             "b": torch.from_numpy(rgb[2]), "valid": torch.ones(n, dtype=torch.uint8),
+             "cam": (0.0, 0.0, -800.0), "s": s, "seed": 77 + frame, "log2_slots": m, "max_probe": 64,
+             "frac_bits": 24}
+        cur, other = tabs[frame % 2], tabs[(frame + 1) % 2]
+        res = gpu_frame(f, to_dev(f), cur, prev=other if frame else None, agg="fused", temporal=True, alpha=0.2,
+                        clear=False, clear_in_lookup=other, temporal_in_insert=True)
+        R = oracle.filter_frame(_host(f), prev_state=state, temporal=True, alpha_old=0.2)
+        assert int((R.table.gslot < 2048).sum()) >= 590      # all but a few jittered over a border in bin 0
+        check_frame_against_oracle(res, R, cur)
+        state = R.state

@@ -14,7 +14,15 @@ import os
 import torch
 
 BLOCKS = (64, 128, 256, 512, 1024)
-AGGS = (0, 1)  # 0: device atomics per vertex; nonzero: vertices merged by key in LDS first
+# aggregation width as a multiple of the workgroup size: 0 = device atomics
+# per vertex; f > 0 = windows of f x block consecutive vertices merged by key
+# in LDS before their cells are touched
+AGG_FACTORS = (0, 1, 2, 4, 8)
+
+
+def candidates(blocks=BLOCKS, factors=AGG_FACTORS):
+    """Every (block, agg_width) pair the tuner times."""
+    return [(b, f * b) for b in blocks for f in factors]
 
 
 def cache_path() -> str:
@@ -42,7 +50,7 @@ def time_config(mvf, frames, block, agg, reps=5) -> float:
     return ts[len(ts) // 2]
 
 
-def tune(mvf, frames, blocks=BLOCKS, aggs=AGGS, reps=5, use_cache=True, verbose=False):
+def tune(mvf, frames, blocks=BLOCKS, factors=AGG_FACTORS, reps=5, use_cache=True, verbose=False):
     """Returns (block, agg_width, {(block, agg): ms})."""
     key = signature(frames)
     path = cache_path()
@@ -57,13 +65,10 @@ def tune(mvf, frames, blocks=BLOCKS, aggs=AGGS, reps=5, use_cache=True, verbose=
             c = cache[key]
             return c["block"], c["agg"], {tuple(map(int, k.split("/"))): v for k, v in c["ms"].items()}
     res = {}
-    for b in blocks:
-        for a in aggs:
-            if a > b:
-                continue
-            res[(b, a)] = time_config(mvf, frames, b, a, reps)
-            if verbose:
-                print(f"[autotune] block {b:4d} agg {a:3d}: {res[(b, a)]:.3f} ms", flush=True)
+    for b, a in candidates(blocks, factors):
+        res[(b, a)] = time_config(mvf, frames, b, a, reps)
+        if verbose:
+            print(f"[autotune] block {b:4d} agg {a:4d}: {res[(b, a)]:.3f} ms", flush=True)
     best = min(res, key=res.get)
     if use_cache:
         cache[key] = {"block": best[0], "agg": best[1], "ms": {f"{b}/{a}": v for (b, a), v in res.items()}}

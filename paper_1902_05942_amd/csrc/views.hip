@@ -105,10 +105,12 @@ __device__ bool grid_barrier(const Barrier &bar, uint32_t epoch) {
     return s_ok != 0;
 }
 
-// LDS merge table of the insert phase: a sub-chunk of 2B vertices merges into
-// at most 2B entries (1536 for B = 1024, keeping the table in static LDS).
+// LDS merge table of the insert phase: a window of agg_width consecutive
+// vertices (block .. kIters * block) merges into at most min(agg_width,
+// 4 * block, 1536) entries (the table stays in static LDS and small
+// workgroups keep their residency); a vertex that finds no room goes alone.
 template <int B>
-constexpr uint32_t kMergeCap = 2 * B < 1536 ? 2 * B : 1536;
+constexpr uint32_t kMergeCap = 4 * B < 1536 ? 4 * B : 1536;
 
 template <int B>
 struct Lds {
@@ -129,7 +131,7 @@ __device__ __forceinline__ void item_of(const Lds<B> &L, int phase, uint32_t nvi
 
 // Key, flags and fixed-point contribution of vertex i of a view (masked
 // vertices read nothing more than their valid byte).
-__device__ __forceinline__ uint8_t view_vertex(const pf_view &d, const Tab &t, uint32_t i, uint64_t &key,
+__device__ __forceinline__ uint8_t view_vertex(const pf_view &d, const Tab &t, float inv_s, uint32_t i, uint64_t &key,
                                                int64_t &q0, int64_t &q1, int64_t &q2) {
     key = 0;
     q0 = q1 = q2 = 0;
@@ -137,14 +139,20 @@ __device__ __forceinline__ uint8_t view_vertex(const pf_view &d, const Tab &t, u
     const float x[3] = {d.px[i], d.py[i], d.pz[i]};
     const float nr[3] = {d.nx[i], d.ny[i], d.nz[i]};
     uint32_t fp, home;
-    uint8_t fl = vertex_key(x, nr, true, d.kp.cam, d.kp.s, d.kp.seed, d.kp.idx_base + i, t.mask, key, fp, home);
+    const PcgJump jp(d.kp.seed, d.kp.idx_base);
+    uint8_t fl = vertex_key(x, nr, true, d.kp.cam, d.kp.s, inv_s, jp, i, t.mask, key, fp, home);
     if (fl == 0) fl = fixed_point(d.r[i], d.g[i], d.b[i], t.frac_bits, q0, q1, q2);
     return fl;
 }
 
+// At least kWavesPerSimd waves of this kernel fit a SIMD (the compiler
+// keeps the registers within that), which bounds the resident workgroups
+// from below independently of the occupancy query.
+constexpr int kWavesPerSimd = 4;
+
 template <int B>
-__global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ views, uint32_t nviews, uint32_t agg,
-                                                  Barrier bar) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd))) void views_kernel(
+    const pf_view *__restrict__ views, uint32_t nviews, uint32_t agg, Barrier bar) {
     __shared__ Lds<B> L;
     constexpr uint32_t kItem = (uint32_t)B * kIters;
     // work items per view and phase: 0 clear (B bitmap words), 1 keys +
@@ -203,15 +211,18 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
     stamp(1);
 
     // ---- phase 1: keys and insertion.  agg == 0: one claim and one set of
-    // device atomics per vertex.  Otherwise each sub-chunk of 2B vertices
-    // merges by key in LDS (runs across lanes first), then every group claims
-    // its cell once and adds its count and sums with one set of atomics.
-    constexpr uint32_t kCap = kMergeCap<B>;
+    // device atomics per vertex.  Otherwise each window of agg consecutive
+    // vertices (a power of two, block <= agg <= kIters * block) merges by key
+    // in LDS, then every group claims its cell once and adds its count and
+    // sums with one set of atomics.
+    const uint32_t kCap = agg < kMergeCap<B> ? agg : kMergeCap<B>;
+    const uint32_t per = agg / B;  // vertices per lane and window (1, 2, 4 or 8)
     for (uint32_t it = blockIdx.x; it < L.first[1][nviews]; it += G) {
         uint32_t v, local;
         item_of(L, 1, nviews, it, v, local);
         const pf_view &d = views[v];
         const Tab t = to_tab(d.cur);
+        const float inv_s = 1.0f / d.kp.s;
         if (agg == 0) {
             for (int k = 0; k < kIters; ++k) {
                 const uint32_t i = local * kItem + k * B + threadIdx.x;
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
                 uint64_t key;
                 int64_t q0 = 0, q1 = 0, q2 = 0;
                 uint32_t slot = kNoSlot;
-                uint8_t fl = view_vertex(d, t, i, key, q0, q1, q2);
+                uint8_t fl = view_vertex(d, t, inv_s, i, key, q0, q1, q2);
                 if (fl == 0) {
                     slot = find_or_claim(t, key);
                     if (slot == kNoSlot) {
@@ -235,8 +246,8 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
             }
             continue;
         }
-        for (int sub = 0; sub < kIters / 2; ++sub) {
-            const uint32_t base = local * kItem + sub * 2 * B;
+        for (uint32_t sub = 0; sub < (uint32_t)kIters / per; ++sub) {
+            const uint32_t base = local * kItem + sub * agg;
             if (base >= d.n) break;  // uniform across the workgroup
             for (uint32_t j = threadIdx.x; j < kCap; j += B) {
                 L.mkey[j] = kEmpty;
@@ -246,19 +257,26 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
                 L.mcnt[j] = 0;
             }
             __syncthreads();
-            uint64_t kv[2];
-            int64_t qv[2][3];
-            uint8_t fv[2];
-            int ev[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            // a lane keeps only its vertices' flags and LDS entries across
+            // the barriers; the rare vertex that found no room rebuilds its
+            // key and contribution
+            uint64_t fv = 0;          // 8 bits per vertex
+            uint64_t ev[2] = {0, 0};  // 16 bits per vertex (4 per word), 0xffff = no room
+#pragma unroll 1
+            for (uint32_t u = 0; u < per; ++u) {
                 const uint32_t i = base + u * B + threadIdx.x;
-                kv[u] = 0;
-                qv[u][0] = qv[u][1] = qv[u][2] = 0;
-                fv[u] = PF_V_INVALID;
-                if (i < d.n) fv[u] = view_vertex(d, t, i, kv[u], qv[u][0], qv[u][1], qv[u][2]);
-                ev[u] = merge_into_lds<false>(L.mkey, L.ms0, L.ms1, L.ms2, L.mcnt, kCap, fv[u] == 0, kv[u], qv[u][0],
-                                       qv[u][1], qv[u][2]);
+                uint64_t k = 0;
+                int64_t q0 = 0, q1 = 0, q2 = 0;
+                uint8_t f = PF_V_INVALID;
+                if (i < d.n) f = view_vertex(d, t, inv_s, i, k, q0, q1, q2);
+                if (i < d.n) d.key[i] = k;
+                const int e = merge_into_lds<false>(L.mkey, L.ms0, L.ms1, L.ms2, L.mcnt, kCap, f == 0, k, q0, q1, q2);
+                fv |= (uint64_t)f << (8 * u);
+                const uint64_t eb = (uint64_t)(uint16_t)e << (16 * (u & 3));
+                if (u < 4)
+                    ev[0] |= eb;
+                else
+                    ev[1] |= eb;
             }
             __syncthreads();
             for (uint32_t j = threadIdx.x; j < kCap; j += B) {
@@ -273,25 +291,28 @@ __global__ __launch_bounds__(B) void views_kernel(const pf_view *__restrict__ vi
                 L.mcnt[j] = slot;
             }
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
+#pragma unroll 1
+            for (uint32_t u = 0; u < per; ++u) {
                 const uint32_t i = base + u * B + threadIdx.x;
                 if (i >= d.n) continue;
-                uint8_t fl = fv[u];
+                uint8_t fl = (uint8_t)(fv >> (8 * u));
+                const uint32_t e = (uint32_t)((u < 4 ? ev[0] : ev[1]) >> (16 * (u & 3))) & 0xffffu;
                 uint32_t slot = kNoSlot;
                 if (fl == 0) {
-                    if (ev[u] >= 0) {
-                        slot = L.mcnt[ev[u]];
+                    if (e != 0xffffu) {
+                        slot = L.mcnt[e];
                     } else {  // no room in the LDS table: on its own
-                        slot = find_or_claim(t, kv[u]);
+                        uint64_t k;
+                        int64_t q0, q1, q2;
+                        view_vertex(d, t, inv_s, i, k, q0, q1, q2);
+                        slot = find_or_claim(t, k);
                         if (slot != kNoSlot)
-                            accumulate(t, slot, 1, qv[u][0], qv[u][1], qv[u][2]);
+                            accumulate(t, slot, 1, q0, q1, q2);
                         else
                             add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], 1ull);
                     }
                     if (slot == kNoSlot) fl = PF_V_OVERFLOW;
                 }
-                d.key[i] = kv[u];
                 d.vflags[i] = fl;
                 d.slot[i] = slot;
             }
@@ -388,6 +409,22 @@ hipError_t launch_b(const pf_view *views, uint32_t nviews, uint32_t agg, uint32_
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(views_kernel<B>), B,
                                                          0);
         if (e != hipSuccess) return e;
+        // every workgroup of a cooperative grid must be resident at once: the
+        // LDS-bound count is taken as well, with the static LDS rounded up to
+        // 2 KB, so that an allocation granularity the occupancy query may not
+        // model cannot leave a workgroup waiting for a slot
+        int lds_cu = 0;
+        e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        if (e != hipSuccess) return e;
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(views_kernel<B>));
+        if (e != hipSuccess) return e;
+        const size_t per_wg = (fa.sharedSizeBytes + 2047) / 2048 * 2048;
+        if (per_wg > 0 && lds_cu > 0 && (size_t)resident * per_wg > (size_t)lds_cu)
+            resident = (int)((size_t)lds_cu / per_wg);
+        // and the register-bound count the compiler guarantees (4 SIMDs)
+        const int by_waves = 4 * kWavesPerSimd * 64 / B > 0 ? 4 * kWavesPerSimd * 64 / B : 1;
+        if (resident > by_waves) resident = by_waves;
         if (resident < 1) return hipErrorInvalidConfiguration;
     }
     static uint64_t ticks_per_s = 0;

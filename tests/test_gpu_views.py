@@ -1,6 +1,8 @@
 """GPU parity of the persistent multi-view launch: every view of every frame
 equals the oracle bit for bit, for every (workgroup size, aggregation width)
-the autotuner can pick."""
+the autotuner can pick, and on one full-size frame of the 8-view workload."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -8,6 +10,7 @@ import torch
 import oracle
 import paper_1902_05942_amd as pf
 import synth
+from paper_1902_05942_amd import autotune
 from gpu_util import assert_bits_equal, table_contents
 
 pytestmark = pytest.mark.gpu
@@ -27,18 +30,44 @@ def _views(frame):
     return wl, out
 
 
-@pytest.mark.parametrize("block,agg", [(64, 0), (256, 1), (1024, 1), (512, 0), (128, 1)])
+@functools.lru_cache(maxsize=None)
+def _oracle_frames():
+    """The oracle's results of the three frames of every view (they do not
+    depend on the launch configuration)."""
+    states = [None] * len(SHAPES)
+    res = []
+    for frame in range(3):
+        wl, fs = _views(frame)
+        row = []
+        for v, f in enumerate(fs):
+            R = oracle.filter_frame(f, prev_state=states[v], temporal=True, alpha_old=0.2)
+            row.append((R, states[v]))
+            states[v] = R.state
+        res.append(row)
+    return res
+
+
+def test_every_tuner_pick_is_tested():
+    assert len(autotune.candidates()) == 25
+    assert set(autotune.candidates()) == set(PICKS)
+
+
+PICKS = autotune.candidates()
+
+
+@pytest.mark.parametrize("block,agg", PICKS)
 def test_views_bit_exact_over_frames(gpu, block, agg):
     mvf = pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=True, alpha_old=0.2)
     states = [None] * len(SHAPES)
+    expected = _oracle_frames()
     for frame in range(3):
         wl, fs = _views(frame)
         dev = [{k: (v.cuda() if torch.is_tensor(v) else v) for k, v in f.items()} for f in fs]
         outs = mvf.filter(dev, block, agg, with_count=True)
         torch.cuda.synchronize()
-        assert mvf.status() == 0
+        assert mvf.status() == 0, mvf.status_words()
         for v, f in enumerate(fs):
-            R = oracle.filter_frame(f, prev_state=states[v], temporal=True, alpha_old=0.2)
+            R, _ = expected[frame][v]
             b = mvf.bufs[v]
             n = f["px"].numel()
             assert_bits_equal(b["key"][:n].cpu().numpy().view(np.uint64), R.key, f"view {v} keys")
@@ -70,10 +99,55 @@ def test_views_argument_checks(gpu):
     with pytest.raises(pf.PfError):
         pf.filter_views(d, 96, 0, mvf2.ws)                 # unsupported workgroup size
     with pytest.raises(pf.PfError):
-        pf.filter_views(d, 256, 3, mvf2.ws)                # aggregation width not a power of two
+        pf.filter_views(d, 256, 768, mvf2.ws)              # aggregation width not a power of two
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d, 256, 128, mvf2.ws)              # aggregation width below the workgroup
+    with pytest.raises(pf.PfError):
+        pf.filter_views(d, 256, 4096, mvf2.ws)             # aggregation width above 8 x workgroup
     with pytest.raises(pf.PfError):
         pf.filter_views(d + d, 256, 0, mvf2.ws)            # two views sharing tables
     d[0].r_out = d[0].r
     with pytest.raises(pf.PfError):
         pf.filter_views(d, 256, 0, mvf2.ws)                # output aliasing the input
     del mvf
+
+
+def test_eight_views_full_size_one_frame(gpu):
+    """One frame of the full 8-view workload (59.5M vertex slots, per-view
+    tables of 2^19 .. 2^24 slots in one arena) at the configuration the
+    benchmark's tuner picked most often, every view against the oracle."""
+    wl = synth.get("multiview_8")
+    shapes = [(v.width * v.height * v.verts_per_path, v.log2_slots) for v in wl.views]
+    mvf = pf.MultiViewFilter(shapes, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old)
+    for frame in range(2):
+        fs = [synth.generate(wl, view=v, frame=frame) for v in range(len(wl.views))]
+        print(f"multiview_8 frame {frame}: {sum(f['px'].numel() for f in fs)} slots", flush=True)
+        dev = [{k: (x.cuda() if torch.is_tensor(x) else x) for k, x in f.items()} for f in fs]
+        outs = mvf.filter(dev, 256, 512, with_count=True)
+        torch.cuda.synchronize()
+        assert mvf.status() == 0
+        if frame == 0:
+            states = []
+            for v, f in enumerate(fs):
+                states.append(oracle.filter_frame(f, temporal=True, alpha_old=wl.alpha_old).state)
+            continue
+        for v, f in enumerate(fs):
+            R = oracle.filter_frame(f, prev_state=states[v], temporal=True, alpha_old=wl.alpha_old)
+            b = mvf.bufs[v]
+            n = f["px"].numel()
+            assert_bits_equal(b["key"][:n].cpu().numpy().view(np.uint64), R.key, f"view {v} keys")
+            assert_bits_equal(b["vflags"][:n].cpu().numpy(), R.flags, f"view {v} flags")
+            assert_bits_equal(b["count"][:n].cpu().numpy().view(np.uint32), R.cnt, f"view {v} counts")
+            got = np.stack([o.cpu().numpy() for o in outs[v]], 1)
+            assert_bits_equal(got, R.out, f"view {v} radiance")
+            t = mvf.tables[v][1]
+            tc = table_contents(t)
+            order = np.argsort(tc["key"])
+            assert R.table.order_free
+            assert_bits_equal(tc["key"][order], R.gkey, f"view {v} table keys")
+            assert_bits_equal(tc["count"][order], R.gcnt, f"view {v} table counts")
+            assert_bits_equal(tc["sum"][order], R.gsum, f"view {v} table sums")
+            assert_bits_equal(tc["occupied"], R.table.occupied, f"view {v} occupancy")
+            st = pf.read_stats(t)
+            assert int(st[pf.STAT_USED]) == len(R.gkey) and int(st[pf.STAT_DISP]) == R.table.total_disp
+            assert int(st[pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, states[v][0]).sum())

@@ -53,9 +53,16 @@ def parse():
                         "atomics per aggregated group")
     p.add_argument("--frames", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-legs", action="store_true",
+                   help="leave out the learned-fallback, 8-view and 4K blocks of the default run")
+    p.add_argument("--cpu-workers", type=int, default=0,
+                   help="host processes for the all-cores oracle timing (0 = the cores this process may use, at "
+                        "most 16)")
     p.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle timed on the host")
     p.add_argument("--lean", action="store_true",
                    help="time the frames only (no probes, segments, quality or oracle legs): for profiler runs")
+    p.add_argument("--probes", action="store_true",
+                   help="with --lean: run the random-access probes after the frames (counter runs of both)")
     p.add_argument("--low-density", default="",
                    help="below,mode: add the low-density fallback (mode 0 neighbourhood, 1 similar normals) for "
                         "cells with fewer than `below` vertices, timed as its own stage")
@@ -68,7 +75,7 @@ def parse():
     p.add_argument("--across-levels", action="store_true",
                    help="the temporal pass also searches a changed cell's region one level coarser and finer")
     p.add_argument("--resolve", action="store_true",
-                   help="add the pixel resolve (value times a synthetic throughput, summed per pixel) as a stage")
+                   help="add the pixel resolve (value times the path throughput, summed per pixel) as a stage")
     p.add_argument("--separate-temporal", action="store_true",
                    help="run the temporal pass as a launch of its own instead of inside the fused insert")
     p.add_argument("--separate-clear", action="store_true",
@@ -93,14 +100,16 @@ def source_digest():
     return h.hexdigest()
 
 
-def counted_traffic(kernel, workload, mode):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    profiles/hbm_traffic_<kernel>_<workload>_<mode>.txt (FETCH_SIZE and
-    WRITE_SIZE, each scaled by the same counter's reading for a copy of known
-    size), or None when there is none or the sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{workload}_{mode}.txt")
+def counter_profile(workload, mode):
+    """Fields of the committed counter summary
+    profiles/hbm_traffic_<workload>_<mode>.txt (HBM bytes per call of each
+    stage from FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size, and the bytes fetched per random
+    32-byte gather of the probe), or {} when there is none or the sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{mode}.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     with open(path) as fh:
         for line in fh:
@@ -108,8 +117,15 @@ def counted_traffic(kernel, workload, mode):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
     if fields.get("sources_sha256") != source_digest():
-        return None
-    return int(float(fields["traffic_bytes_per_launch"]))
+        return {}
+    return fields
+
+
+def counted_traffic(stage, workload, mode):
+    """Counted HBM bytes per call of `stage`, or None (no summary, or the
+    sources changed since it was taken)."""
+    v = counter_profile(workload, mode).get(f"stage_bytes.{stage}")
+    return None if v is None else int(float(v))
 
 
 def copy_probe(mib):
@@ -171,10 +187,8 @@ def main():
     low_density = tuple(int(x) for x in a.low_density.split(",")) if a.low_density else None
     multilevel = tuple(int(x) for x in a.multilevel.split(",")) if a.multilevel else None
     hist = pf.History(*(int(x) for x in a.history.split(","))) if a.history else None
-    if a.resolve:
-        pixels = view.width * view.height
-        tput = synth.synthetic_throughput(n, 7, dev)
-        image = tuple(torch.empty(pixels, device=dev) for _ in range(3))
+    pixels = view.width * view.height
+    image = tuple(torch.empty(pixels, device=dev) for _ in range(3))
     if multilevel:
         ctabs = [pf.Table(view.log2_slots, wl.max_probe, wl.frac_bits, True, dev) for _ in range(2)]
         for t in ctabs:
@@ -251,7 +265,8 @@ def main():
                                                                  outs[0], outs[1], outs[2],
                                                                  count if use_mlp else None)))
         if a.resolve:
-            st.append(("resolve_pixels", lambda: pf.resolve_pixels(outs[0], outs[1], outs[2], tput, f["valid"],
+            st.append(("resolve_pixels", lambda: pf.resolve_pixels(outs[0], outs[1], outs[2],
+                                                                   (f["tr"], f["tg"], f["tb"]), f["valid"],
                                                                    pixels, view.verts_per_path, image)))
         if use_mlp:
             def mlp():
@@ -310,9 +325,10 @@ def main():
     st = pf.read_stats(flt.prev)
     cells = int(st[pf.STAT_USED])
     if a.lean:
+        ra = random_access(dev, (1 << view.log2_slots) * pf.SLOT_BYTES) if a.probes else None
         print(json.dumps({"metric": "per-stage microseconds (lean profiling run)", "kernel_us":
                           {k: round(v, 2) for k, v in per.items()}, "ms_per_step": round(wall * 1e3 / a.steps, 4),
-                          "insert": a.insert, "steps": a.steps}), flush=True)
+                          "insert": a.insert, "steps": a.steps, "random_access": ra}), flush=True)
         return
 
     # the random-access denominators, measured at the table's footprint right
@@ -373,6 +389,22 @@ def main():
                       f_last["seed"])
     q_plain = rmse(o2, f_last)
 
+    # the image of the last frame (Section 3: each vertex's value times its
+    # path throughput, summed per pixel) against the noise-free image
+    def resolved(vals):
+        img = tuple(torch.empty(pixels, device=dev) for _ in range(3))
+        pf.resolve_pixels(*[x.contiguous() for x in vals], (f_last["tr"], f_last["tg"], f_last["tb"]),
+                          f_last["valid"], pixels, view.verts_per_path, img)
+        return torch.stack(img, 1)
+    tr_last = f_last["truth"]
+    img_truth = resolved((tr_last[:, 0], tr_last[:, 1], tr_last[:, 2]))
+
+    def img_rmse(vals):
+        return round(float(torch.sqrt(((resolved(vals) - img_truth) ** 2).mean())), 5)
+    image_rmse = {"noisy": img_rmse((f_last["r"], f_last["g"], f_last["b"])), "filtered": img_rmse(o2),
+                  "filtered_temporal": img_rmse(outs), "pixels": pixels,
+                  "mean_pixel_truth": round(float(img_truth.mean()), 5)}
+
     # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
     nv = float(np.mean(n_valid))
     algo_bytes = {
@@ -389,10 +421,10 @@ def main():
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
-    launches = {"insert_accumulate": ("aggregate, colscan, scatter (bin starts scanned in it), reduce"
+    launches = {"insert_accumulate": ("zero, aggregate (records into per-XCD bin buckets), reduce"
                                       if a.insert == "binned" else "insert"),
-                "build_keys_insert": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), reduce",
-                "build_keys_insert_temporal": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), "
+                "build_keys_insert": "zero, aggregate (keys built in it; records into per-XCD bin buckets), reduce",
+                "build_keys_insert_temporal": "zero, aggregate (keys built in it; records into per-XCD bin buckets), "
                                               "reduce (temporal blend in it)"}
     roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -410,11 +442,41 @@ def main():
     t_iq = (t_ins + t_q) * 1e-6   # with the fused clear, the lookup's time includes emptying the other table
     ra["insert_query_touches"] = int(touches)
     ra["achieved_G_touches_per_s"] = round(touches / t_iq / 1e9, 2)
-    ra["frac_of_gather"] = round(touches / t_iq / 1e9 / ra["G_per_s"]["gather_32B"], 4)
+    # achieved random-access bandwidth: the headline calls' counted HBM bytes
+    # per second over the counted bytes per second of the random 32-byte
+    # gather probe at the table's footprint (the same counters, the probe's
+    # rate measured live); both move whole lines, so the ratio compares like
+    # with like and the probe, which does nothing but random line fetches,
+    # bounds it
+    prof = counter_profile(a.workload, a.insert)
+    ins_name = "build_keys_insert_temporal" if temporal_in_insert else ("build_keys_insert" if fused
+                                                                         else "insert_accumulate")
+    q_name = "query_average_clear" if clear_in_lookup else "query_average"
+    b_ins, b_q = prof.get(f"stage_bytes.{ins_name}"), prof.get(f"stage_bytes.{q_name}")
+    per_gather = prof.get("probe_fetch_bytes_per_gather")
+    if b_ins and b_q and per_gather:
+        got = (float(b_ins) + float(b_q)) / t_iq
+        probe = ra["G_per_s"]["gather_32B"] * 1e9 * float(per_gather)
+        ra["headline_counted_GB_per_s"] = round(got / 1e9, 1)
+        ra["gather_counted_GB_per_s"] = round(probe / 1e9, 1)
+        ra["frac_of_random_access_bw"] = round(got / probe, 4)
+    else:
+        ra["frac_of_random_access_bw"] = None
 
+    legs = {"mlp": None, "multiview": None, "uhd_4k": None}
+    if a.workload == "hd_1080p_x3" and not a.no_legs:
+        # the other configurations, each as one block of this line: the learned
+        # fallback on the same frames, one 8-view launch, the 4K frame
+        print("[bench] learned fallback leg", file=sys.stderr, flush=True)
+        legs["mlp"] = mlp_leg(frames, wl, dev, per.get("build_keys_insert_temporal", 0.0) +
+                              per.get("query_average_clear", 0.0))
+        print("[bench] 8-view leg", file=sys.stderr, flush=True)
+        legs["multiview"] = multiview_leg(a, dev, steps=20, warmup=4)
+        print("[bench] 4K leg", file=sys.stderr, flush=True)
+        legs["uhd_4k"] = uhd_leg(a, dev, probes=(64,), reps=10)
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(frames, wl, a.cpu_frames)
+        cpu = cpu_baseline(frames, wl, a.cpu_frames, a.cpu_workers)
 
     line = {
         "metric": "vertices/s filtered (insert+query) at 1080p; RMSE vs noise-free mean",
@@ -424,7 +486,8 @@ def main():
         "config": {"workload": a.workload, "width": view.width, "height": view.height,
                    "verts_per_path": view.verts_per_path, "vertex_slots": n, "valid_vertices_mean": round(nv, 1),
                    "log2_slots": view.log2_slots, "max_probe": wl.max_probe, "frac_bits": wl.frac_bits,
-                   "frames": a.frames, "alpha_old": wl.alpha_old, "agg_width": a.agg, "insert": a.insert,
+                   "frames": a.frames, "alpha_old": wl.alpha_old, "insert": a.insert,
+                   **({"agg_width": a.agg} if a.insert == "atomic" else {}),
                    "parallelism": "single-gpu"},
         "vertex_slots_per_s": round(n * a.steps / wall, 1),
         "gpu_ms_per_step": round(gpu_ms / a.steps, 4),
@@ -435,7 +498,10 @@ def main():
         "segments": segments(dev, frames[(a.warmup + a.steps - 1) % len(frames)], view, wl),
         "cells_last_frame": cells,
         "rmse": {"unfiltered": round(q_noisy, 5), "filtered": round(q_plain, 5), "filtered_temporal": round(q_temporal, 5)},
-        "mlp": mlp_info,
+        "image_rmse": image_rmse,
+        "mlp": mlp_info or legs["mlp"],
+        "multiview": legs["multiview"],
+        "uhd_4k": legs["uhd_4k"],
         "roofline": roofline,
         "random_access": ra,
         "cpu_baseline": cpu,
@@ -445,6 +511,27 @@ def main():
 
 def main_multiview(a):
     """8 views of uneven resolution, one persistent launch per frame."""
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    leg = multiview_leg(a, dev, a.steps, a.warmup, verbose=True)
+    line = {
+        "metric": "vertices/s filtered (insert+query), 8 views in one persistent launch",
+        "value": leg["vertices_per_s"], "unit": "vertices/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
+        "config": dict(leg["config"], parallelism="single-gpu"),
+        **{k: v for k, v in leg.items() if k not in ("config", "vertices_per_s", "ms_per_step")},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def multiview_leg(a, dev, steps, warmup, verbose=False):
+    """The 8-view workload (59.5M vertex slots, per-view tables in one arena):
+    the autotuner's pick over every (workgroup, aggregation width) pair, then
+    `steps` timed launches cycling over 4 frames, next to the same frames
+    sent view by view through the single-view calls."""
     import numpy as np
     import torch
 
@@ -452,8 +539,6 @@ def main_multiview(a):
     from paper_1902_05942_amd import autotune
     import synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     wl = synth.get("multiview_8")
     nfr = min(a.frames, 4)
     shapes = [(v.width * v.height * v.verts_per_path, v.log2_slots) for v in wl.views]
@@ -462,23 +547,23 @@ def main_multiview(a):
     frames = [[synth.generate(wl, view=v, frame=i, device=dev) for v in range(len(wl.views))] for i in range(nfr)]
     n_valid = [sum(int(f["valid"].sum()) for f in fr) for fr in frames]
     mvf = pf.MultiViewFilter(shapes, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old, device=dev)
-    block, agg, table = autotune.tune(mvf, frames[0], reps=3, use_cache=False, verbose=True)
-    print(f"[bench] autotuned workgroup {block}, aggregation {agg}", file=sys.stderr, flush=True)
-    for k in range(a.warmup):
+    block, agg, table = autotune.tune(mvf, frames[0], reps=3, use_cache=False, verbose=verbose)
+    print(f"[bench] autotuned workgroup {block}, aggregation width {agg}", file=sys.stderr, flush=True)
+    for k in range(warmup):
         mvf.filter(frames[k % nfr], block, agg)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     ev[0].record()
-    for k in range(a.steps):
-        mvf.filter(frames[(a.warmup + k) % nfr], block, agg)
+    for k in range(steps):
+        mvf.filter(frames[(warmup + k) % nfr], block, agg)
         ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert mvf.status() == 0
     phases = [round(x, 1) for x in mvf.phase_us()]
-    launch_us = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)])) * 1e3
-    valid_total = sum(n_valid[(a.warmup + k) % nfr] for k in range(a.steps))
+    launch_us = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])) * 1e3
+    valid_total = sum(n_valid[(warmup + k) % nfr] for k in range(steps))
     n_total = sum(s for s, _ in shapes)
     nv = float(np.mean(n_valid))
     cells = 0
@@ -494,31 +579,30 @@ def main_multiview(a):
         for flt, f in zip(flts, fr):
             flt.filter(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["r"], f["g"], f["b"],
                        f["cam"], f["s"], f["seed"])
-    for k in range(a.warmup):
+    for k in range(warmup):
         seq_frame(frames[k % nfr])
     torch.cuda.synchronize()
     sev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     sev[0].record()
-    for k in range(a.steps):
-        seq_frame(frames[(a.warmup + k) % nfr])
+    for k in range(steps):
+        seq_frame(frames[(warmup + k) % nfr])
     sev[1].record()
     torch.cuda.synchronize()
-    seq_us = sev[0].elapsed_time(sev[1]) * 1e3 / a.steps
+    seq_us = sev[0].elapsed_time(sev[1]) * 1e3 / steps
+    del flts, frames, mvf
+    torch.cuda.empty_cache()
     # per slot: position/normal/valid 25 read, key/flags/slot 13 written, lookup flags+slot 5 read, output 12
     # written; per valid vertex: contribution 12, probe 4, cell update 28, temporal value 16; per invalid slot:
     # own contribution 12; per cell: clear 32, temporal 84; the occupancy bitmaps read twice
     algo = n_total * 55 + nv * 60 + (n_total - nv) * 12 + cells * 116 + 2 * words
     achieved = algo / (launch_us * 1e-6) / 1e9
-    line = {
-        "metric": "vertices/s filtered (insert+query), 8 views in one persistent launch",
-        "value": round(valid_total / wall, 1), "unit": "vertices/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": round(wall * 1e3 / a.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
+    return {
+        "vertices_per_s": round(valid_total / wall, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
         "config": {"workload": "multiview_8", "views": [[v.width, v.height, v.verts_per_path] for v in wl.views],
                    "vertex_slots": n_total, "valid_vertices_mean": round(nv, 1), "table_slots":
-                   sum(1 << l for _, l in shapes), "block": block, "agg_width": agg, "frames": nfr,
-                   "parallelism": "single-gpu"},
+                   sum(1 << l for _, l in shapes), "block": block, "agg_width": agg, "frames": nfr},
         "launch_us": round(launch_us, 2),
+        "launch_vertices_per_s": round(nv / (launch_us * 1e-6), 1),
         "phase_us_last_launch": {"clear": phases[0], "keys_insert": phases[1], "temporal": phases[2],
                                  "lookup": phases[3]},
         "autotune_ms": {f"{b}/{g}": round(v, 4) for (b, g), v in sorted(table.items())},
@@ -527,28 +611,43 @@ def main_multiview(a):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic("views_kernel", "multiview_8", "persistent"),
                      "algorithmic_bytes_per_launch": int(algo)},
-        "cpu_baseline": None,
     }
-    print(json.dumps(line), flush=True)
 
 
 def main_uhd(a):
     """3840x2160x4 (33,177,600 slots, 2^25-slot table): a real frame at the
     default scale, then synthetic key streams at table loads 0.1 .. 0.7 for
-    probe limits 32, 64, 128.  Per point: insert (binned) + lookup time,
-    achieved load, mean displacement, displacement percentiles and overflow."""
+    probe limits 32, 64, 128."""
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    leg = uhd_leg(a, dev, probes=(32, 64, 128), reps=max(3, min(a.steps, 20)))
+    line = {
+        "metric": "vertices/s filtered (insert+query) at 3840x2160x4 per table load",
+        "value": leg["scene"]["vertices_per_s"], "unit": "vertices/s", "n_gpus": 1, "steps": leg["reps"],
+        "warmup": 1, "ms_per_step": round((leg["scene"]["insert_us"] + leg["scene"]["query_us"]) * 1e-3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
+        "config": dict(leg["config"], parallelism="single-gpu"),
+        "scene": leg["scene"], "scene_small_cells": leg["scene_small_cells"], "key_sweep": leg["key_sweep"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def uhd_leg(a, dev, probes, reps):
+    """3840x2160x4 (33,177,600 slots, 2^25-slot table): a real frame at the
+    default scale (and at s / 5, more cells), then synthetic key streams at
+    table loads 0.1 .. 0.7 for each probe limit in `probes`.  Per point:
+    insert (binned) + lookup time, achieved load, mean displacement,
+    displacement percentiles and histogram, overflow."""
     import numpy as np
     import torch
 
     import paper_1902_05942_amd as pf
     import synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     wl = synth.get("uhd_4k_x4")
     m = wl.views[0].log2_slots
     n = 3840 * 2160 * 4
-    reps = max(3, min(a.steps, 20))
     key = torch.empty(n, dtype=torch.int64, device=dev)
     vflags = torch.empty(n, dtype=torch.uint8, device=dev)
     slot = torch.empty(n, dtype=torch.int32, device=dev)
@@ -601,11 +700,11 @@ def main_uhd(a):
         frame = frame or pt
         print(f"[bench] scene s={s}: {json.dumps(pt)}", file=sys.stderr, flush=True)
         scene_small = pt
-    del f
+    del f, t
     sweep = []
     for load in (0.1, 0.3, 0.5, 0.7):
         d = synth.synthetic_keys(n, int(load * (1 << m)), device=dev)
-        for P in (32, 64, 128):
+        for P in probes:
             tp = pf.Table(m, P, wl.frac_bits, with_blend=False)
             pf.table_init(tp)
 
@@ -618,16 +717,82 @@ def main_uhd(a):
             sweep.append(pt)
             del tp
         del d
-    line = {
-        "metric": "vertices/s filtered (insert+query) at 3840x2160x4 per table load",
-        "value": frame["vertices_per_s"], "unit": "vertices/s", "n_gpus": 1, "steps": reps, "warmup": 1,
-        "ms_per_step": round((frame["insert_us"] + frame["query_us"]) * 1e-3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+int64", "data": "synthetic",
-        "config": {"workload": "uhd_4k_x4", "vertex_slots": n, "log2_slots": m, "insert": "binned",
-                   "parallelism": "single-gpu"},
-        "scene": frame, "scene_small_cells": scene_small, "key_sweep": sweep,
-    }
-    print(json.dumps(line), flush=True)
+    del key, vflags, slot, outs, ws
+    torch.cuda.empty_cache()
+    return {"reps": reps, "config": {"workload": "uhd_4k_x4", "vertex_slots": n, "log2_slots": m,
+                                     "insert": "binned"},
+            "scene": frame, "scene_small_cells": scene_small, "key_sweep": sweep}
+
+
+def mlp_leg(frames, wl, dev, frame_us_plain):
+    """The learned fallback for sparse cells on the same 1080p frames (the
+    network trained online from scratch, 4 steps of 16384 samples per frame):
+    16 frames to train, then 32 timed frames; RMSE against the noise-free
+    radiance with and without it (and the paper's own fallbacks for the same
+    cells) on the last frame, and the cost per frame."""
+    import numpy as np
+    import torch
+
+    import paper_1902_05942_amd as pf
+    from synth.mlp_init import init_params
+
+    view = wl.views[0]
+    n = view.width * view.height * view.verts_per_path
+    warm, timed = 16, 32
+    fb = pf.MlpFallback(n, init_params(1902), batch=16384, steps=4, lr=1e-3)
+    flt = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
+                         device=dev, fused=True, mlp=fb)
+    nfr = len(frames)
+
+    def run(fl, k, **kw):
+        f = frames[k % nfr]
+        return fl.filter(f["px"], f["py"], f["pz"], f["nx"], f["ny"], f["nz"], f["valid"], f["r"], f["g"], f["b"],
+                         f["cam"], f["s"], f["seed"], **kw)
+    for k in range(warm):
+        run(flt, k)
+    torch.cuda.synchronize()
+    evs = []
+    for k in range(warm, warm + timed):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        e[0].record()
+        out = run(flt, k, mlp_timing=e[1:5])
+        e[5].record()
+        evs.append(e)
+    torch.cuda.synchronize()
+    ms = lambda i, j: float(np.mean([e[i].elapsed_time(e[j]) for e in evs])) * 1e3  # noqa: E731
+    frame_us, select_us, train_us, infer_us = ms(0, 5), ms(1, 2), ms(2, 3), ms(3, 4)
+    f_last = frames[(warm + timed - 1) % nfr]
+    n_ = n
+    sparse = (flt.vflags[:n_] == 0) & (flt.count[:n_] < 4)
+    truth = f_last["truth"]
+    valid = f_last["valid"].bool()
+
+    def rmse(o, msk):
+        return float(torch.sqrt(((torch.stack(o, 1)[msk] - truth[msk]) ** 2).mean()))
+    q_with, q_with_all = rmse(out, sparse), rmse(out, valid)
+    res = {}
+    # the same 16 frames ending on the same one: the moving average alone, then the paper's fallbacks
+    for name, opt in (("without", {}), ("neighbours", {"low_density": (4, pf.LD_NEIGHBOURS)}),
+                      ("normals", {"low_density": (4, pf.LD_NORMALS)}), ("multilevel_1", {"multilevel": (4, 1)})):
+        ref = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
+                             device=dev, fused=True, **opt)
+        for k in range(warm + timed - 16, warm + timed):
+            o = run(ref, k)
+        res[name] = {"rmse_sparse": round(rmse(o, sparse), 5), "rmse_all": round(rmse(o, valid), 5)}
+        del ref
+    flops = fb.steps * fb.batch * 2 * (10240 + 15360)
+    mlp_us = select_us + train_us + infer_us
+    return {"workload": "hd_1080p_x3_mlp", "frames_trained_before_timing": warm, "timed_frames": timed,
+            "sparse_vertices": int(sparse.sum()),
+            "rmse_sparse_without": res["without"]["rmse_sparse"], "rmse_sparse_with": round(q_with, 5),
+            "rmse_all_without": res["without"]["rmse_all"], "rmse_all_with": round(q_with_all, 5),
+            "us_per_frame": round(mlp_us, 2), "frame_us_with": round(frame_us, 2),
+            "frame_us_without": round(frame_us_plain, 2),
+            "select_us": round(select_us, 2), "train_us": round(train_us, 2), "infer_us": round(infer_us, 2),
+            "train_flops_per_frame": flops, "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
+            "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),
+            "loss": float(fb.net.loss().cpu()[0]),
+            "paper_fallbacks_below_4": {k: v for k, v in res.items() if k != "without"}}
 
 
 def segments(dev, f, view, wl, reps=20):
@@ -708,13 +873,62 @@ def random_access(dev, footprint):
     return {"footprint_bytes": footprint, "G_per_s": rates, "copy_GB_per_s": round(copy, 1)}
 
 
-def cpu_baseline(frames, wl, k):
-    """The oracle (single-threaded C plus numpy glue) on k frames of the same
-    workload, with the moving average; vertices/s over valid vertices."""
+def _oracle_worker(wname, frame0, k, barrier, results):
+    """One host process of the all-cores timing: the oracle on frames
+    frame0+1 .. frame0+k of the workload (moving average; frame0 only
+    builds the previous state), timed after every process is ready."""
+    import torch
+    torch.set_num_threads(1)
+    import oracle
+    import synth
+    wl = synth.get(wname)
+    fr = [synth.generate(wl, frame=frame0 + i) for i in range(k + 1)]
+    state = oracle.filter_frame(fr[0], temporal=True, alpha_old=wl.alpha_old).state
+    barrier.wait()
+    t0 = time.perf_counter()
+    nv = 0
+    for i in range(1, k + 1):
+        state = oracle.filter_frame(fr[i], prev_state=state, temporal=True, alpha_old=wl.alpha_old).state
+        nv += int(fr[i]["valid"].sum())
+    results.put((t0, time.perf_counter(), nv))
+
+
+def host_cores():
+    """Cores this process may run on, at most 16 (a one-GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if env > 0:
+        n = min(n, env)
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(frames, wl, k, workers=0):
+    """The oracle (single-threaded C plus numpy glue, not tuned for speed) on
+    the same workload with the moving average, vertices/s over valid
+    vertices: on one host thread (k consecutive frames), and on every core
+    this process may use (one process per core, each filtering its own 2
+    consecutive frames, all started together; the rate is all their valid
+    vertices over the span from the first start to the last end)."""
+    import multiprocessing as mp
+
     import oracle
     hosts = [{kk: (v.cpu() if hasattr(v, "cpu") else v) for kk, v in frames[i].items()} for i in range(k + 1)]
     state = oracle.filter_frame(hosts[0], temporal=True, alpha_old=wl.alpha_old).state
-    print(f"[bench] timing the oracle on {k} frames", file=sys.stderr, flush=True)
+    print(f"[bench] timing the oracle on {k} frames, one thread", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     nv = 0
     for i in range(1, k + 1):
@@ -722,9 +936,28 @@ def cpu_baseline(frames, wl, k):
         state = R.state
         nv += int(hosts[i]["valid"].sum())
     dt = time.perf_counter() - t0
-    return {"value": round(nv / dt, 1), "unit": "vertices/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} consecutive frames of {wl.name} (1920x1080x3 slots each) with the moving average, "
-                      f"{dt:.1f} s on one host thread"}
+    del hosts, state, R
+    one = nv / dt
+    w = workers or host_cores()
+    per = 2
+    print(f"[bench] timing the oracle in {w} host processes x {per} frames", file=sys.stderr, flush=True)
+    ctx = mp.get_context("spawn")   # fresh interpreters: nothing of this process's GPU state is inherited
+    barrier, results = ctx.Barrier(w), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(wl.name, (3 * j) % 13, per, barrier, results))
+             for j in range(w)]
+    for p in procs:
+        p.start()
+    got = [results.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join(timeout=60)
+    span = max(t1 for _, t1, _ in got) - min(t0 for t0, _, _ in got)
+    nv_all = sum(x for _, _, x in got)
+    return {"value": round(nv_all / span, 1), "unit": "vertices/s", "cores": w, "kind": "oracle",
+            "sample": f"{w} host processes, each the oracle on {per} consecutive frames of {wl.name} "
+                      f"(1920x1080x3 slots each) with the moving average: {nv_all} valid vertices in {span:.1f} s",
+            "cpu_model": cpu_model(), "host_cores_online": os.cpu_count(),
+            "one_core": {"value": round(one, 1), "cores": 1,
+                         "sample": f"{k} consecutive frames, {dt:.1f} s on one host thread"}}
 
 
 if __name__ == "__main__":

@@ -142,8 +142,9 @@ class FrameFilter:
         return self.tables[1] if (self.temporal and self.frames > 0) else None
 
     def filter(self, px, py, pz, nx, ny, nz, valid, r, g, b, cam, s, seed, out=None, idx_base=0,
-               with_count=False):
-        """Filters one frame; returns (r_out, g_out, b_out) (in place if out is (r, g, b))."""
+               with_count=False, mlp_timing=None):
+        """Filters one frame; returns (r_out, g_out, b_out) (in place if out is (r, g, b)).
+        mlp_timing: optional 4 events for the learned fallback's stages (MlpFallback.apply)."""
         n = px.numel()
         key, vflags, slot = self.key[:n], self.vflags[:n], self.slot[:n]
         cnt = self.count[:n] if (with_count or self.mlp is not None) else None
@@ -205,7 +206,7 @@ class FrameFilter:
             query_average(cur, key, slot, r, g, b, vflags, use_blend, out[0], out[1], out[2], cnt)
         if self.mlp is not None:
             geo = geometry(key, px, py, pz, nx, ny, nz, cam)
-            self.mlp.apply(cur, geo, vflags, cnt, slot, out, seed)
+            self.mlp.apply(cur, geo, vflags, cnt, slot, out, seed, timing=mlp_timing)
         if self.temporal:
             self.tables.reverse()
             if self.coarse is not None:
@@ -267,8 +268,10 @@ class MultiViewFilter:
                                    b["count"][:n] if with_count else None, self.temporal, self.alpha_old))
         return descs
 
-    def filter(self, frames, block=256, agg_width=64, with_count=False, grid_per_cu=0):
-        filter_views(self.descriptors(frames, with_count), block, agg_width, self.ws, grid_per_cu)
+    def filter(self, frames, block=256, agg_width=None, with_count=False, grid_per_cu=0):
+        """agg_width: None = 2 x block (windows of 2 x block vertices merged in LDS)."""
+        agg = 2 * block if agg_width is None else agg_width
+        filter_views(self.descriptors(frames, with_count), block, agg, self.ws, grid_per_cu)
         if self.temporal:
             for pair in self.tables:
                 pair.reverse()

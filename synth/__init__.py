@@ -2,4 +2,3 @@
 from .workloads import WORKLOADS, Workload, ViewSpec, frame_seed, generate, get  # noqa: F401
 from .keys import synthetic_keys  # noqa: F401,E402
 from .cloud import mixed_normals_frame  # noqa: F401,E402
-from .throughput import synthetic_throughput  # noqa: F401,E402

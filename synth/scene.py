@@ -7,7 +7,10 @@ plus seeded axis-aligned boxes (and spheres for the 4K scene), a pinhole
 camera, one path per pixel with cosine-sampled bounces, and per-vertex
 "contributions" (Eq. (9)'s L_i * f_i * cos) equal to
 albedo * max(0, n . l) times a mean-one noise multiplier.  The noise-free
-value albedo * max(0, n . l) is returned as the truth.
+value albedo * max(0, n . l) is returned as the truth, and each vertex's path
+throughput (the product of the albedos before it on its path) as tr, tg, tb,
+so that sum over a pixel's vertices of throughput times contribution forms
+its image.
 
 Vertex streams are bounce-major structure-of-arrays: slot b * W * H + pixel
 holds bounce b of the path through that pixel, pixels in row-major order.
@@ -205,6 +208,12 @@ def generate_view(scene: Scene, width: int, height: int, verts_per_path: int,
     rgb_all = torch.zeros((N, 3), device=device)
     truth_all = torch.zeros((N, 3), device=device)
     valid_all = torch.zeros((N,), dtype=torch.uint8, device=device)
+    tput_all = torch.zeros((N, 3), device=device)
+    # path throughput of each vertex: the product of the albedos of the
+    # earlier vertices of its path (the cosine of a cosine-sampled bounce
+    # cancels its density, and the lambertian 1/pi cancels the pi of the
+    # density's normalisation); 1 for the first hit of the camera ray
+    tput = torch.ones((P, 3), device=device)
 
     alive = torch.ones((P,), dtype=torch.bool, device=device)
     for b in range(verts_per_path):
@@ -225,6 +234,8 @@ def generate_view(scene: Scene, width: int, height: int, verts_per_path: int,
         truth_all[sl] = torch.where(okf, truth, 0.0)
         rgb_all[sl] = torch.where(okf, truth * mult[:, None], 0.0)
         valid_all[sl] = ok.to(torch.uint8)
+        tput_all[sl] = torch.where(okf, tput, 0.0)
+        tput = tput * alb
         alive = ok
         if b + 1 < verts_per_path:
             u1 = rand_uniform(derive_key(fkey, 31 + 2 * b), pix)
@@ -238,6 +249,7 @@ def generate_view(scene: Scene, width: int, height: int, verts_per_path: int,
         "r": rgb_all[:, 0].contiguous(), "g": rgb_all[:, 1].contiguous(), "b": rgb_all[:, 2].contiguous(),
         "valid": valid_all,
         "truth": truth_all,
+        "tr": tput_all[:, 0].contiguous(), "tg": tput_all[:, 1].contiguous(), "tb": tput_all[:, 2].contiguous(),
         "cam": tuple(float(torch.tensor(c, dtype=torch.float32)) for c in eye),
         "width": width, "height": height, "verts_per_path": verts_per_path,
     }

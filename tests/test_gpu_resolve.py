@@ -1,7 +1,8 @@
 """GPU parity of the pixel resolve (pf_resolve_pixels) against the CPU
 oracle, bit for bit: the full 1080p x3 frame filtered by the fused path and
-resolved with a seeded throughput, a ragged image with four vertices per
-path accumulated onto an existing image, and a missing throughput."""
+resolved with the generator's path throughput (the product of the albedos
+before each vertex), a ragged image with four vertices per path accumulated
+onto an existing image, and a missing throughput."""
 import numpy as np
 import pytest
 import torch
@@ -24,15 +25,29 @@ def test_resolve_full_hd_frame(gpu):
     flt = pf.FrameFilter(n, f["log2_slots"], temporal=False, fused=True)
     out = flt.filter(g["px"], g["py"], g["pz"], g["nx"], g["ny"], g["nz"], g["valid"], g["r"], g["g"], g["b"],
                      f["cam"], f["s"], f["seed"])
-    tp = synth.synthetic_throughput(n, 7, "cuda")
+    tp = (f["tr"], f["tg"], f["tb"])
+    assert float(tp[0][P:].max()) < 1.0 and float(tp[0][:P].max()) == 1.0   # attenuated after the first hit
     img = tuple(torch.empty(P, device="cuda") for _ in range(3))
     pf.resolve_pixels(out[0], out[1], out[2], tp, g["valid"], P, V, img)
+    truth = tuple(torch.empty(P, device="cuda") for _ in range(3))
+    tt = f["truth"]
+    pf.resolve_pixels(tt[:, 0].contiguous(), tt[:, 1].contiguous(), tt[:, 2].contiguous(), tp, g["valid"], P, V,
+                      truth)
     torch.cuda.synchronize()
     got_out = np.stack([o.cpu().numpy() for o in out], 1)
     R = oracle.filter_frame({k: (x.cpu() if torch.is_tensor(x) else x) for k, x in f.items()}, temporal=False)
     assert_bits_equal(got_out, R.out, "filtered radiance")
     exp = oracle.resolve_pixels(R.out, np.stack([t.cpu().numpy() for t in tp], 1), f["valid"].cpu().numpy(), P, V)
-    assert_bits_equal(np.stack([x.cpu().numpy() for x in img], 1), exp, "resolved pixels")
+    got = np.stack([x.cpu().numpy() for x in img], 1)
+    assert_bits_equal(got, exp, "resolved pixels")
+    # the filtered image is closer to the noise-free one than the noisy image
+    ref = np.stack([x.cpu().numpy() for x in truth], 1).astype(np.float64)
+    noisy = oracle.resolve_pixels(np.stack([f[c].cpu().numpy() for c in "rgb"], 1),
+                                  np.stack([t.cpu().numpy() for t in tp], 1), f["valid"].cpu().numpy(), P, V)
+    e_f = np.sqrt(((got - ref) ** 2).mean())
+    e_n = np.sqrt(((noisy - ref) ** 2).mean())
+    print(f"image rmse: noisy {e_n:.4f}, filtered {e_f:.4f}")
+    assert e_f < 0.5 * e_n
 
 
 @pytest.mark.parametrize("with_throughput", [True, False])

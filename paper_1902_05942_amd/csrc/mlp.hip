@@ -25,6 +25,12 @@ constexpr int kOffB3 = kOffW3 + kOutPad * kH;   // 10368
 constexpr int kNParam = kOffB3 + kOutPad;       // 10384
 static_assert(kNParam == PF_MLP_NPARAM, "parameter packing");
 constexpr int kBS = PF_MLP_BLOCK_SAMPLES;      // 64 samples per workgroup (4 waves x 16)
+// LDS row strides of the arrays whose rows hold 64 values: 72 elements (144
+// bytes), so that the 16 rows a wavefront's MFMA operand loads and
+// transposed stores touch fall on different banks (a 128-byte stride puts
+// them all on two)
+constexpr int kLdH = kH + 8;   // rows of 64 hidden units (weights W2, W3, W2^T; activations)
+constexpr int kLdS = kBS + 8;  // rows of 64 samples (transposed operands)
 constexpr int kThreads = 256;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -53,14 +59,38 @@ __device__ __forceinline__ void st4(uint16_t *p, float a, float b, float c, floa
     *reinterpret_cast<v4s *>(p) = v;
 }
 
+// FP64 -> FP32 -> BF16, zeros as +0 (sinpi and cospi may return -0)
+__device__ __forceinline__ uint16_t to_feature(double v) {
+    v = v + 0.0;
+    return bf16((float)v);
+}
+
+// Positional-encoding pair j of coordinate c: sin and cos of pi t with the
+// exact phase t = (q + 1/2) 2^(lp - 10 + j) = (2q + 1) 2^e, e = lp - 11 + j.
+// For e >= 0 the phase is an integer (even for e >= 1) and the values are
+// 0 and +-1 exactly; otherwise one FP64 sincospi gives both.
+__device__ __forceinline__ void pe_pair(int32_t qc, int lp, int j, uint16_t &sv, uint16_t &cv) {
+    const int e = lp - 11 + j;
+    double sn = 0.0, cs = 1.0;
+    if (e == 0) {
+        cs = -1.0;  // odd integer
+    } else if (e < 0) {
+        const double t = ldexp((double)qc + 0.5, lp - 10 + j);  // exact
+        sincospi(t, &sn, &cs);
+    }
+    sv = to_feature(sn);
+    cv = to_feature(cs);
+}
+
 // Feature f of a vertex (f in [0, 80)), FP64 then FP64 -> FP32 -> BF16, zeros as +0.
 __device__ __forceinline__ uint16_t feature(int f, const int32_t q[3], int lp, const float x[3], const float n[3],
                                             const float cam[3]) {
     double v = 0.0;
     if (f < 72) {
         const int j = f / 6, r = f % 6, c = r % 3;
-        const double t = ldexp((double)q[c] + 0.5, lp - 10 + j);  // exact
-        v = (r < 3) ? sinpi(t) : cospi(t);
+        uint16_t sv, cv;
+        pe_pair(q[c], lp, j, sv, cv);
+        return r < 3 ? sv : cv;
     } else if (f < 75) {
         v = (double)n[f - 72];
     } else if (f < 78) {
@@ -72,8 +102,24 @@ __device__ __forceinline__ uint16_t feature(int f, const int32_t q[3], int lp, c
         const double d[3] = {dx, dy, dz};
         v = d[f - 75] / len;
     }
-    v = v + 0.0;  // zeros are +0 (sinpi and cospi may return -0)
-    return bf16((float)v);
+    return to_feature(v);
+}
+
+// The 80 features of one vertex, computed by the 4 lanes lg = 0..3 of its
+// group: lane lg takes the positional pairs lg, lg + 4, ... (9 of the 36)
+// and features 72 + lg and 76 + lg; put(f, value) stores feature f.
+template <typename Put>
+__device__ __forceinline__ void vertex_features(int lg, const int32_t q[3], int lp, const float x[3],
+                                                const float n[3], const float cam[3], Put put) {
+    for (int pi = lg; pi < 36; pi += 4) {
+        const int j = pi / 3, c = pi % 3;
+        uint16_t sv, cv;
+        pe_pair(q[c], lp, j, sv, cv);
+        put(6 * j + c, sv);
+        put(6 * j + 3 + c, cv);
+    }
+    put(72 + lg, feature(72 + lg, q, lp, x, n, cam));
+    put(76 + lg, feature(76 + lg, q, lp, x, n, cam));
 }
 
 struct Geo {
@@ -97,28 +143,31 @@ __device__ __forceinline__ void vertex_inputs(const Geo &g, uint32_t v, int32_t 
     n[2] = g.nz[v];
 }
 
-// Stages the BF16 weights (and the transposes the backward pass reads) and
-// the FP32 biases in LDS.
+// Stages the BF16 weights and the FP32 biases in LDS (and, for training,
+// the transposes the backward pass reads).
 struct Weights {
     uint16_t w1[kH * kIn];
-    uint16_t w2[kH * kH];
-    uint16_t w2t[kH * kH];
-    uint16_t w3[kOutPad * kH];
-    uint16_t w3t[kH * kOutPad];
+    uint16_t w2[kH * kLdH];
+    uint16_t w3[kOutPad * kLdH];
     float b1[kH], b2[kH], b3[kOutPad];
 };
 
-__device__ void load_weights(Weights &W, const uint16_t *wb, const float *w, bool transposes) {
+struct WeightsT {
+    uint16_t w2t[kH * kLdH];
+    uint16_t w3t[kH * kOutPad];
+};
+
+__device__ void load_weights(Weights &W, WeightsT *T, const uint16_t *wb, const float *w) {
     for (int i = threadIdx.x; i < kH * kIn; i += kThreads) W.w1[i] = wb[kOffW1 + i];
     for (int i = threadIdx.x; i < kH * kH; i += kThreads) {
         const uint16_t val = wb[kOffW2 + i];
-        W.w2[i] = val;
-        if (transposes) W.w2t[(i % kH) * kH + i / kH] = val;
+        W.w2[(i / kH) * kLdH + i % kH] = val;
+        if (T) T->w2t[(i % kH) * kLdH + i / kH] = val;
     }
     for (int i = threadIdx.x; i < kOutPad * kH; i += kThreads) {
         const uint16_t val = wb[kOffW3 + i];
-        W.w3[i] = val;
-        if (transposes) W.w3t[(i % kH) * kOutPad + i / kH] = val;
+        W.w3[(i / kH) * kLdH + i % kH] = val;
+        if (T) T->w3t[(i % kH) * kOutPad + i / kH] = val;
     }
     for (int i = threadIdx.x; i < kH; i += kThreads) {
         W.b1[i] = w[kOffB1 + i];
@@ -128,10 +177,10 @@ __device__ void load_weights(Weights &W, const uint16_t *wb, const float *w, boo
 }
 
 // Forward pass of one wave's 16-row tile (rows r0..r0+15 of x, a1, a2 with
-// row strides kIn / kH).  Keeps z1, z2 (C layout) for the backward pass and
+// row strides kIn / lda).  Keeps z1, z2 (C layout) for the backward pass and
 // returns y (C layout, columns = outputs).  If a1t/a2t are given, the
 // transposed activations are stored too (row stride ldt).
-__device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x, uint16_t *a1, uint16_t *a2,
+__device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x, uint16_t *a1, uint16_t *a2, int lda,
                                             uint16_t *a1t, uint16_t *a2t, int ldt, int r0, v4f z1[4], v4f z2[4]) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     // layer 1
@@ -151,7 +200,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         for (int i = 0; i < 4; ++i) {
             z1[nt][i] += W.b1[n];
             h[i] = z1[nt][i] > 0.0f ? z1[nt][i] : 0.0f;
-            a1[(r0 + 4 * lg + i) * kH + n] = bf16(h[i]);
+            a1[(r0 + 4 * lg + i) * lda + n] = bf16(h[i]);
         }
         if (a1t) st4(a1t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
@@ -162,9 +211,9 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
     for (int nt = 0; nt < 4; ++nt) z2[nt] = v4f{0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < kH / 16; ++kk) {
-        const v4s a = ld4(a1 + (r0 + lr) * kH + kk * 16 + 4 * lg);
+        const v4s a = ld4(a1 + (r0 + lr) * lda + kk * 16 + 4 * lg);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) z2[nt] = mfma(a, ld4(W.w2 + (nt * 16 + lr) * kH + kk * 16 + 4 * lg), z2[nt]);
+        for (int nt = 0; nt < 4; ++nt) z2[nt] = mfma(a, ld4(W.w2 + (nt * 16 + lr) * kLdH + kk * 16 + 4 * lg), z2[nt]);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -174,7 +223,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         for (int i = 0; i < 4; ++i) {
             z2[nt][i] += W.b2[n];
             h[i] = z2[nt][i] > 0.0f ? z2[nt][i] : 0.0f;
-            a2[(r0 + 4 * lg + i) * kH + n] = bf16(h[i]);
+            a2[(r0 + 4 * lg + i) * lda + n] = bf16(h[i]);
         }
         if (a2t) st4(a2t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
@@ -184,7 +233,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
     v4f y = {0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < kH / 16; ++kk)
-        y = mfma(ld4(a2 + (r0 + lr) * kH + kk * 16 + 4 * lg), ld4(W.w3 + lr * kH + kk * 16 + 4 * lg), y);
+        y = mfma(ld4(a2 + (r0 + lr) * lda + kk * 16 + 4 * lg), ld4(W.w3 + lr * kLdH + kk * 16 + 4 * lg), y);
 #pragma unroll
     for (int i = 0; i < 4; ++i) y[i] += W.b3[lr];
     return y;
@@ -200,12 +249,13 @@ __device__ __forceinline__ float col_sum(float v) {
 
 struct TrainLds {
     Weights W;
-    uint16_t x[kBS * kIn], xt[kIn * kBS];
-    uint16_t a1[kBS * kH], a1t[kH * kBS];
-    uint16_t a2[kBS * kH], a2t[kH * kBS];
-    uint16_t gy[kBS * kOutPad], gyt[kOutPad * kBS];
-    uint16_t gz2[kBS * kH], gz2t[kH * kBS];
-    uint16_t gz1t[kH * kBS];
+    WeightsT T;
+    uint16_t x[kBS * kIn], xt[kIn * kLdS];
+    uint16_t a1[kBS * kLdH], a1t[kH * kLdS];
+    uint16_t a2[kBS * kLdH], a2t[kH * kLdS];
+    uint16_t gy[kBS * kOutPad], gyt[kOutPad * kLdS];
+    uint16_t gz2[kBS * kLdH], gz2t[kH * kLdS];
+    uint16_t gz1t[kH * kLdS];
     float target[kBS * 4];
     float red[4][kH + kH + kOutPad + 1];  // per-wave bias-gradient and loss sums
 };
@@ -233,9 +283,9 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
     const int r0 = wave * 16;  // this wave's rows of the block tile
 
-    load_weights(L.W, wb, w, true);
+    load_weights(L.W, &L.T, wb, w);
 
-    // features and target of sample r0 + lr (4 lanes per sample, 20 features each)
+    // features and target of sample r0 + lr (4 lanes per sample)
     {
         const uint32_t j = blockIdx.x * kBS + r0 + lr;
         Pcg32 rng(A.seed, j);
@@ -246,11 +296,10 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         int lp;
         float x[3], n[3];
         vertex_inputs(A.g, v, q, lp, x, n);
-        for (int f = lg; f < kIn; f += 4) {
-            const uint16_t val = feature(f, q, lp, x, n, A.g.cam);
+        vertex_features(lg, q, lp, x, n, A.g.cam, [&](int f, uint16_t val) {
             L.x[(r0 + lr) * kIn + f] = val;
-            L.xt[f * kBS + r0 + lr] = val;
-        }
+            L.xt[f * kLdS + r0 + lr] = val;
+        });
         if (lg == 0) {
             const pf_cell c = A.t.cell_at(A.slot[v]);
             L.target[(r0 + lr) * 4 + 0] = A.t.average(c, 0);
@@ -262,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
 
     // forward (this wave's 16 rows)
     v4f z1[4], z2[4];
-    const v4f y = forward_tile(L.W, L.x, L.a1, L.a2, L.a1t, L.a2t, kBS, r0, z1, z2);
+    const v4f y = forward_tile(L.W, L.x, L.a1, L.a2, kLdH, L.a1t, L.a2t, kLdS, r0, z1, z2);
 
     // output gradient: gy = 2 (y - t) / (3 B) for the 3 live outputs
     float loss = 0.0f, gyv[4];
@@ -275,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         gyv[i] = A.gscale * d;
         L.gy[row * kOutPad + lr] = bf16(gyv[i]);
     }
-    st4(L.gyt + lr * kBS + r0 + 4 * lg, gyv[0], gyv[1], gyv[2], gyv[3]);
+    st4(L.gyt + lr * kLdS + r0 + 4 * lg, gyv[0], gyv[1], gyv[2], gyv[3]);
     {
         const float s3 = col_sum((gyv[0] + gyv[1]) + (gyv[2] + gyv[3]));
         const float sl = col_sum(loss);
@@ -294,15 +343,15 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         v4f d = {0, 0, 0, 0};
-        d = mfma(ld4(L.gy + (r0 + lr) * kOutPad + 4 * lg), ld4(L.W.w3t + (nt * 16 + lr) * kOutPad + 4 * lg), d);
+        d = mfma(ld4(L.gy + (r0 + lr) * kOutPad + 4 * lg), ld4(L.T.w3t + (nt * 16 + lr) * kOutPad + 4 * lg), d);
         const int n = nt * 16 + lr;
         float g[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             g[i] = z2[nt][i] > 0.0f ? d[i] : 0.0f;
-            L.gz2[(r0 + 4 * lg + i) * kH + n] = bf16(g[i]);
+            L.gz2[(r0 + 4 * lg + i) * kLdH + n] = bf16(g[i]);
         }
-        st4(L.gz2t + n * kBS + r0 + 4 * lg, g[0], g[1], g[2], g[3]);
+        st4(L.gz2t + n * kLdS + r0 + 4 * lg, g[0], g[1], g[2], g[3]);
         const float s = col_sum((g[0] + g[1]) + (g[2] + g[3]));
         if (lg == 0) L.red[wave][kH + n] = s;
     }
@@ -315,13 +364,13 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         v4f d = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < kH / 16; ++kk)
-            d = mfma(ld4(L.gz2 + (r0 + lr) * kH + kk * 16 + 4 * lg),
-                     ld4(L.W.w2t + (nt * 16 + lr) * kH + kk * 16 + 4 * lg), d);
+            d = mfma(ld4(L.gz2 + (r0 + lr) * kLdH + kk * 16 + 4 * lg),
+                     ld4(L.T.w2t + (nt * 16 + lr) * kLdH + kk * 16 + 4 * lg), d);
         const int n = nt * 16 + lr;
         float g[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) g[i] = z1[nt][i] > 0.0f ? d[i] : 0.0f;
-        st4(L.gz1t + n * kBS + r0 + 4 * lg, g[0], g[1], g[2], g[3]);
+        st4(L.gz1t + n * kLdS + r0 + 4 * lg, g[0], g[1], g[2], g[3]);
         const float s = col_sum((g[0] + g[1]) + (g[2] + g[3]));
         if (lg == 0) L.red[wave][n] = s;
     }
@@ -334,8 +383,8 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         v4f acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < kBS / 16; ++kk)
-            acc = mfma(ld4(L.gz1t + (mt * 16 + lr) * kBS + kk * 16 + 4 * lg),
-                       ld4(L.xt + (nt * 16 + lr) * kBS + kk * 16 + 4 * lg), acc);
+            acc = mfma(ld4(L.gz1t + (mt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
+                       ld4(L.xt + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg), acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[kOffW1 + (mt * 16 + 4 * lg + i) * kIn + nt * 16 + lr] = acc[i];
     }
@@ -345,8 +394,8 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         v4f acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < kBS / 16; ++kk)
-            acc = mfma(ld4(L.gz2t + (mt * 16 + lr) * kBS + kk * 16 + 4 * lg),
-                       ld4(L.a1t + (nt * 16 + lr) * kBS + kk * 16 + 4 * lg), acc);
+            acc = mfma(ld4(L.gz2t + (mt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
+                       ld4(L.a1t + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg), acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[kOffW2 + (mt * 16 + 4 * lg + i) * kH + nt * 16 + lr] = acc[i];
     }
@@ -356,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         v4f acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < kBS / 16; ++kk)
-            acc = mfma(ld4(L.gyt + lr * kBS + kk * 16 + 4 * lg), ld4(L.a2t + (nt * 16 + lr) * kBS + kk * 16 + 4 * lg),
+            acc = mfma(ld4(L.gyt + lr * kLdS + kk * 16 + 4 * lg), ld4(L.a2t + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
                        acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[kOffW3 + (4 * lg + i) * kH + nt * 16 + lr] = acc[i];
@@ -421,13 +470,16 @@ __global__ __launch_bounds__(kThreads) void reduce_adam_kernel(float *__restrict
     wb[p] = bf16(wn);
 }
 
+// Per wave: the tile's features (then, once layer 1 has read them, its
+// outputs) and one activation buffer that layer 2 overwrites after reading
+// it (all of a wave's reads of a1 complete before its first write), so
+// that four workgroups fit a CU.
 struct InferLds {
     Weights W;
     uint16_t x[4 * 16 * kIn];
     uint16_t a1[4 * 16 * kH];
-    uint16_t a2[4 * 16 * kH];
-    float y[4 * 16 * kOutPad];
 };
+static_assert(16 * kIn * sizeof(uint16_t) >= 16 * kOutPad * sizeof(float), "outputs fit a wave's feature rows");
 
 __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *__restrict__ wb,
                                                           const float *__restrict__ w, const uint32_t *idx,
@@ -436,13 +488,13 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
     InferLds &L = *reinterpret_cast<InferLds *>(smem);
     const uint32_t n = counts[1];
     if (n == 0) return;
-    load_weights(L.W, wb, w, false);
+    load_weights(L.W, nullptr, wb, w);
     __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
     uint16_t *x = L.x + wave * 16 * kIn;
     uint16_t *a1 = L.a1 + wave * 16 * kH;
-    uint16_t *a2 = L.a2 + wave * 16 * kH;
-    float *yb = L.y + wave * 16 * kOutPad;
+    uint16_t *a2 = a1;
+    float *yb = reinterpret_cast<float *>(x);
     const uint32_t ntiles = (n + 15) / 16;
     for (uint32_t tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
         const uint32_t e = tile * 16 + lr;
@@ -453,14 +505,14 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
             int lp;
             float xv[3], nv[3];
             vertex_inputs(g, vtx, q, lp, xv, nv);
-            for (int f = lg; f < kIn; f += 4) x[lr * kIn + f] = feature(f, q, lp, xv, nv, g.cam);
+            vertex_features(lg, q, lp, xv, nv, g.cam, [&](int f, uint16_t val) { x[lr * kIn + f] = val; });
         } else {
             for (int f = lg; f < kIn; f += 4) x[lr * kIn + f] = 0;
         }
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
         v4f z1[4], z2[4];
-        const v4f y = forward_tile(L.W, x, a1, a2, nullptr, nullptr, 0, 0, z1, z2);
+        const v4f y = forward_tile(L.W, x, a1, a2, kH, nullptr, nullptr, 0, 0, z1, z2);
 #pragma unroll
         for (int i = 0; i < 4; ++i) yb[(4 * lg + i) * kOutPad + lr] = y[i];
         __builtin_amdgcn_s_waitcnt(0);
@@ -552,15 +604,33 @@ __global__ __launch_bounds__(1024) void select_scan_kernel(uint32_t *bcnt, uint3
         s_sum[list][threadIdx.x] = local;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {  // serial scan of 1024 partials per list (cheap)
+    // exclusive scan of the 1024 partials of each list: inclusive scans
+    // within each wavefront (shuffles), then over the 16 wavefront totals
+    __shared__ uint32_t s_wave[2][16];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl[2];
+    for (int list = 0; list < 2; ++list) {
+        uint32_t v = s_sum[list][threadIdx.x];
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(v, off);
+            if (lane >= off) v += o;
+        }
+        incl[list] = v;
+        if (lane == 63) s_wave[list][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {  // 16 wavefront totals per list
         uint32_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const uint32_t t = s_sum[threadIdx.x][k];
-            s_sum[threadIdx.x][k] = run;
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t t = s_wave[threadIdx.x][k];
+            s_wave[threadIdx.x][k] = run;
             run += t;
         }
         counts[threadIdx.x] = run;
     }
+    __syncthreads();
+    for (int list = 0; list < 2; ++list)
+        s_sum[list][threadIdx.x] = s_wave[list][wave] + incl[list] - s_sum[list][threadIdx.x];
     __syncthreads();
     for (int list = 0; list < 2; ++list) {
         uint32_t *c = bcnt + list * nblocks;

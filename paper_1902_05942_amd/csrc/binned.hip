@@ -10,22 +10,21 @@
 //              sums added with LDS atomics; the LDS serialises the lanes of
 //              a coherent run on one entry more cheaply than a wavefront
 //              prefix sum over them costs in VALU work, which bounds this
-//              kernel); each group then probes / claims its cell once
-//              (compare-and-swap on new cells only) and writes one record
-//              {slot, count, sums} into its bin's bucket (a bin is a range
-//              of slots; a bucket has one part per XCD, so that the records
-//              of a cache line are written through one L2), its position
-//              taken with one device atomic add; every vertex receives its
-//              group's slot
-//   reduce     per bin: records summed in LDS, then count and sums added
-//              to the cells with plain loads and stores by the workgroup
-//              that owns them, occupancy bits set; with a temporal blend
-//              (Section 3.4.1) in the same launch, the owner also blends
-//              each cell's final average with the previous table's value of
-//              its key and stores the temporal value
-// A bucket part that is full (never at the workloads' densities: it holds
-// twice a vertex's share) takes further groups' counts and sums by device
-// atomics on the cell instead, and the group's occupancy bit is set at once.
+//              kernel); each group then probes / claims its cell
+//              once (compare-and-swap on new cells only), writes one record
+//              {slot, count, sums} to the tile's staging area and counts it
+//              in the tile's histogram of slot bins; every vertex receives
+//              its group's slot
+//   colscan    per bin: running record offsets over the tiles, bin totals
+//   scatter    per tile: the start offset of every bin (each workgroup scans
+//              the bin totals itself), then staged records moved to their
+//              bin's range
+//   reduce     per bin (a contiguous slot range): records summed in LDS, then
+//              count and sums added to the cells with plain loads and stores
+//              by the workgroup that owns them, occupancy bits set; with a
+//              temporal blend (Section 3.4.1) in the same launch, the owner
+//              also blends each cell's final average with the previous
+//              table's value of its key and stores the temporal value
 // Integer sums make the result identical to the atomic insert.
 #include <mutex>
 
@@ -61,47 +60,45 @@ struct FusedKeys {
     uint64_t *key_out;  // nullable
 };
 
-constexpr uint32_t kXcds = 8;  // bucket parts per bin: workgroup w runs on XCD w % 8
-
 struct Plan {
-    uint32_t log2_bins, nbins, bin_shift, bin_slots, ntiles, cap, parts, part_cap;
+    uint32_t log2_bins, nbins, bin_shift, bin_slots, ntiles, tile, cap;
     size_t lds_aggregate, lds_reduce;
-    size_t off_cnt, off_rec, bytes;
+    size_t off_h, off_tot, off_start, off_ntr, off_trec, off_rec, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 Plan make_plan(uint32_t n, uint32_t log2_slots) {
     Plan p;
-    // bins of 2048 slots (4096 above 2^24 slots)
+    // bins of 2048 slots (4096 above 2^24 slots, keeping the histogram small)
     uint32_t lbs = log2_slots > 24 ? 12 : 11;
     if (lbs > log2_slots) lbs = log2_slots;
     p.bin_shift = lbs;
     p.bin_slots = 1u << lbs;
     p.log2_bins = log2_slots - lbs;
     p.nbins = 1u << p.log2_bins;
-    // a tile is the set of chunks one workgroup takes (every ntiles-th)
+    // a tile is the set of chunks one workgroup takes (every ntiles-th);
+    // its staging area holds a record per vertex at most
     const uint32_t nchunks = (n + kChunk - 1) / kChunk;
     p.ntiles = nchunks < kMaxTiles ? (nchunks ? nchunks : 1) : kMaxTiles;
-    // LDS of aggregate: key 8 B, sums 24 B and count 4 B per entry, four
-    // counters, the chunk's list of valid vertices and each vertex's entry
-    // (2 B each per vertex); entries take what the budget leaves
-    const size_t fixed = 16 + (size_t)kChunk * 4;
+    p.tile = (nchunks + p.ntiles - 1) / p.ntiles * kChunk;
+    if (p.tile == 0) p.tile = kChunk;
+    // LDS of aggregate: key 8 B, sums 24 B and count 4 B per entry, the bin
+    // histogram and two counters; entries take what the budget leaves
+    const size_t fixed = (size_t)p.nbins * 4 + 16;
     uint32_t cap = (uint32_t)((kLdsBudget - fixed) / 36) / 64 * 64;
+    if (cap < 512) cap = 512;
     if (cap > kFlush * kT) cap = kFlush * kT;
     p.cap = cap;
     p.lds_aggregate = (size_t)cap * 36 + fixed;
     p.lds_reduce = (size_t)p.bin_slots * 28;
-    // bucket parts (one per XCD, fewer when fewer workgroups run): together
-    // twice one record per vertex, each part a multiple of 4 records (whole
-    // 128-byte lines)
-    p.parts = p.ntiles < kXcds ? p.ntiles : kXcds;
-    const uint64_t nparts = (uint64_t)p.nbins * p.parts;
-    const uint64_t want = 2ull * (n ? n : 1);
-    p.part_cap = (uint32_t)(((want + nparts - 1) / nparts + 3) / 4 * 4);
-    p.off_cnt = 0;
-    p.off_rec = align256(nparts * 4);
-    p.bytes = p.off_rec + align256(nparts * p.part_cap * sizeof(Rec)) + 256;
+    p.off_h = 0;
+    p.off_tot = align256((size_t)p.ntiles * p.nbins * 4);
+    p.off_start = p.off_tot + align256((size_t)p.nbins * 4);
+    p.off_ntr = p.off_start + align256((size_t)p.nbins * 4);
+    p.off_trec = p.off_ntr + align256((size_t)p.ntiles * 4);
+    p.off_rec = p.off_trec + align256((size_t)p.ntiles * p.tile * sizeof(Rec));
+    p.bytes = p.off_rec + align256((size_t)(n ? n : 1) * sizeof(Rec)) + 256;
     return p;
 }
 
@@ -148,60 +145,29 @@ __device__ __forceinline__ uint8_t fused_key(const FusedKeys &fk, uint32_t i, ui
     return vertex_key(x, nr, true, fk.a.cam, fk.a.s, fk.a.inv_s, jp, i, fk.a.mask, k, fp, home);
 }
 
-// A group whose bucket part is full: its count and sums go to the cell by
-// device atomics and its occupancy bit is set now (reduce sets the bits of
-// the cells it receives records for).
-__device__ __noinline__ void spill(const Tab &t, uint32_t s, uint32_t count, uint64_t s0, uint64_t s1, uint64_t s2) {
-    accumulate(t, s, count, (int64_t)s0, (int64_t)s1, (int64_t)s2);
-    __hip_atomic_fetch_or(&t.occ[s >> 5], 1u << (s & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Where the records of this workgroup's groups go: bin b's part `part` of
-// `parts` (the workgroup's XCD), part_cap records each.
-struct Buckets {
-    uint32_t *cnt;
-    Rec *rec;
-    uint32_t bin_shift, parts, part, part_cap;
-};
-
-// Position of a record of slot s in its bin's bucket part.
-__device__ __forceinline__ uint32_t bucket_pos(const Buckets &bk, uint32_t s) {
-    return __hip_atomic_fetch_add(&bk.cnt[(s >> bk.bin_shift) * bk.parts + bk.part], 1u, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void put_rec(const Tab &t, const Buckets &bk, uint32_t pos, uint32_t s, uint32_t count,
-                                        uint64_t s0, uint64_t s1, uint64_t s2) {
-    if (pos < bk.part_cap)
-        store_rec(bk.rec + ((size_t)(s >> bk.bin_shift) * bk.parts + bk.part) * bk.part_cap + pos, s, count, s0, s1,
-                  s2);
-    else
-        spill(t, s, count, s0, s1, s2);
-}
-
 // kKeys: keys are built here from positions and normals (fk) and the flags
 // are outputs only; otherwise key[] and flags[] come from pf_build_keys.
 template <bool kKeys>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void aggregate_kernel(
     Tab t, const uint64_t *__restrict__ key, const float *__restrict__ r, const float *__restrict__ g,
     const float *__restrict__ b, uint8_t *__restrict__ flags, uint32_t *__restrict__ slot_out, uint32_t n,
-    uint32_t cap, Buckets bk, FusedKeys fk) {
+    uint32_t tile, uint32_t cap, uint32_t nbins, uint32_t bin_shift, uint32_t *__restrict__ H,
+    uint32_t *__restrict__ ntr, Rec *__restrict__ trec, FusedKeys fk) {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *lkey = reinterpret_cast<unsigned long long *>(lds);
     unsigned long long *ls0 = lkey + cap, *ls1 = ls0 + cap, *ls2 = ls1 + cap;
     uint32_t *lcnt = reinterpret_cast<uint32_t *>(ls2 + cap);  // count, then the group's slot
-    uint32_t *misc = lcnt + cap;                                // [0] listed vertices, [1] overflowed vertices
-    uint16_t *vlist = reinterpret_cast<uint16_t *>(misc + 4);   // the chunk's valid vertices (local indices)
-    uint16_t *vent = vlist + kChunk;                            // per local vertex: flags << 11 | entry
+    uint32_t *hist = lcnt + cap;
+    uint32_t *misc = hist + nbins;                              // [0] staged records, [1] overflowed vertices
+    for (uint32_t k = threadIdx.x; k < nbins; k += kT) hist[k] = 0;
     if (threadIdx.x < 2) misc[threadIdx.x] = 0;
-    bk.part = blockIdx.x % bk.parts;
     // chunks are dealt out with a stride so that every workgroup gets a mix
     // of coherent and incoherent (or empty) parts of the stream
     const uint32_t nchunks = (n + kChunk - 1) / kChunk;
+    Rec *out = trec + (size_t)blockIdx.x * tile;
     for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
         const uint32_t c0 = ci * kChunk;
         const uint32_t i1 = min(n, c0 + kChunk);
-        if (threadIdx.x == 0) misc[0] = 0;
         for (uint32_t j = threadIdx.x; j < cap; j += kT) {
             lkey[j] = kEmpty;
             ls0[j] = 0;
@@ -215,45 +181,32 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         // vertex that finds no room reloads its key and contribution
         uint32_t flp0 = 0, flp = 0;
         uint64_t ep = 0;
-        uint32_t live = 0;
         if constexpr (kKeys) {
             flp0 = 0xffffffffu;  // no input flags: every vertex's flags are written
             // the valid bytes of the thread's vertices first: masked vertices
-            // (sky, escaped paths) read nothing more.  The valid vertices are
-            // listed (each wavefront's in one run, in vertex order), so that
-            // key construction runs on full wavefronts: a bounce segment holds
-            // about one valid vertex in four
+            // (sky, escaped paths) read nothing more
+            uint32_t live = 0;
 #pragma unroll
             for (uint32_t u = 0; u < kPer; ++u) {
                 const uint32_t i = c0 + u * kT + threadIdx.x;
                 const bool v = i < i1 && (fk.valid == nullptr || fk.valid[i] != 0);
                 live |= (v ? 1u : 0u) << u;
             }
-#pragma unroll
-            for (uint32_t u = 0; u < kPer; ++u) {
-                const bool v = (live >> u) & 1u;
-                const uint32_t pos = wave_reserve(&misc[0], v);
-                if (v) vlist[pos] = (uint16_t)(u * kT + threadIdx.x);
-            }
-            __syncthreads();
-            const uint32_t nlisted = misc[0];
 #pragma unroll 1
-            for (uint32_t j0 = 0; j0 < nlisted; j0 += kT) {
-                const uint32_t j = j0 + threadIdx.x;
-                const bool on = j < nlisted;
-                const uint32_t li = on ? vlist[j] : 0u;
-                const uint32_t i = c0 + li;
+            for (uint32_t u = 0; u < kPer; ++u) {
+                const uint32_t i = c0 + u * kT + threadIdx.x;
                 uint32_t f = PF_V_INVALID;
                 uint64_t k = 0;
                 int64_t q0 = 0, q1 = 0, q2 = 0;
-                if (on) {
+                if ((live >> u) & 1u) {
                     const float cr = r[i], cg = g[i], cb = b[i];
                     f = fused_key(fk, i, k);
                     if (f == 0) f = fixed_point(cr, cg, cb, t.frac_bits, q0, q1, q2);
-                    if (fk.key_out) fk.key_out[i] = k;
                 }
-                const int e = merge_into_lds<false>(lkey, ls0, ls1, ls2, lcnt, cap, on && f == 0, k, q0, q1, q2);
-                if (on) vent[li] = (uint16_t)((f << 11) | (e < 0 ? 0x7ffu : (uint32_t)e));
+                if (fk.key_out && i < i1) fk.key_out[i] = k;
+                flp |= f << (8 * u);
+                const int e = merge_into_lds<false>(lkey, ls0, ls1, ls2, lcnt, cap, f == 0, k, q0, q1, q2);
+                ep |= (uint64_t)(uint16_t)e << (16 * u);
             }
         } else {
 #pragma unroll
@@ -293,22 +246,9 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         }
         __syncthreads();
-        if constexpr (kKeys) {  // the thread's vertices' flags and entries, packed as in the other mode
-#pragma unroll
-            for (uint32_t u = 0; u < kPer; ++u) {
-                uint32_t f = PF_V_INVALID, e = 0xffffu;
-                if ((live >> u) & 1u) {
-                    const uint32_t ve = vent[u * kT + threadIdx.x];
-                    f = ve >> 11;
-                    e = (ve & 0x7ffu) == 0x7ffu ? 0xffffu : (ve & 0x7ffu);
-                }
-                flp |= f << (8 * u);
-                ep |= (uint64_t)e << (16 * u);
-            }
-        }
-        // one probe / claim and one record per group; a thread's entries
-        // issue their home-slot loads, then their compare-and-swaps on empty
-        // home slots, then their bucket positions, before any result is used
+        // one probe / claim and one staged record per group; a thread's
+        // entries issue their home-slot loads, then their compare-and-swaps
+        // on empty home slots, before either result is needed
         uint64_t gk[kFlush];
         uint32_t fs[kFlush], ff[kFlush], fcur[kFlush];
 #pragma unroll
@@ -335,30 +275,23 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 fcur[v] = won[v] ? ff[v] : expected;
             }
         }
-        uint32_t sl[kFlush], pos[kFlush];
 #pragma unroll
         for (uint32_t v = 0; v < kFlush; ++v) {
             const uint32_t j = v * kT + threadIdx.x;
-            sl[v] = kNoSlot;
-            pos[v] = 0;
+            uint32_t s = kNoSlot;
             if (gk[v] != kEmpty) {
                 if (won[v]) t.key_at(fs[v]) = gk[v];
                 // the home slot holds another key: probe on from the next
-                sl[v] = fcur[v] == ff[v] ? fs[v] : claim_next(t, gk[v], ff[v], (fs[v] + 1) & t.mask, 1);
-                if (sl[v] == kNoSlot)
-                    atomicAdd(&misc[1], lcnt[j]);
-                else
-                    pos[v] = bucket_pos(bk, sl[v]);
+                s = fcur[v] == ff[v] ? fs[v] : claim_next(t, gk[v], ff[v], (fs[v] + 1) & t.mask, 1);
+                if (s == kNoSlot) atomicAdd(&misc[1], lcnt[j]);
             }
-        }
-#pragma unroll
-        for (uint32_t v = 0; v < kFlush; ++v) {
-            const uint32_t j = v * kT + threadIdx.x;
-            if (gk[v] != kEmpty) {
-                if (sl[v] != kNoSlot)
-                    put_rec(t, bk, pos[v], sl[v], lcnt[j], ls0[j], ls1[j], ls2[j]);
-                lcnt[j] = sl[v];
+            const bool stage = gk[v] != kEmpty && s != kNoSlot;
+            const uint32_t pos = wave_reserve(&misc[0], stage);
+            if (stage) {
+                store_rec(out + pos, s, lcnt[j], ls0[j], ls1[j], ls2[j]);
+                atomicAdd(&hist[s >> bin_shift], 1u);
             }
+            if (gk[v] != kEmpty) lcnt[j] = s;
         }
         __syncthreads();
 #pragma unroll 1
@@ -367,11 +300,12 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             uint32_t f = (flp >> (8 * u)) & 0xffu;
             const uint32_t e = (uint32_t)(ep >> (16 * u)) & 0xffffu;
             uint32_t s = kNoSlot;
+            bool alone = false;
+            int64_t q0 = 0, q1 = 0, q2 = 0;
             if (f == 0) {
                 if (e != 0xffffu) {
                     s = lcnt[e];
                 } else {  // no room in the LDS table: a group of its own
-                    int64_t q0, q1, q2;
                     fixed_point(r[i], g[i], b[i], t.frac_bits, q0, q1, q2);
                     uint64_t k;
                     if constexpr (kKeys)
@@ -379,30 +313,145 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                     else
                         k = key[i];
                     s = claim(t, k);
-                    if (s != kNoSlot)
-                        put_rec(t, bk, bucket_pos(bk, s), s, 1u, (uint64_t)q0, (uint64_t)q1, (uint64_t)q2);
-                    else
-                        atomicAdd(&misc[1], 1u);
+                    alone = s != kNoSlot;
+                    if (!alone) atomicAdd(&misc[1], 1u);
                 }
                 if (s == kNoSlot) f = PF_V_OVERFLOW;
+            }
+            const uint32_t pos = wave_reserve(&misc[0], alone);
+            if (alone) {
+                store_rec(out + pos, s, 1u, (uint64_t)q0, (uint64_t)q1, (uint64_t)q2);
+                atomicAdd(&hist[s >> bin_shift], 1u);
             }
             if (i < i1) {
                 if (f != ((flp0 >> (8 * u)) & 0xffu)) flags[i] = (uint8_t)f;
                 slot_out[i] = s;
-                if constexpr (kKeys)
-                    if (fk.key_out && !((live >> u) & 1u)) fk.key_out[i] = 0;
             }
         }
         __syncthreads();  // the table is cleared for the next chunk
     }
-    if (threadIdx.x == 0 && misc[1]) add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], misc[1]);
+    __syncthreads();
+    uint32_t *row = H + (size_t)blockIdx.x * nbins;
+    for (uint32_t k = threadIdx.x; k < nbins; k += kT) row[k] = hist[k];
+    if (threadIdx.x == 0) {
+        ntr[blockIdx.x] = misc[0];
+        if (misc[1]) add_u64(&t.stats[PF_STAT_PART_OVF + (blockIdx.x & 15)], misc[1]);
+    }
 }
 
-__global__ void zero_kernel(uint32_t *__restrict__ p, uint32_t m) {
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) p[j] = 0;
+// Per bin: exclusive running offset over the tiles (in place), bin total.
+// Tiles are taken XCD by XCD (workgroups are dealt to the 8 XCDs in turn,
+// so tile t runs on XCD t % 8): a bin's range is cut into 8 sub-ranges each
+// written by the scatter workgroups of one XCD, and a cache line of records
+// is filled through one L2 instead of several.
+// A workgroup takes 16 bins; each of its 64 rows of lanes holds the counts of
+// 8 consecutive tiles of that order in registers, so a column is loaded
+// once, summed in parallel and rewritten without a second read.
+constexpr int kScanBins = 16, kScanRows = 64, kScanPer = 8;
+constexpr uint32_t kXcds = 8;
+static_assert(kScanRows * kScanPer >= kMaxTiles, "one register batch covers every tile");
+static_assert(kMaxTiles % kXcds == 0, "tiles split evenly over the XCDs");
+__global__ __launch_bounds__(kScanBins *kScanRows) void colscan_kernel(uint32_t *__restrict__ H, uint32_t ntiles,
+                                                                       uint32_t nbins,
+                                                                       uint32_t *__restrict__ total) {
+    __shared__ uint32_t part[kScanRows][kScanBins + 1];
+    const uint32_t bx = threadIdx.x % kScanBins, cy = threadIdx.x / kScanBins;
+    const uint32_t bin = blockIdx.x * kScanBins + bx;
+    const uint32_t per = (ntiles + kXcds - 1) / kXcds;  // tiles per XCD (at most 64)
+    const uint32_t q0 = cy * kScanPer;
+    uint32_t v[kScanPer], tt[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t q = q0 + k;  // position in XCD-major order
+        tt[k] = (q % per) * kXcds + q / per;
+        const bool in = bin < nbins && q < kXcds * per && tt[k] < ntiles;
+        if (!in) tt[k] = ~0u;
+        v[k] = in ? H[(size_t)tt[k] * nbins + bin] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += v[k];
+    part[cy][bx] = s;
+    __syncthreads();
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < cy; ++c) run += part[c][bx];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (tt[k] != ~0u) H[(size_t)tt[k] * nbins + bin] = run;
+        run += v[k];
+    }
+    if (cy == kScanRows - 1 && bin < nbins) total[bin] = run;
 }
 
-constexpr uint32_t kBatch = 4;  // records per thread loaded before any is used
+constexpr uint32_t kBatch = 4;  // records per thread loaded before any is moved
+
+__global__ __launch_bounds__(kT) void scatter_kernel(const Rec *__restrict__ trec, const uint32_t *__restrict__ ntr,
+                                                     uint32_t tile, uint32_t nbins, uint32_t bin_shift,
+                                                     const uint32_t *__restrict__ H,
+                                                     const uint32_t *__restrict__ total, uint32_t *__restrict__ start,
+                                                     Rec *__restrict__ rec) {
+    extern __shared__ uint32_t cursor[];
+    __shared__ uint32_t part[kT];
+    const uint4 *in = reinterpret_cast<const uint4 *>(trec + (size_t)blockIdx.x * tile);
+    const uint32_t m = ntr[blockIdx.x];
+    uint4 lo[kBatch], hi[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {  // first batch in flight while the cursors are set up
+        const uint32_t j = u * kT + threadIdx.x;
+        if (j < m) {
+            lo[u] = in[2 * j];
+            hi[u] = in[2 * j + 1];
+        }
+    }
+    // every workgroup scans the bin totals itself (a few KB, L2-resident)
+    // instead of waiting for a launch of its own; workgroup 0 stores the
+    // bins' start offsets for reduce.  Each lane takes `per` consecutive
+    // bins; a Hillis-Steele scan runs over the lanes' partial sums.
+    const uint32_t *row = H + (size_t)blockIdx.x * nbins;
+    const uint32_t per = (nbins + kT - 1) / kT;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nbins) local += total[b0 + k];
+    part[threadIdx.x] = local;
+    __syncthreads();
+    for (uint32_t off = 1; off < kT; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - local;  // exclusive
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < nbins) {
+            cursor[b0 + k] = run + row[b0 + k];
+            if (blockIdx.x == 0) start[b0 + k] = run;
+            run += total[b0 + k];
+        }
+    __syncthreads();
+    for (uint32_t j0 = 0; j0 < m; j0 += kBatch * kT) {
+        if (j0) {
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) {
+                const uint32_t j = j0 + u * kT + threadIdx.x;
+                if (j < m) {
+                    lo[u] = in[2 * j];
+                    hi[u] = in[2 * j + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t j = j0 + u * kT + threadIdx.x;
+            if (j < m) {
+                const uint32_t pos = atomicAdd(&cursor[lo[u].x >> bin_shift], 1u);
+                uint4 *o = reinterpret_cast<uint4 *>(rec + pos);
+                o[0] = lo[u];
+                o[1] = hi[u];
+            }
+        }
+    }
+}
 
 // The temporal blend done by reduce: the previous table (has_prev) and the
 // blend's parameters as pf_temporal_update / pf_temporal_integrate take them.
@@ -412,22 +461,19 @@ struct Blend {
     uint32_t cap;
 };
 
-// One workgroup per bin: LDS sums over its records (the bucket parts of
-// the XCDs), then the exclusive owner adds them to the cells and sets the
-// occupancy bits of its words.  kBlend: the owner then computes the temporal
-// values of its cells (the cells are final: every record of a slot is in the
-// slot's bin, and spilled groups went to their cells before this launch), as
+// One workgroup per bin: LDS sums over its records, then the exclusive
+// owner adds them to the cells and sets the occupancy bits of its words.
+// kBlend: the owner then computes the temporal values of its cells (the
+// cells are final: every record of a slot is in the slot's bin), as
 // temporal_word does for one bitmap word.
 template <bool kBlend = false, bool kHasPrev = false, bool kIntegrate = false>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec *__restrict__ rec,
-                                                                const uint32_t *__restrict__ cnt_parts,
-                                                                uint32_t parts, uint32_t part_cap, uint32_t bin_slots,
-                                                                Blend bl) {
+                                                                const uint32_t *__restrict__ start,
+                                                                const uint32_t *__restrict__ total,
+                                                                uint32_t bin_slots, Blend bl) {
     extern __shared__ unsigned long long lred[];
     unsigned long long *sum0 = lred, *sum1 = lred + bin_slots, *sum2 = lred + 2 * bin_slots;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(lred + 3 * bin_slots);
-    __shared__ uint32_t seg[kXcds + 1];    // running record counts of the parts
-    __shared__ uint32_t spilled[4096 / 32];  // occupancy bits set by spilled groups (kBlend)
     const uint32_t bin = blockIdx.x;
     const uint32_t base = bin * bin_slots;
     for (uint32_t k = threadIdx.x; k < bin_slots; k += kReduceThreads) {
@@ -436,36 +482,17 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
         sum2[k] = 0;
         cnt[k] = 0;
     }
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (uint32_t x = 0; x < kXcds; ++x) {
-            seg[x] = acc;
-            const uint32_t c = x < parts ? cnt_parts[bin * parts + x] : 0u;
-            acc += c < part_cap ? c : part_cap;
-        }
-        seg[kXcds] = acc;
-    }
-    if constexpr (kBlend) {
-        // before this launch only spilled groups set bits (the table was
-        // empty before the insert)
-        for (uint32_t w = threadIdx.x; w < (bin_slots + 31) / 32; w += kReduceThreads)
-            spilled[w] = t.occ[(base >> 5) + w];
-    }
     __syncthreads();
-    const uint4 *in = reinterpret_cast<const uint4 *>(rec + (size_t)bin * parts * part_cap);
-    const uint32_t j1 = seg[kXcds];
-    for (uint32_t jb = 0; jb < j1; jb += kBatch * kReduceThreads) {
+    const uint4 *in = reinterpret_cast<const uint4 *>(rec);
+    const uint32_t j0 = start[bin], j1 = j0 + total[bin];
+    for (uint32_t jb = j0; jb < j1; jb += kBatch * kReduceThreads) {
         uint4 lo[kBatch], hi[kBatch];
 #pragma unroll
         for (uint32_t u = 0; u < kBatch; ++u) {
             const uint32_t j = jb + u * kReduceThreads + threadIdx.x;
             if (j < j1) {
-                uint32_t x = 0;
-#pragma unroll
-                for (uint32_t y = 1; y < kXcds; ++y) x = j >= seg[y] ? y : x;
-                const size_t at = (size_t)x * part_cap + (j - seg[x]);
-                lo[u] = in[2 * at];
-                hi[u] = in[2 * at + 1];
+                lo[u] = in[2 * (size_t)j];
+                hi[u] = in[2 * (size_t)j + 1];
             }
         }
 #pragma unroll
@@ -528,7 +555,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(Tab t, const Rec
         }
         __syncthreads();  // the cells are written, the sums no longer read
         for (uint32_t k = threadIdx.x; k < bin_slots; k += kReduceThreads)
-            if (cnt[k] || ((spilled[k >> 5] >> (k & 31)) & 1u)) list[atomicAdd(&nlist, 1u)] = k;
+            if (cnt[k]) list[atomicAdd(&nlist, 1u)] = k;
         __syncthreads();
         const uint32_t m = nlist;
         for (uint32_t q = threadIdx.x; q < m; q += kReduceThreads) {
@@ -584,7 +611,11 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
     const uint32_t log2_slots = 32 - __builtin_clz(t.mask + 1) - 1;
     const Plan p = make_plan(n, log2_slots);
     char *base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ws) + 255) / 256 * 256);
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(base + p.off_cnt);
+    uint32_t *H = reinterpret_cast<uint32_t *>(base + p.off_h);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(base + p.off_tot);
+    uint32_t *start = reinterpret_cast<uint32_t *>(base + p.off_start);
+    uint32_t *ntr = reinterpret_cast<uint32_t *>(base + p.off_ntr);
+    Rec *trec = reinterpret_cast<Rec *>(base + p.off_trec);
     Rec *rec = reinterpret_cast<Rec *>(base + p.off_rec);
     static bool attrs = false;  // dynamic LDS above 64 KB needs the attribute, set once per function
     if (!attrs) {
@@ -599,26 +630,27 @@ static hipError_t run(const Tab &t, const uint64_t *key, const float *r, const f
         if (e != hipSuccess) return e;
         attrs = true;
     }
-    const uint32_t nparts = p.nbins * p.parts;
-    zero_kernel<<<(nparts + 1023) / 1024 < 256 ? (nparts + 1023) / 1024 : 256, 1024, 0, st>>>(cnt, nparts);
-    const Buckets bk{cnt, rec, p.bin_shift, p.parts, 0, p.part_cap};
-    aggregate_kernel<kKeys><<<p.ntiles, kT, p.lds_aggregate, st>>>(t, key, r, g, b, flags, slot_out, n, p.cap, bk,
-                                                                   fk);
+    aggregate_kernel<kKeys><<<p.ntiles, kT, p.lds_aggregate, st>>>(t, key, r, g, b, flags, slot_out, n, p.tile, p.cap,
+                                                                   p.nbins, p.bin_shift, H, ntr, trec, fk);
+    colscan_kernel<<<(p.nbins + kScanBins - 1) / kScanBins, kScanBins * kScanRows, 0, st>>>(H, p.ntiles, p.nbins,
+                                                                                          tot);
+    scatter_kernel<<<p.ntiles, kT, (size_t)p.nbins * 4, st>>>(trec, ntr, p.tile, p.nbins, p.bin_shift, H, tot,
+                                                              start, rec);
     const Blend none{};
     const Blend &bl = blend ? *blend : none;
     if (!blend)
-        reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, cnt, p.parts, p.part_cap, p.bin_slots, bl);
+        reduce_kernel<<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot, p.bin_slots, bl);
     else if (!has_prev && !integrate)
-        reduce_kernel<true, false, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, cnt, p.parts, p.part_cap,
+        reduce_kernel<true, false, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
                                                                                        p.bin_slots, bl);
     else if (has_prev && !integrate)
-        reduce_kernel<true, true, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, cnt, p.parts, p.part_cap,
+        reduce_kernel<true, true, false><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
                                                                                       p.bin_slots, bl);
     else if (!has_prev)
-        reduce_kernel<true, false, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, cnt, p.parts, p.part_cap,
+        reduce_kernel<true, false, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
                                                                                       p.bin_slots, bl);
     else
-        reduce_kernel<true, true, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, cnt, p.parts, p.part_cap,
+        reduce_kernel<true, true, true><<<p.nbins, kReduceThreads, p.lds_reduce, st>>>(t, rec, start, tot,
                                                                                      p.bin_slots, bl);
     return hipGetLastError();
 }
@@ -710,8 +742,6 @@ hipError_t launch_keys_insert_binned_noalloc(const Tab &t, const float *px, cons
     // call would; each batch's workspace is written before it is read
     for (uint32_t i0 = 0; i0 < n; i0 += binned::kNoAllocBatch) {
         const uint32_t m = n - i0 < binned::kNoAllocBatch ? n - i0 : binned::kNoAllocBatch;
-        const uint32_t log2_slots = 32 - __builtin_clz(t.mask + 1) - 1;
-        if (binned::make_plan(m, log2_slots).bytes + 256 > binned::kScratchBytes) return hipErrorInvalidValue;
         KeyArgs ab = a;
         ab.idx_base = a.idx_base + i0;
         const binned::FusedKeys fk{px + i0, py + i0, pz + i0, nx + i0, ny + i0, nz + i0,

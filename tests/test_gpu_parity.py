@@ -400,13 +400,12 @@ def test_nonfinite_and_out_of_range_radiance(gpu):
 
 
 @pytest.mark.parametrize("temporal", [False, True])
-def test_binned_bucket_parts_overflow_into_atomics(gpu, temporal):
-    """Groups whose bin's bucket part is full go to their cell by device
-    atomics.  700 cells whose slots all lie in one bin, repeated over 600
-    chunks of 4096 vertices: every chunk sends 700 records to that bin,
-    far beyond a part's share, so most groups spill.  The table, counts and
-    averages must still be the oracle's group-by bit for bit (and the
-    temporal variant must blend spilled-only cells too)."""
+def test_binned_insert_with_every_record_in_one_bin(gpu, temporal):
+    """A skewed table: 700 cells whose slots all lie in the first bin of
+    2048 slots, repeated over 600 chunks of 4096 vertices, so that one bin
+    receives ~420k records (every chunk sends it 700) while the other 31
+    receive none.  The table, counts and averages must still be the
+    oracle's group-by bit for bit."""
     m, n, cells = 16, 600 * 4096, 700
     cand = np.arange(1, 400000, dtype=np.uint64) * np.uint64(2654435761)
     home, _ = oracle.key_hashes(cand, m)
@@ -445,13 +444,12 @@ def test_binned_bucket_parts_overflow_into_atomics(gpu, temporal):
     assert_bits_equal(np.stack([o.cpu().numpy() for o in out], 1), R.out, "lookup averages")
 
 
-def test_fused_temporal_insert_with_spilled_cells(gpu):
-    """The temporal blend done in the insert must also blend cells that only
-    spilled groups reached.  Vertices sit at the centres of 600 voxels whose
-    home slots all lie in the first bin of a 2^16-slot table (level 9 for
-    every vertex: the camera is 690 .. 912 units away), repeated over 600
-    chunks, so the bin's bucket parts overflow; two frames, against the
-    oracle bit for bit."""
+def test_fused_temporal_insert_with_every_record_in_one_bin(gpu):
+    """The same skew through the fused insert with the temporal blend:
+    vertices sit at the centres of 600 voxels whose home slots all lie in
+    the first bin of a 2^16-slot table (level 9 for every vertex: the camera
+    is 690 .. 912 units away), repeated over 600 chunks; two frames, against
+    the oracle bit for bit."""
     m, n, cells = 16, 600 * 4096, 600
     s, lvl = 0.01, 9
     h = float(np.ldexp(np.float32(s), lvl))

@@ -593,13 +593,13 @@ typedef struct pf_view {
     const float *px, *py, *pz, *nx, *ny, *nz;
     const uint8_t *valid;     /* nullable */
     const float *r, *g, *b;   /* contributions */
-    uint64_t *key;            /* [n] out */
+    uint64_t *key;            /* [n] out, nullable (8 bytes a vertex that only callers reading the keys need) */
     uint8_t *vflags;          /* [n] out */
     uint32_t *slot;           /* [n] out: cell of each vertex, 0xffffffff if unfiltered */
     float *r_out, *g_out, *b_out;  /* [n] out; must not alias r, g, b */
     uint32_t *count_out;      /* [n] out, nullable */
     pf_table cur;             /* cleared, then filled by this launch */
-    pf_table prev;            /* previous frame (read only); prev.cell == NULL: none */
+    pf_table prev;            /* previous frame (read, then emptied); prev.cell == NULL: none */
     pf_key_params kp;
     uint32_t n;               /* vertices (at most PF_MAX_VERTICES) */
     float alpha_old;          /* moving-average weight of the previous value */
@@ -609,41 +609,54 @@ typedef struct pf_view {
 
 #define PF_MAX_VIEWS 64
 
-/* [host] Device workspace bytes of pf_filter_views for nviews views (barrier
- * counters and the device copy of the descriptors). */
-size_t pf_views_workspace_bytes(uint32_t nviews);
+/* [host] Device workspace bytes of pf_filter_views for nviews views of n[v]
+ * vertices and tables of 2^log2_slots[v] slots (host arrays), enough for
+ * every workgroup size: barrier counters, the device copy of the
+ * descriptors, and per view the records of its insert (32 bytes, about two
+ * per vertex) with their bucket counts.  0 for bad arguments. */
+size_t pf_views_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews);
 
 /* Filters nviews views in ONE persistent launch (a cooperative grid of
- * resident workgroups of `block` threads): per view it clears `cur`, builds
- * the keys and inserts every vertex (as pf_build_keys + pf_insert_accumulate;
- * agg_width 0: one claim and one set of device atomics per vertex; nonzero:
- * each workgroup merges windows of agg_width consecutive vertices by key in
- * an LDS table of min(agg_width, 4 x block, 1536) entries, and each group
- * claims its cell once and adds its count and sums with one set of device
- * atomics; a vertex that finds no room goes alone), computes the temporal
- * values when
- * temporal is set (as pf_temporal_update, mode 0), and looks up every vertex
- * (as pf_query_average with the slots).  Phases are separated by grid-wide
- * barriers; the work items of all views are spread over all workgroups.
- * Results equal those of the single-view calls.
+ * resident workgroups of `block` threads), in four phases separated by
+ * grid-wide barriers, the work items of all views spread over all
+ * workgroups:
+ *   clear      every view's `cur` and its bucket counts;
+ *   insert     keys of every vertex (as pf_build_keys) and its cell
+ *              (Sections 3.2, 3.3.1): agg_width 0 claims the cell and adds
+ *              count and sums with one set of device atomics per vertex;
+ *              otherwise each workgroup merges windows of agg_width
+ *              consecutive vertices by key in an LDS table of
+ *              min(agg_width, 4 x block, 1536) entries (a vertex that finds
+ *              no room goes alone), and each group claims its cell once and
+ *              writes one record {slot, count, sums} into the bucket of its
+ *              bin of min(2 x block, 2048) slots (a full bucket adds the
+ *              group with device atomics instead);
+ *   reduce     per bin, the records summed and added to the cells by one
+ *              workgroup, then, when temporal is set, the temporal values of
+ *              the bin's cells (as pf_temporal_update, mode 0, Section 3.4.1);
+ *   lookup     every vertex (as pf_query_average with the slots), and,
+ *              in the same phase, `prev` emptied (as pf_clear): the temporal
+ *              blend has read it for the last time, so that a caller who
+ *              alternates two tables finds the next frame's `cur` empty and
+ *              the next launch's clear costs nothing.
+ * Results equal those of the single-view calls (integer sums).
  * views: [host] array of nviews descriptors, validated on the host and
  * copied into the workspace before the call returns.  block in
  * {64, 128, 256, 512, 1024}; agg_width 0 or a power of two from block to
- * 8 x block;
- * grid_per_cu: workgroups per compute unit (0 = as many as fit).
- * workspace: pf_views_workspace_bytes(nviews) device bytes, 256-byte
- * aligned; its first uint32 is a status word, non-zero if a barrier wait
- * ever exceeded its bound (every workgroup then stops; with a cooperative
- * launch all workgroups are resident, so it stays 0); the next words hold
- * the grid size and, after a timed-out wait, the arrivals that were seen;
- * words 4..13 hold five 64-bit wall-clock readings of workgroup 0 (start,
- * end of clear, of keys + insert, of temporal values, of its own lookup),
- * in ticks of pf_wall_clock_hz().
+ * 8 x block; grid_per_cu: workgroups per compute unit (0 = as many as fit).
+ * workspace: pf_views_workspace_bytes(n, log2_slots, nviews) device bytes
+ * (workspace_bytes gives its size), 256-byte aligned; its first uint32 is a
+ * status word, non-zero if a barrier wait ever exceeded its bound (every
+ * workgroup then stops; with a cooperative launch all workgroups are
+ * resident, so it stays 0); the next words hold the grid size and, after a
+ * timed-out wait, the arrivals that were seen; words 4..13 hold five 64-bit
+ * wall-clock readings of workgroup 0 (start, end of clear, of insert, of
+ * reduce, of its own lookup), in ticks of pf_wall_clock_hz().
  * Errors: PF_EINVAL (NULL, misaligned, inconsistent descriptor, a
- * PF_SUMS_FLOAT32 table), PF_ERANGE (nviews 0 or above PF_MAX_VIEWS,
- * block, agg_width, parameters), PF_ELAUNCH. */
+ * PF_SUMS_FLOAT32 table, workspace too small), PF_ERANGE (nviews 0 or above
+ * PF_MAX_VIEWS, block, agg_width, parameters), PF_ELAUNCH. */
 pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
-                          uint32_t grid_per_cu, void *workspace, void *stream);
+                          uint32_t grid_per_cu, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------ diagnostics */
 /* ------------------------------------------------------------ diagnostics */

@@ -226,9 +226,9 @@ class MultiViewFilter:
     """
 
     def __init__(self, views, max_probe: int = 64, frac_bits: int = 24, temporal: bool = True,
-                 alpha_old: float = 0.2, device="cuda"):
-        # views: list of (n_max, log2_slots)
-        self.temporal, self.alpha_old = temporal, alpha_old
+                 alpha_old: float = 0.2, device="cuda", keys: bool = True):
+        # views: list of (n_max, log2_slots); keys: write every vertex's key (8 bytes a vertex)
+        self.temporal, self.alpha_old, self.keys = temporal, alpha_old, keys
         sizes = [table_bytes(l, True) for _, l in views]
         ntab = 2 if temporal else 1
         total = sum(sizes) * ntab
@@ -250,7 +250,7 @@ class MultiViewFilter:
                 "count": torch.empty(n, dtype=torch.int32, device=device),
                 "out": tuple(torch.empty(n, dtype=torch.float32, device=device) for _ in range(3)),
             })
-        ws = views_workspace_bytes(len(views))
+        ws = views_workspace_bytes([n for n, _ in views], [l for _, l in views])
         self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self.ws = self.workspace[(-base) % 256:][:ws]
@@ -263,7 +263,7 @@ class MultiViewFilter:
             n = f["px"].numel()
             pair = self.tables[v]
             prev = pair[1] if (self.temporal and self.frames > 0) else None
-            descs.append(make_view(f, b["key"][:n], b["vflags"][:n], b["slot"][:n],
+            descs.append(make_view(f, b["key"][:n] if self.keys else None, b["vflags"][:n], b["slot"][:n],
                                    tuple(o[:n] for o in b["out"]), pair[0], prev,
                                    b["count"][:n] if with_count else None, self.temporal, self.alpha_old))
         return descs
@@ -283,7 +283,7 @@ class MultiViewFilter:
 
     def phase_us(self):
         """Microseconds of the last launch's phases as seen by workgroup 0:
-        clear, keys + insert, temporal values, lookup."""
+        clear, keys + insert, reduce with the temporal values, lookup."""
         w = self.ws[:64].view(torch.int32).cpu().numpy().view("uint32").astype("uint64")
         t = [int(w[4 + 2 * k]) | (int(w[5 + 2 * k]) << 32) for k in range(5)]
         hz = int(_lib.lib.pf_wall_clock_hz()) or 100_000_000

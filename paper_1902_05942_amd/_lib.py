@@ -108,8 +108,8 @@ def _load():
         "pf_temporal_history": ([T, ctypes.POINTER(pf_history), f32, i, u32, u32, vp], i),
         "pf_query_multilevel": ([T, T, vp, vp, vp, vp, vp, vp, vp, u64, u32, i, vp, vp, vp, vp, vp], i),
         "pf_read_stats": ([T, vp, vp], i),
-        "pf_views_workspace_bytes": ([u32], ctypes.c_size_t),
-        "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, vp], i),
+        "pf_views_workspace_bytes": ([ctypes.POINTER(u64), ctypes.POINTER(u32), u32], ctypes.c_size_t),
+        "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, ctypes.c_size_t, vp], i),
         "pf_mlp_bytes": ([u32], ctypes.c_size_t),
         "pf_mlp_carve": ([vp, u32, ctypes.POINTER(pf_mlp)], i),
         "pf_mlp_init": ([ctypes.POINTER(pf_mlp), vp], i),
@@ -512,8 +512,10 @@ def mlp_infer(m: Mlp, geo, sparse_idx, counts, r, g, b, stream=None):
 
 
 # ---------------------------------------------------------------- many views
-def views_workspace_bytes(nviews: int) -> int:
-    return int(lib.pf_views_workspace_bytes(nviews))
+def views_workspace_bytes(ns, log2_slots) -> int:
+    """Workspace bytes of pf_filter_views for views of ns[v] vertices and 2^log2_slots[v]-slot tables."""
+    k = len(ns)
+    return int(lib.pf_views_workspace_bytes((ctypes.c_uint64 * k)(*ns), (ctypes.c_uint32 * k)(*log2_slots), k))
 
 
 def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, temporal=True, alpha_old=0.2,
@@ -523,7 +525,8 @@ def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, 
     for name in ("px", "py", "pz", "nx", "ny", "nz", "r", "g", "b"):
         setattr(d, name, f[name].data_ptr())
     d.valid = f["valid"].data_ptr() if f.get("valid") is not None else None
-    d.key, d.vflags, d.slot = key.data_ptr(), vflags.data_ptr(), slot.data_ptr()
+    d.key = key.data_ptr() if key is not None else None
+    d.vflags, d.slot = vflags.data_ptr(), slot.data_ptr()
     d.r_out, d.g_out, d.b_out = out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr()
     d.count_out = count_out.data_ptr() if count_out is not None else None
     d.cur = cur.t
@@ -534,7 +537,7 @@ def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, 
     d.kp.s = float(f["s"])
     d.kp.seed = int(f["seed"]) & 0xFFFFFFFFFFFFFFFF
     d.kp.idx_base = int(idx_base)
-    d.n = key.numel()
+    d.n = vflags.numel()
     d.alpha_old = float(alpha_old)
     d.temporal = int(bool(temporal))
     return d
@@ -543,4 +546,4 @@ def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, 
 def filter_views(descs, block, agg_width, workspace, grid_per_cu=0, stream=None):
     arr = (pf_view * len(descs))(*descs)
     _check("pf_filter_views", lib.pf_filter_views(arr, len(descs), block, agg_width, grid_per_cu, _ptr(workspace),
-                                                  _stream(stream)))
+                                                  workspace.numel() * workspace.element_size(), _stream(stream)))

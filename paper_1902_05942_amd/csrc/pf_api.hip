@@ -578,18 +578,20 @@ pf_status pf_mlp_infer(const pf_mlp *m, const pf_geometry *g, const uint32_t *sp
 static_assert(sizeof(pf_view) == 296, "pf_view layout is part of the ABI");
 static_assert(sizeof(pf_table) == 56, "pf_table layout is part of the ABI");
 
-size_t pf_views_workspace_bytes(uint32_t nviews) {
-    if (nviews == 0 || nviews > PF_MAX_VIEWS) return 0;
-    return align_up(pfk::views_counter_bytes(), 256) + align_up(nviews * sizeof(pf_view), 256);
+size_t pf_views_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews) {
+    if (!n || !log2_slots || nviews == 0 || nviews > PF_MAX_VIEWS) return 0;
+    for (uint32_t v = 0; v < nviews; ++v)
+        if (n[v] > kMaxN || log2_slots[v] < 4 || log2_slots[v] > 30) return 0;
+    return pfk::views_workspace_bytes(n, log2_slots, nviews);
 }
 
 namespace {
 pf_status check_view(const pf_view &d) {
-    if (!d.px || !d.py || !d.pz || !d.nx || !d.ny || !d.nz || !d.r || !d.g || !d.b || !d.key || !d.vflags ||
-        !d.slot || !d.r_out || !d.g_out || !d.b_out)
+    if (!d.px || !d.py || !d.pz || !d.nx || !d.ny || !d.nz || !d.r || !d.g || !d.b || !d.vflags || !d.slot ||
+        !d.r_out || !d.g_out || !d.b_out)
         return PF_EINVAL;
     if (!aligned(d.px) || !aligned(d.py) || !aligned(d.pz) || !aligned(d.nx) || !aligned(d.ny) || !aligned(d.nz) ||
-        !aligned(d.r) || !aligned(d.g) || !aligned(d.b) || !aligned(d.key) || !aligned(d.slot) ||
+        !aligned(d.r) || !aligned(d.g) || !aligned(d.b) || (d.key && !aligned(d.key)) || !aligned(d.slot) ||
         !aligned(d.r_out) || !aligned(d.g_out) || !aligned(d.b_out) || (d.count_out && !aligned(d.count_out)))
         return PF_EINVAL;
     if (d.r_out == d.r || d.g_out == d.g || d.b_out == d.b) return PF_EINVAL;
@@ -612,7 +614,7 @@ pf_status check_view(const pf_view &d) {
 }  // namespace
 
 pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
-                          uint32_t grid_per_cu, void *workspace, void *stream) {
+                          uint32_t grid_per_cu, void *workspace, size_t workspace_bytes, void *stream) {
     if (!views || !workspace || (reinterpret_cast<uintptr_t>(workspace) % 256)) return PF_EINVAL;
     if (nviews == 0 || nviews > PF_MAX_VIEWS) return PF_ERANGE;
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return PF_ERANGE;
@@ -628,13 +630,15 @@ pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block,
                 views[u].prev.cell == views[v].cur.cell)
                 return PF_EINVAL;
     }
-    uint32_t *ws = reinterpret_cast<uint32_t *>(workspace);
-    pf_view *dev_views = reinterpret_cast<pf_view *>(reinterpret_cast<char *>(workspace) +
-                                                     align_up(pfk::views_counter_bytes(), 256));
-    if (hipMemcpyAsync(dev_views, views, nviews * sizeof(pf_view), hipMemcpyHostToDevice, (hipStream_t)stream) !=
-        hipSuccess)
-        return PF_ELAUNCH;
-    return launched(pfk::launch_views(dev_views, nviews, block, agg_width, grid_per_cu, ws, (hipStream_t)stream));
+    uint64_t n[PF_MAX_VIEWS];
+    uint32_t lg[PF_MAX_VIEWS];
+    for (uint32_t v = 0; v < nviews; ++v) {
+        n[v] = views[v].n;
+        lg[v] = views[v].cur.log2_slots;
+    }
+    if (workspace_bytes < pfk::views_workspace_bytes(n, lg, nviews)) return PF_EINVAL;
+    return launched(pfk::launch_views(views, nviews, block, agg_width, grid_per_cu, workspace, workspace_bytes,
+                                      (hipStream_t)stream));
 }
 
 pf_status pf_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint32_t accesses_per_thread,

@@ -56,7 +56,15 @@ struct GeoArgs {
     float cam[3];
 };
 
-size_t views_counter_bytes();
+// A view of the batched launch as its kernel sees it: the caller's
+// descriptor and the view's bucket space in the workspace.
+struct ViewDev {
+    pf_view d;
+    uint32_t *cnt;      // [nbins * 8] records per bucket part
+    uint4 *rec;         // [nbins * 8][part_cap] records of 32 bytes (two uint4)
+    uint32_t nbins, part_cap;
+};
+size_t views_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews);
 hipError_t launch_keys_insert_binned(const Tab &t, const float *px, const float *py, const float *pz,
                                      const float *nx, const float *ny, const float *nz, const uint8_t *valid,
                                      const KeyArgs &a, uint64_t *key_out, const float *r, const float *g,
@@ -76,8 +84,8 @@ hipError_t launch_keys_insert_binned_noalloc(const Tab &t, const float *px, cons
                                              uint32_t *slot_out, uint32_t n, hipStream_t st);
 hipError_t launch_microbench(int kind, void *buf, uint64_t bytes, uint32_t grain, uint64_t accesses, uint64_t seed,
                              uint32_t *sink, hipStream_t st);
-hipError_t launch_views(const pf_view *views_dev, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,
-                        uint32_t *ws, hipStream_t st);
+hipError_t launch_views(const pf_view *host_views, uint32_t nviews, uint32_t block, uint32_t agg, uint32_t per_cu,
+                        void *workspace, size_t workspace_bytes, hipStream_t st);
 hipError_t launch_mlp_init(const MlpArgs &a, hipStream_t st);
 uint32_t mlp_select_blocks(uint32_t n);
 hipError_t launch_mlp_select(const uint8_t *flags, const uint32_t *count, uint32_t n, uint32_t lo, uint32_t hi,

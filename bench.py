@@ -113,9 +113,9 @@ def counter_profile(workload, mode):
     fields = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                fields[k.strip()] = v.strip()
+            k, sep, v = line.partition(": ")
+            if sep and not line.startswith("#") and k and " " not in k:
+                fields[k] = v.strip()
     if fields.get("sources_sha256") != source_digest():
         return {}
     return fields
@@ -421,10 +421,10 @@ def main():
     }
     dom = max((k for k in per if k in algo_bytes), key=lambda k: per[k])
     achieved = algo_bytes[dom] / (per[dom] * 1e-6) / 1e9
-    launches = {"insert_accumulate": ("zero, aggregate (records into per-XCD bin buckets), reduce"
+    launches = {"insert_accumulate": ("aggregate, colscan, scatter (bin starts scanned in it), reduce"
                                       if a.insert == "binned" else "insert"),
-                "build_keys_insert": "zero, aggregate (keys built in it; records into per-XCD bin buckets), reduce",
-                "build_keys_insert_temporal": "zero, aggregate (keys built in it; records into per-XCD bin buckets), "
+                "build_keys_insert": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), reduce",
+                "build_keys_insert_temporal": "aggregate (keys built in it), colscan, scatter (bin starts scanned in it), "
                                               "reduce (temporal blend in it)"}
     roofline = {"bound": "hbm", "kernel": dom, "launch": launches.get(dom, dom), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -789,8 +789,12 @@ def mlp_leg(frames, wl, dev, frame_us_plain):
             "sparse_vertices": int(sparse.sum()),
             "rmse_sparse_without": res["without"]["rmse_sparse"], "rmse_sparse_with": round(q_with, 5),
             "rmse_all_without": res["without"]["rmse_all"], "rmse_all_with": round(q_with_all, 5),
-            "us_per_frame": round(mlp_us, 2), "frame_us_with": round(frame_us, 2),
-            "frame_us_without": round(frame_us_plain, 2),
+            "us_per_frame": round(mlp_us, 2),
+            # the frame's kernels: the plain frame's (the default run's events) plus the fallback's stages
+            "frame_gpu_us_without": round(frame_us_plain, 2), "frame_gpu_us_with": round(frame_us_plain + mlp_us, 2),
+            # between the first and the last event of a frame driven from Python, one library call at a time:
+            # the host's time to issue the fallback's eleven calls exceeds the kernels'
+            "frame_wall_us_python_driven": round(frame_us, 2),
             "select_us": round(select_us, 2), "train_us": round(train_us, 2), "infer_us": round(infer_us, 2),
             "train_flops_per_frame": flops, "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
             "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),

@@ -514,7 +514,7 @@ pf_status pf_resolve_pixels(const float *r, const float *g, const float *b, cons
 
 typedef struct pf_mlp {
     float *w;            /* [PF_MLP_NPARAM] FP32 weights (caller fills before pf_mlp_init) */
-    uint16_t *wb;        /* [PF_MLP_NPARAM] BF16 copy used by the products */
+    uint16_t *wb;        /* [PF_MLP_NPARAM] BF16 copy used by the products (16-byte aligned) */
     float *m;            /* [PF_MLP_NPARAM] Adam first moment */
     float *v;            /* [PF_MLP_NPARAM] Adam second moment */
     float *partial;      /* [max_batch / 64][PF_MLP_NPARAM + 1] per-workgroup gradient and loss sums */

@@ -29,6 +29,7 @@ constexpr int kBS = PF_MLP_BLOCK_SAMPLES;      // 64 samples per workgroup (4 wa
 // bytes), so that the 16 rows a wavefront's MFMA operand loads and
 // transposed stores touch fall on different banks (a 128-byte stride puts
 // them all on two)
+constexpr int kLdIn = kIn + 8; // rows of W1 (80 inputs in slot order)
 constexpr int kLdH = kH + 8;   // rows of 64 hidden units (weights W2, W3, W2^T; activations)
 constexpr int kLdS = kBS + 8;  // rows of 64 samples (transposed operands)
 constexpr int kThreads = 256;
@@ -40,13 +41,19 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// float -> bfloat16, round to nearest even, NaN kept quiet
+// float -> bfloat16, round to nearest even, NaN kept quiet; a select, not a
+// branch (the conversions sit between the products of every layer)
 __device__ __forceinline__ uint16_t bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? quiet : rounded);
 }
+
+// Waits for this wave's LDS operations only (lgkmcnt 0, vmcnt and expcnt at
+// their maxima), before a wave barrier that publishes LDS stores to the other
+// lanes; global loads issued ahead stay in flight.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 __device__ __forceinline__ v4s ld4(const uint16_t *p) { return *reinterpret_cast<const v4s *>(p); }
 
@@ -105,21 +112,51 @@ __device__ __forceinline__ uint16_t feature(int f, const int32_t q[3], int lp, c
     return to_feature(v);
 }
 
-// The 80 features of one vertex, computed by the 4 lanes lg = 0..3 of its
-// group: lane lg takes the positional pairs lg, lg + 4, ... (9 of the 36)
-// and features 72 + lg and 76 + lg; put(f, value) stores feature f.
+// The 80 inputs of a vertex are computed by its 4 lanes lg = 0..3 (16
+// vertices a wave, lane = 16 lg + vertex), 20 values each: lane lg's m-th
+// value is the sine (m even) or cosine (m odd) of positional pair
+// lg + 4 (m / 2) for m < 18, input 72 + lg for m = 18 and input 76 + lg for
+// m = 19.  Inference keeps them in slot order, lane lg's m-th value in slot
+// 16 (m / 4) + 4 lg + m % 4, which is the layout of a 16 x 16 x 16
+// product's operand with the vertices along its 16 columns (its W1 columns
+// are permuted to match when staged); training stores them in input order.
+__device__ __forceinline__ int slot_of_input(int f) {
+    if (f >= 72) return 64 + 4 * ((f - 72) & 3) + 2 + ((f - 72) >> 2);
+    const int j = f / 6, r = f % 6, p = 3 * j + r % 3, m = 2 * (p >> 2) + r / 3;
+    return 16 * (m >> 2) + 4 * (p & 3) + (m & 3);
+}
+// input index of lane group lg's m-th value
+__device__ __forceinline__ int input_of_lane_value(int lg, int m) {
+    if (m >= 18) return (m == 18 ? 72 : 76) + lg;
+    const int p = lg + 4 * (m >> 1), j = p / 3, c = p % 3;
+    return 6 * j + 3 * (m & 1) + c;
+}
+
+// The 20 values of lane group lg of one vertex, in slot order:
+// put(m, value) for m = 0..19 (m known at compile time once unrolled).
 template <typename Put>
-__device__ __forceinline__ void vertex_features(int lg, const int32_t q[3], int lp, const float x[3],
-                                                const float n[3], const float cam[3], Put put) {
-    for (int pi = lg; pi < 36; pi += 4) {
-        const int j = pi / 3, c = pi % 3;
+__device__ __forceinline__ void vertex_slots(int lg, const int32_t q[3], int lp, const float x[3], const float n[3],
+                                             const float cam[3], Put put) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {  // independent phases: unrolled so that their FP64 chains interleave
+        const int pi = lg + 4 * k, j = pi / 3, c = pi % 3;
+        const int32_t qc = c == 0 ? q[0] : (c == 1 ? q[1] : q[2]);  // selects: q stays in registers
         uint16_t sv, cv;
-        pe_pair(q[c], lp, j, sv, cv);
-        put(6 * j + c, sv);
-        put(6 * j + 3 + c, cv);
+        pe_pair(qc, lp, j, sv, cv);
+        put(2 * k, sv);
+        put(2 * k + 1, cv);
     }
-    put(72 + lg, feature(72 + lg, q, lp, x, n, cam));
-    put(76 + lg, feature(76 + lg, q, lp, x, n, cam));
+    // inputs 72 + lg and 76 + lg: the normal (72..74), the view direction
+    // (75..77) and two zeros (78, 79); a lane needs at most one component of
+    // the direction, so it divides once
+    const double dx = (double)x[0] - (double)cam[0];
+    const double dy = (double)x[1] - (double)cam[1];
+    const double dz = (double)x[2] - (double)cam[2];
+    const double len = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double dir = (lg == 3 ? dx : (lg == 0 ? dy : dz)) / len;
+    const float nl = lg == 0 ? n[0] : (lg == 1 ? n[1] : n[2]);
+    put(18, to_feature(lg < 3 ? (double)nl : dir));
+    put(19, to_feature(lg < 2 ? dir : 0.0));
 }
 
 struct Geo {
@@ -146,7 +183,7 @@ __device__ __forceinline__ void vertex_inputs(const Geo &g, uint32_t v, int32_t 
 // Stages the BF16 weights and the FP32 biases in LDS (and, for training,
 // the transposes the backward pass reads).
 struct Weights {
-    uint16_t w1[kH * kIn];
+    uint16_t w1[kH * kLdIn];  // columns in input order (training) or slot order (inference)
     uint16_t w2[kH * kLdH];
     uint16_t w3[kOutPad * kLdH];
     float b1[kH], b2[kH], b3[kOutPad];
@@ -157,24 +194,79 @@ struct WeightsT {
     uint16_t w3t[kH * kOutPad];
 };
 
-__device__ void load_weights(Weights &W, WeightsT *T, const uint16_t *wb, const float *w) {
-    for (int i = threadIdx.x; i < kH * kIn; i += kThreads) W.w1[i] = wb[kOffW1 + i];
-    for (int i = threadIdx.x; i < kH * kH; i += kThreads) {
-        const uint16_t val = wb[kOffW2 + i];
-        W.w2[(i / kH) * kLdH + i % kH] = val;
-        if (T) T->w2t[(i % kH) * kLdH + i / kH] = val;
+// The weights' global loads, all issued before any is stored (16-byte loads
+// of the BF16 copy; wb is 16-byte aligned and every matrix starts and every
+// row ends on a 16-byte boundary), held in registers until stage().
+struct WeightLoads {
+    static constexpr int kW1 = kH * kIn / 8, kW2 = kH * kH / 8, kW3 = kOutPad * kH / 8, kB = kH + kH + kOutPad;
+    static constexpr int kN1 = (kW1 + kThreads - 1) / kThreads, kN2 = (kW2 + kThreads - 1) / kThreads;
+    uint4 w1[kN1], w2[kN2], w3;
+    float b;
+
+    __device__ __forceinline__ void issue(const uint16_t *wb, const float *w) {
+        const uint4 *v1 = reinterpret_cast<const uint4 *>(wb + kOffW1);
+        const uint4 *v2 = reinterpret_cast<const uint4 *>(wb + kOffW2);
+        const uint4 *v3 = reinterpret_cast<const uint4 *>(wb + kOffW3);
+        // unconditional loads of clamped indices (a guarded load becomes a
+        // branch that waits for it); stage() stores only the valid ones
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < kN1; ++k) w1[k] = v1[min(t + k * kThreads, kW1 - 1)];
+#pragma unroll
+        for (int k = 0; k < kN2; ++k) w2[k] = v2[min(t + k * kThreads, kW2 - 1)];
+        w3 = v3[min(t, kW3 - 1)];
+        const int tb = min(t, kB - 1);
+        b = w[tb < kH ? kOffB1 + tb : (tb < 2 * kH ? kOffB2 + tb - kH : kOffB3 + tb - 2 * kH)];
     }
-    for (int i = threadIdx.x; i < kOutPad * kH; i += kThreads) {
-        const uint16_t val = wb[kOffW3 + i];
-        W.w3[(i / kH) * kLdH + i % kH] = val;
-        if (T) T->w3t[(i % kH) * kOutPad + i / kH] = val;
+
+    // element j of 8 BF16 values (by shifts: taking the address of the
+    // registers would move them to scratch memory)
+    static __device__ __forceinline__ uint16_t half(const uint4 &u, int j) {
+        const uint32_t word = (j >> 1) == 0 ? u.x : (j >> 1) == 1 ? u.y : (j >> 1) == 2 ? u.z : u.w;
+        return (uint16_t)((j & 1) ? word >> 16 : word & 0xffffu);
     }
-    for (int i = threadIdx.x; i < kH; i += kThreads) {
-        W.b1[i] = w[kOffB1 + i];
-        W.b2[i] = w[kOffB2 + i];
+
+    // Stores the BF16 weights (row-padded W2, W3), the FP32 biases and, for
+    // training, the transposes the backward pass reads.  Unconditional, like
+    // the loads: a lane past the end stores the clamped last element again
+    // (the same value to the same address), so no branch holds a load back.
+    template <bool kSlotOrder>
+    __device__ __forceinline__ void stage(Weights &W, WeightsT *T) const {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < kN1; ++k) {
+            const int e = 8 * min(t + k * kThreads, kW1 - 1), row = e / kIn, f0 = e % kIn;
+            if (kSlotOrder) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) W.w1[row * kLdIn + slot_of_input(f0 + j)] = half(w1[k], j);
+            } else {
+                *reinterpret_cast<uint4 *>(W.w1 + row * kLdIn + f0) = w1[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kN2; ++k) {
+            const int i = min(t + k * kThreads, kW2 - 1);
+            const int row = (8 * i) / kH, col = (8 * i) % kH;
+            *reinterpret_cast<uint4 *>(W.w2 + row * kLdH + col) = w2[k];
+            if (T) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) T->w2t[(col + j) * kLdH + row] = half(w2[k], j);
+            }
+        }
+        {
+            const int i = min(t, kW3 - 1);
+            const int row = (8 * i) / kH, col = (8 * i) % kH;
+            *reinterpret_cast<uint4 *>(W.w3 + row * kLdH + col) = w3;
+            if (T) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) T->w3t[(col + j) * kOutPad + row] = half(w3, j);
+            }
+        }
+        const int tb = min(t, kB - 1);
+        float *bias = tb < kH ? W.b1 + tb : (tb < 2 * kH ? W.b2 + tb - kH : W.b3 + tb - 2 * kH);
+        *bias = b;
     }
-    for (int i = threadIdx.x; i < kOutPad; i += kThreads) W.b3[i] = w[kOffB3 + i];
-}
+};
 
 // Forward pass of one wave's 16-row tile (rows r0..r0+15 of x, a1, a2 with
 // row strides kIn / lda).  Keeps z1, z2 (C layout) for the backward pass and
@@ -190,7 +282,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
     for (int kk = 0; kk < kIn / 16; ++kk) {
         const v4s a = ld4(x + (r0 + lr) * kIn + kk * 16 + 4 * lg);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) z1[nt] = mfma(a, ld4(W.w1 + (nt * 16 + lr) * kIn + kk * 16 + 4 * lg), z1[nt]);
+        for (int nt = 0; nt < 4; ++nt) z1[nt] = mfma(a, ld4(W.w1 + (nt * 16 + lr) * kLdIn + kk * 16 + 4 * lg), z1[nt]);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -204,7 +296,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         }
         if (a1t) st4(a1t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    lds_wait();
     __builtin_amdgcn_wave_barrier();
     // layer 2
 #pragma unroll
@@ -227,7 +319,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         }
         if (a2t) st4(a2t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    lds_wait();
     __builtin_amdgcn_wave_barrier();
     // layer 3 (16 padded outputs)
     v4f y = {0, 0, 0, 0};
@@ -270,7 +362,9 @@ struct TrainArgs {
     float gscale;  // 2 / (3 * batch)
 };
 
-__global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint16_t *__restrict__ wb,
+// one workgroup per compute unit (the LDS it needs): registers are not scarce, so
+// the weights' loads can all be issued before the features are computed
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void train_kernel(TrainArgs A, const uint16_t *__restrict__ wb,
                                                           const float *__restrict__ w, float *__restrict__ partial) {
     extern __shared__ __align__(16) unsigned char smem[];
     TrainLds &L = *reinterpret_cast<TrainLds *>(smem);
@@ -283,25 +377,33 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
     const int r0 = wave * 16;  // this wave's rows of the block tile
 
-    load_weights(L.W, &L.T, wb, w);
-
-    // features and target of sample r0 + lr (4 lanes per sample)
+    // features and target of sample r0 + lr (4 lanes per sample); the
+    // weights' loads go out with the sample's first load and are staged in
+    // LDS while the vertex's loads are in flight
+    WeightLoads wl;
     {
         const uint32_t j = blockIdx.x * kBS + r0 + lr;
         Pcg32 rng(A.seed, j);
         const uint32_t u = rng.next();
         const uint32_t pick = (uint32_t)(((uint64_t)u * (uint64_t)n_el) >> 32);
         const uint32_t v = A.train_idx[pick];
+        wl.issue(wb, w);
+        __builtin_amdgcn_sched_barrier(0);  // the weights' loads go out here, not where they are used
         int32_t q[3];
         int lp;
         float x[3], n[3];
         vertex_inputs(A.g, v, q, lp, x, n);
-        vertex_features(lg, q, lp, x, n, A.g.cam, [&](int f, uint16_t val) {
+        // the target's cell is requested, and the weights staged, before the
+        // features are computed
+        pf_cell c;
+        if (lg == 0) c = A.t.cell_at(A.slot[v]);
+        wl.stage<false>(L.W, &L.T);
+        vertex_slots(lg, q, lp, x, n, A.g.cam, [&](int m, uint16_t val) {
+            const int f = input_of_lane_value(lg, m);
             L.x[(r0 + lr) * kIn + f] = val;
             L.xt[f * kLdS + r0 + lr] = val;
         });
         if (lg == 0) {
-            const pf_cell c = A.t.cell_at(A.slot[v]);
             L.target[(r0 + lr) * 4 + 0] = A.t.average(c, 0);
             L.target[(r0 + lr) * 4 + 1] = A.t.average(c, 1);
             L.target[(r0 + lr) * 4 + 2] = A.t.average(c, 2);
@@ -336,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         tot += __shfl_xor(tot, 8);
         if (lane == 0) L.red[wave][2 * kH + kOutPad] = tot;
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    lds_wait();
     __builtin_amdgcn_wave_barrier();
 
     // da2 = gy W3, gz2 = da2 * [z2 > 0]
@@ -355,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
         const float s = col_sum((g[0] + g[1]) + (g[2] + g[3]));
         if (lg == 0) L.red[wave][kH + n] = s;
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    lds_wait();
     __builtin_amdgcn_wave_barrier();
 
     // da1 = gz2 W2, gz1 = da1 * [z1 > 0]
@@ -422,37 +524,40 @@ __global__ __launch_bounds__(kThreads) void train_kernel(TrainArgs A, const uint
     }
 }
 
-// Sum of the per-workgroup partials, then Adam.  A workgroup takes 64
-// parameters; its four groups of 64 lanes each sum a contiguous quarter of
-// the partials (independent loads in flight together), and the four
-// quarter sums are added in a fixed order, so the result is deterministic.
-constexpr int kRedParams = 64;
-__global__ __launch_bounds__(kThreads) void reduce_adam_kernel(float *__restrict__ w, uint16_t *__restrict__ wb,
-                                                               float *__restrict__ m, float *__restrict__ v,
-                                                               const float *__restrict__ partial, uint32_t nblocks,
-                                                               const uint32_t *__restrict__ counts, float lr,
-                                                               float c1, float c2, float *__restrict__ loss,
-                                                               float loss_scale) {
-    static_assert(kThreads == 4 * kRedParams, "four groups of 64 lanes");
-    __shared__ float quarter[4][kRedParams];
+// Sum of the per-workgroup partials, then Adam.  A workgroup of 1024 lanes
+// takes 64 parameters; its 16 groups of 64 lanes each sum a contiguous
+// sixteenth of the partials (all of a lane's loads in flight together), and
+// the 16 group sums are added in a fixed order, so the result is
+// deterministic.
+constexpr int kRedParams = 64, kRedGroups = 16, kRedThreads = kRedParams * kRedGroups;
+__global__ __launch_bounds__(kRedThreads) void reduce_adam_kernel(float *__restrict__ w, uint16_t *__restrict__ wb,
+                                                                  float *__restrict__ m, float *__restrict__ v,
+                                                                  const float *__restrict__ partial, uint32_t nblocks,
+                                                                  const uint32_t *__restrict__ counts, float lr,
+                                                                  float c1, float c2, float *__restrict__ loss,
+                                                                  float loss_scale) {
+    __shared__ float part[kRedGroups][kRedParams];
     if (counts[0] == 0) return;
     const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
     const int p = blockIdx.x * kRedParams + pl;
-    const uint32_t per = (nblocks + 3) / 4;
+    const uint32_t per = (nblocks + kRedGroups - 1) / kRedGroups;
     const uint32_t b0 = grp * per, b1 = min(nblocks, b0 + per);
     float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (p <= kNParam) {
-        uint32_t bb = b0;
-        for (; bb + 8 <= b1; bb += 8) {
+        for (uint32_t bb = b0; bb < b1; bb += 16) {
+            float t[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += partial[(size_t)(bb + u) * (kNParam + 1) + p];
+            for (int u = 0; u < 16; ++u) t[u] = bb + u < b1 ? partial[(size_t)(bb + u) * (kNParam + 1) + p] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[u & 7] += t[u];
         }
-        for (; bb < b1; ++bb) acc[0] += partial[(size_t)bb * (kNParam + 1) + p];
     }
-    quarter[grp][pl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    part[grp][pl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
     if (grp != 0 || p > kNParam) return;
-    const float g = (quarter[0][pl] + quarter[1][pl]) + (quarter[2][pl] + quarter[3][pl]);
+    float g = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRedGroups; ++k) g += part[k][pl];
     if (p == kNParam) {
         loss[0] = g * loss_scale;
         return;
@@ -470,16 +575,59 @@ __global__ __launch_bounds__(kThreads) void reduce_adam_kernel(float *__restrict
     wb[p] = bf16(wn);
 }
 
-// Per wave: the tile's features (then, once layer 1 has read them, its
-// outputs) and one activation buffer that layer 2 overwrites after reading
-// it (all of a wave's reads of a1 complete before its first write), so
-// that four workgroups fit a CU.
+// Inference keeps a tile's activations in registers.  Each layer is
+// computed transposed, z^T = W a^T, with the weights as the first operand of
+// the 16 x 16 x 16 products and the vertices along the columns of the
+// second: a lane's result, 4 hidden units of one vertex, is then exactly its
+// part of the next layer's second operand, so nothing goes through LDS but
+// the weights.
 struct InferLds {
     Weights W;
-    uint16_t x[4 * 16 * kIn];
-    uint16_t a1[4 * 16 * kH];
 };
-static_assert(16 * kIn * sizeof(uint16_t) >= 16 * kOutPad * sizeof(float), "outputs fit a wave's feature rows");
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
+    v4s v;
+    v.x = (short)bf16(a);
+    v.y = (short)bf16(b);
+    v.z = (short)bf16(c);
+    v.w = (short)bf16(d);
+    return v;
+}
+
+// One wave's 16 vertices: xf[kk] holds this lane's slots 16 kk + 4 lg + i
+// of vertex lr.  Returns this lane's 4 outputs 4 lg + i of vertex lr
+// (outputs 0..2 live in lane group 0).
+__device__ __forceinline__ v4f forward_regs(const Weights &W, const v4s xf[5]) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    v4s a1[4], a2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        v4f z = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < kIn / 16; ++kk) z = mfma(ld4(W.w1 + (mt * 16 + lr) * kLdIn + kk * 16 + 4 * lg), xf[kk], z);
+        const float4 bb = *reinterpret_cast<const float4 *>(W.b1 + mt * 16 + 4 * lg);
+        a1[mt] = pack4(fmaxf(z[0] + bb.x, 0.0f), fmaxf(z[1] + bb.y, 0.0f), fmaxf(z[2] + bb.z, 0.0f),
+                       fmaxf(z[3] + bb.w, 0.0f));
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        v4f z = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < kH / 16; ++kk) z = mfma(ld4(W.w2 + (mt * 16 + lr) * kLdH + kk * 16 + 4 * lg), a1[kk], z);
+        const float4 bb = *reinterpret_cast<const float4 *>(W.b2 + mt * 16 + 4 * lg);
+        a2[mt] = pack4(fmaxf(z[0] + bb.x, 0.0f), fmaxf(z[1] + bb.y, 0.0f), fmaxf(z[2] + bb.z, 0.0f),
+                       fmaxf(z[3] + bb.w, 0.0f));
+    }
+    v4f y = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < kH / 16; ++kk) y = mfma(ld4(W.w3 + lr * kLdH + kk * 16 + 4 * lg), a2[kk], y);
+    const float4 bb = *reinterpret_cast<const float4 *>(W.b3 + 4 * lg);
+    y[0] += bb.x;
+    y[1] += bb.y;
+    y[2] += bb.z;
+    y[3] += bb.w;
+    return y;
+}
 
 __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *__restrict__ wb,
                                                           const float *__restrict__ w, const uint32_t *idx,
@@ -488,44 +636,69 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
     InferLds &L = *reinterpret_cast<InferLds *>(smem);
     const uint32_t n = counts[1];
     if (n == 0) return;
-    load_weights(L.W, nullptr, wb, w);
-    __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
-    uint16_t *x = L.x + wave * 16 * kIn;
-    uint16_t *a1 = L.a1 + wave * 16 * kH;
-    uint16_t *a2 = a1;
-    float *yb = reinterpret_cast<float *>(x);
+    {
+        WeightLoads wl;
+        wl.issue(wb, w);
+        wl.stage<true>(L.W, nullptr);
+    }
+    __syncthreads();
+
+    // Tiles of 16 listed vertices, strided over the waves.  The loads are
+    // software-pipelined: a tile's vertex inputs are requested one tile
+    // ahead and its list entries two tiles ahead, so that the two dependent
+    // random loads before a tile's features overlap the tiles before it.
     const uint32_t ntiles = (n + 15) / 16;
-    for (uint32_t tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
-        const uint32_t e = tile * 16 + lr;
-        const bool live = e < n;
-        const uint32_t vtx = live ? idx[e] : 0u;
-        if (live) {
-            int32_t q[3];
-            int lp;
-            float xv[3], nv[3];
-            vertex_inputs(g, vtx, q, lp, xv, nv);
-            vertex_features(lg, q, lp, xv, nv, g.cam, [&](int f, uint16_t val) { x[lr * kIn + f] = val; });
-        } else {
-            for (int f = lg; f < kIn; f += 4) x[lr * kIn + f] = 0;
+    const uint32_t stride = gridDim.x * 4;
+    constexpr uint32_t kNone = 0xffffffffu;
+    auto entry = [&](uint32_t t) -> uint32_t {  // this lane's vertex in tile t (kNone: none)
+        const uint32_t e = t * 16 + lr;
+        return t < ntiles && e < n ? idx[e] : kNone;
+    };
+    struct In {
+        uint64_t key;
+        float x[3], nv[3];
+    };
+    auto inputs = [&](uint32_t vtx) {
+        In in;
+        const uint32_t v = vtx != kNone ? vtx : 0u;  // a lane of no vertex reads vertex 0, unused
+        in.key = g.key[v];
+        in.x[0] = g.px[v];
+        in.x[1] = g.py[v];
+        in.x[2] = g.pz[v];
+        in.nv[0] = g.nx[v];
+        in.nv[1] = g.ny[v];
+        in.nv[2] = g.nz[v];
+        return in;
+    };
+    uint32_t tile = blockIdx.x * 4 + wave;
+    uint32_t vtx = entry(tile);
+    In cur = inputs(vtx);
+    uint32_t vtx_next = entry(tile + stride);
+    for (; tile < ntiles; tile += stride) {
+        const In nxt = inputs(vtx_next);
+        const uint32_t vtx_after = entry(tile + 2 * stride);
+        int32_t q[3];
+        q[0] = (int32_t)((cur.key >> 0) & 0x1ffffu) - 65536;
+        q[1] = (int32_t)((cur.key >> 17) & 0x1ffffu) - 65536;
+        q[2] = (int32_t)((cur.key >> 34) & 0x1ffffu) - 65536;
+        const int lp = (int)((cur.key >> 51) & 31u) - 16;
+        v4s xf[5];
+        vertex_slots(lg, q, lp, cur.x, cur.nv, g.cam, [&](int m, uint16_t val) { xf[m >> 2][m & 3] = (short)val; });
+        // the weights are read from LDS in every tile: an offset the compiler
+        // cannot see through keeps it from holding all of them in registers
+        // (which would leave two waves a SIMD)
+        uint32_t wofs = 0;
+        asm volatile("" : "+v"(wofs));
+        const v4f y = forward_regs(*reinterpret_cast<const Weights *>(smem + wofs), xf);
+        if (lg == 0 && vtx != kNone && isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2])) {
+            r[vtx] = y[0] > 0.0f ? y[0] : 0.0f;
+            gc[vtx] = y[1] > 0.0f ? y[1] : 0.0f;
+            b[vtx] = y[2] > 0.0f ? y[2] : 0.0f;
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        v4f z1[4], z2[4];
-        const v4f y = forward_tile(L.W, x, a1, a2, kH, nullptr, nullptr, 0, 0, z1, z2);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) yb[(4 * lg + i) * kOutPad + lr] = y[i];
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        if (lg == 0 && live) {
-            const float y0 = yb[lr * kOutPad + 0], y1 = yb[lr * kOutPad + 1], y2 = yb[lr * kOutPad + 2];
-            if (isfinite(y0) && isfinite(y1) && isfinite(y2)) {
-                r[vtx] = y0 > 0.0f ? y0 : 0.0f;
-                gc[vtx] = y1 > 0.0f ? y1 : 0.0f;
-                b[vtx] = y2 > 0.0f ? y2 : 0.0f;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
+        cur = nxt;
+        vtx = vtx_next;
+        vtx_next = vtx_after;
     }
 }
 
@@ -555,125 +728,123 @@ __global__ void init_kernel(const float *__restrict__ w, uint16_t *__restrict__ 
 }
 
 // ----------------------------------------------------------- selection
-constexpr int kSelPerBlock = 1024;  // 256 threads x 4 vertices
+// Two passes over blocks of 4096 vertices, 16 consecutive vertices a thread
+// (one 16-byte load of flags, four of counts where both arrays are 16-byte
+// aligned): the first counts each block's listed vertices; the second sums
+// the counts of the blocks before its own (a few KB from L2, so there is no
+// separate scan), ranks its threads, and writes its part of each list as
+// one contiguous run staged in LDS, in vertex order.
+constexpr int kSelPerThread = 16;
+constexpr int kSelPerBlock = kThreads * kSelPerThread;  // 4096
 
-__device__ __forceinline__ void sel_pred(uint32_t i, uint32_t n, const uint8_t *flags, const uint32_t *count,
-                                         uint32_t lo, uint32_t hi, bool &tr, bool &sp) {
-    tr = sp = false;
-    if (i < n && flags[i] == 0) {
-        const uint32_t c = count[i];
-        tr = c >= hi;
-        sp = c < lo;
+// Bit v of tr / sp: vertex base + v is listed for training / as sparse.
+__device__ __forceinline__ void sel_masks(uint32_t base, uint32_t n, const uint8_t *flags, const uint32_t *count,
+                                          uint32_t lo, uint32_t hi, bool vec, uint32_t &tr, uint32_t &sp) {
+    tr = sp = 0;
+    if (vec && base + kSelPerThread <= n) {
+        const uint4 f4 = *reinterpret_cast<const uint4 *>(flags + base);
+        const uint32_t fw[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 c4 = *reinterpret_cast<const uint4 *>(count + base + 4 * q);
+            const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool ok = ((fw[q] >> (8 * k)) & 0xffu) == 0;
+                tr |= (uint32_t)(ok && cw[k] >= hi) << (4 * q + k);
+                sp |= (uint32_t)(ok && cw[k] < lo) << (4 * q + k);
+            }
+        }
+    } else {
+        for (int v = 0; v < kSelPerThread; ++v) {
+            const uint32_t i = base + v;
+            if (i < n && flags[i] == 0) {
+                const uint32_t c = count[i];
+                tr |= (uint32_t)(c >= hi) << v;
+                sp |= (uint32_t)(c < lo) << v;
+            }
+        }
     }
+}
+
+// Block-wide exclusive prefix (in thread order) of a and b, and the totals.
+__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t &pa, uint32_t &pb, uint32_t &ta,
+                                            uint32_t &tb) {
+    __shared__ uint32_t s_wave[2][kThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t ia = a, ib = b;
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t ua = __shfl_up(ia, off), ub = __shfl_up(ib, off);
+        if (lane >= off) {
+            ia += ua;
+            ib += ub;
+        }
+    }
+    if (lane == 63) {
+        s_wave[0][wave] = ia;
+        s_wave[1][wave] = ib;
+    }
+    __syncthreads();
+    uint32_t wa = 0, wb = 0;
+    ta = tb = 0;
+    for (uint32_t k = 0; k < kThreads / 64; ++k) {
+        if (k < wave) {
+            wa += s_wave[0][k];
+            wb += s_wave[1][k];
+        }
+        ta += s_wave[0][k];
+        tb += s_wave[1][k];
+    }
+    pa = wa + ia - a;
+    pb = wb + ib - b;
+    __syncthreads();  // s_wave is reused by the next call
 }
 
 __global__ __launch_bounds__(kThreads) void select_count_kernel(const uint8_t *flags, const uint32_t *count,
-                                                                uint32_t n, uint32_t lo, uint32_t hi,
+                                                                uint32_t n, uint32_t lo, uint32_t hi, bool vec,
                                                                 uint32_t *bcnt, uint32_t nblocks) {
-    __shared__ uint32_t s_t[4], s_s[4];
-    uint32_t ct = 0, cs = 0;
-    for (int k = 0; k < 4; ++k) {
-        bool tr, sp;
-        sel_pred(blockIdx.x * kSelPerBlock + k * kThreads + threadIdx.x, n, flags, count, lo, hi, tr, sp);
-        ct += __popcll(__ballot(tr));
-        cs += __popcll(__ballot(sp));
-    }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_t[wave] = ct;
-        s_s[wave] = cs;
-    }
-    __syncthreads();
+    uint32_t tr, sp;
+    sel_masks(blockIdx.x * kSelPerBlock + threadIdx.x * kSelPerThread, n, flags, count, lo, hi, vec, tr, sp);
+    uint32_t pa, pb, ta, tb;
+    block_scan2(__popc(tr), __popc(sp), pa, pb, ta, tb);
     if (threadIdx.x == 0) {
-        bcnt[blockIdx.x] = s_t[0] + s_t[1] + s_t[2] + s_t[3];
-        bcnt[nblocks + blockIdx.x] = s_s[0] + s_s[1] + s_s[2] + s_s[3];
-    }
-}
-
-// One workgroup: exclusive scan of both per-block count arrays (in place)
-// and the totals into counts[0..1].
-__global__ __launch_bounds__(1024) void select_scan_kernel(uint32_t *bcnt, uint32_t nblocks, uint32_t *counts) {
-    __shared__ uint32_t s_sum[2][1024];
-    const uint32_t per = (nblocks + 1023) / 1024;
-    for (int list = 0; list < 2; ++list) {
-        uint32_t *c = bcnt + list * nblocks;
-        const uint32_t b0 = threadIdx.x * per;
-        uint32_t local = 0;
-        for (uint32_t k = 0; k < per; ++k)
-            if (b0 + k < nblocks) local += c[b0 + k];
-        s_sum[list][threadIdx.x] = local;
-    }
-    __syncthreads();
-    // exclusive scan of the 1024 partials of each list: inclusive scans
-    // within each wavefront (shuffles), then over the 16 wavefront totals
-    __shared__ uint32_t s_wave[2][16];
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl[2];
-    for (int list = 0; list < 2; ++list) {
-        uint32_t v = s_sum[list][threadIdx.x];
-        for (uint32_t off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(v, off);
-            if (lane >= off) v += o;
-        }
-        incl[list] = v;
-        if (lane == 63) s_wave[list][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {  // 16 wavefront totals per list
-        uint32_t run = 0;
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t t = s_wave[threadIdx.x][k];
-            s_wave[threadIdx.x][k] = run;
-            run += t;
-        }
-        counts[threadIdx.x] = run;
-    }
-    __syncthreads();
-    for (int list = 0; list < 2; ++list)
-        s_sum[list][threadIdx.x] = s_wave[list][wave] + incl[list] - s_sum[list][threadIdx.x];
-    __syncthreads();
-    for (int list = 0; list < 2; ++list) {
-        uint32_t *c = bcnt + list * nblocks;
-        const uint32_t b0 = threadIdx.x * per;
-        uint32_t run = s_sum[list][threadIdx.x];
-        for (uint32_t k = 0; k < per; ++k)
-            if (b0 + k < nblocks) {
-                const uint32_t t = c[b0 + k];
-                c[b0 + k] = run;
-                run += t;
-            }
+        bcnt[blockIdx.x] = ta;
+        bcnt[nblocks + blockIdx.x] = tb;
     }
 }
 
 __global__ __launch_bounds__(kThreads) void select_scatter_kernel(const uint8_t *flags, const uint32_t *count,
-                                                                  uint32_t n, uint32_t lo, uint32_t hi,
-                                                                  const uint32_t *boff, uint32_t nblocks,
-                                                                  uint32_t *tr_idx, uint32_t *sp_idx) {
-    __shared__ uint32_t s_t[4], s_s[4];
-    uint32_t base_t = boff[blockIdx.x], base_s = boff[nblocks + blockIdx.x];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t i = blockIdx.x * kSelPerBlock + k * kThreads + threadIdx.x;
-        bool tr, sp;
-        sel_pred(i, n, flags, count, lo, hi, tr, sp);
-        const uint64_t bt = __ballot(tr), bs = __ballot(sp);
-        if (lane == 0) {
-            s_t[wave] = __popcll(bt);
-            s_s[wave] = __popcll(bs);
-        }
-        __syncthreads();
-        uint32_t ot = base_t, os = base_s;
-        for (int w2 = 0; w2 < wave; ++w2) {
-            ot += s_t[w2];
-            os += s_s[w2];
-        }
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        if (tr) tr_idx[ot + __popcll(bt & below)] = i;
-        if (sp) sp_idx[os + __popcll(bs & below)] = i;
-        base_t += s_t[0] + s_t[1] + s_t[2] + s_t[3];
-        base_s += s_s[0] + s_s[1] + s_s[2] + s_s[3];
-        __syncthreads();
+                                                                  uint32_t n, uint32_t lo, uint32_t hi, bool vec,
+                                                                  const uint32_t *bcnt, uint32_t nblocks,
+                                                                  uint32_t *tr_idx, uint32_t *sp_idx,
+                                                                  uint32_t *counts) {
+    const uint32_t base = blockIdx.x * kSelPerBlock + threadIdx.x * kSelPerThread;
+    uint32_t tr, sp;
+    sel_masks(base, n, flags, count, lo, hi, vec, tr, sp);
+    // this block's offsets: the counts of the blocks before it
+    uint32_t before_t = 0, before_s = 0;
+    for (uint32_t k = threadIdx.x; k < blockIdx.x; k += kThreads) {
+        before_t += bcnt[k];
+        before_s += bcnt[nblocks + k];
     }
+    uint32_t dummy_a, dummy_b, off_t, off_s;
+    block_scan2(before_t, before_s, dummy_a, dummy_b, off_t, off_s);
+    uint32_t pt, ps, tt, ts;
+    block_scan2(__popc(tr), __popc(sp), pt, ps, tt, ts);
+    if (blockIdx.x + 1 == gridDim.x && threadIdx.x == 0) {  // the last block knows the totals
+        counts[0] = off_t + tt;
+        counts[1] = off_s + ts;
+    }
+    // the block's entries go to LDS in order, then out as two contiguous runs
+    __shared__ uint32_t s_tr[kSelPerBlock], s_sp[kSelPerBlock];
+    uint32_t ot = pt, os = ps;
+    for (int v = 0; v < kSelPerThread; ++v) {
+        if ((tr >> v) & 1u) s_tr[ot++] = base + v;
+        if ((sp >> v) & 1u) s_sp[os++] = base + v;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < tt; k += kThreads) tr_idx[off_t + k] = s_tr[k];
+    for (uint32_t k = threadIdx.x; k < ts; k += kThreads) sp_idx[off_s + k] = s_sp[k];
 }
 
 }  // namespace mlp
@@ -688,11 +859,14 @@ hipError_t launch_mlp_init(const MlpArgs &a, hipStream_t st) {
 hipError_t launch_mlp_select(const uint8_t *flags, const uint32_t *count, uint32_t n, uint32_t lo, uint32_t hi,
                              uint32_t *tr_idx, uint32_t *sp_idx, uint32_t *counts, uint32_t *ws, hipStream_t st) {
     const uint32_t nblocks = (n + mlp::kSelPerBlock - 1) / mlp::kSelPerBlock;
-    if (nblocks) mlp::select_count_kernel<<<nblocks, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, ws, nblocks);
-    mlp::select_scan_kernel<<<1, 1024, 0, st>>>(ws, nblocks, counts);  // n == 0: writes zero counts
+    // 16-byte loads where both arrays allow them (the blocks start on
+    // multiples of 4096 vertices)
+    const bool vec = reinterpret_cast<uintptr_t>(flags) % 16 == 0 && reinterpret_cast<uintptr_t>(count) % 16 == 0;
     if (nblocks)
-        mlp::select_scatter_kernel<<<nblocks, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, ws, nblocks, tr_idx,
-                                                                      sp_idx);
+        mlp::select_count_kernel<<<nblocks, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, vec, ws, nblocks);
+    // n == 0: one block writes zero counts
+    mlp::select_scatter_kernel<<<nblocks ? nblocks : 1, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, vec, ws,
+                                                                                nblocks, tr_idx, sp_idx, counts);
     return hipGetLastError();
 }
 
@@ -728,7 +902,7 @@ hipError_t launch_mlp_train(const MlpArgs &a, const Tab &t, const GeoArgs &g, co
     mlp::train_kernel<<<nblocks, mlp::kThreads, lds, st>>>(A, a.wb, a.w, a.partial);
     const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
     const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));
-    mlp::reduce_adam_kernel<<<(mlp::kNParam + 1 + mlp::kRedParams - 1) / mlp::kRedParams, mlp::kThreads, 0, st>>>(
+    mlp::reduce_adam_kernel<<<(mlp::kNParam + 1 + mlp::kRedParams - 1) / mlp::kRedParams, mlp::kRedThreads, 0, st>>>(
         a.w, a.wb, a.m, a.v, a.partial, nblocks, counts, lr, (float)c1, (float)c2, a.loss,
         (float)(1.0 / (3.0 * (double)batch)));
     return hipGetLastError();
@@ -761,10 +935,6 @@ hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *
     G.ny = g.ny;
     G.nz = g.nz;
     for (int c = 0; c < 3; ++c) G.cam[c] = g.cam[c];
-    const uint32_t tiles = (n_max + 15) / 16;
-    uint32_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks == 0) blocks = 1;
     const size_t lds = sizeof(mlp::InferLds);
     static bool lds_set = false;  // the attribute is per function: set it once
     if (!lds_set) {
@@ -773,6 +943,27 @@ hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *
         if (e != hipSuccess) return e;
         lds_set = true;
     }
+    // no more workgroups than are resident at once: the waves stride over
+    // the tiles, and a second round of workgroups would start only when the
+    // first has finished (per device, asked once)
+    static uint32_t resident[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(mlp::infer_kernel),
+                                                         mlp::kThreads, lds);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident[dev] = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+    }
+    const uint32_t tiles = (n_max + 15) / 16;
+    uint32_t blocks = (tiles + 3) / 4;
+    if (blocks > resident[dev]) blocks = resident[dev];
+    if (blocks == 0) blocks = 1;
     mlp::infer_kernel<<<blocks, mlp::kThreads, lds, st>>>(G, a.wb, a.w, idx, counts, r, gc, b);
     return hipGetLastError();
 }

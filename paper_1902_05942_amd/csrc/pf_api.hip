@@ -451,7 +451,8 @@ size_t mlp_partial_floats(uint32_t max_batch) { return (size_t)(max_batch / PF_M
 
 bool mlp_ok(const pf_mlp *m) {
     return m && m->w && m->wb && m->m && m->v && m->partial && m->loss && m->max_batch &&
-           m->max_batch % PF_MLP_BLOCK_SAMPLES == 0 && aligned(m->w) && aligned(m->wb) && aligned(m->m) &&
+           m->max_batch % PF_MLP_BLOCK_SAMPLES == 0 && aligned(m->w) && reinterpret_cast<uintptr_t>(m->wb) % 16 == 0 &&
+           aligned(m->m) &&
            aligned(m->v) && aligned(m->partial) && aligned(m->loss);
 }
 

@@ -69,6 +69,17 @@ def test_select_lists_are_exact(gpu):
     assert nt == len(want_tr) and ns == len(want_sp) and nt > 1000 and ns > 1000
     assert np.array_equal(tr[:nt].cpu().numpy(), want_tr)
     assert np.array_equal(sp[:ns].cpu().numpy(), want_sp)
+    # arrays that start one vertex in (not 16-byte aligned: the per-vertex
+    # loads instead of the 16-byte ones): the lists of vertices 1..n-1, renumbered
+    m = n - 1
+    tr1 = torch.empty(m, dtype=torch.int32, device="cuda")
+    sp1 = torch.empty(m, dtype=torch.int32, device="cuda")
+    c1 = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ws = torch.empty(pf.mlp_select_workspace_bytes(m), dtype=torch.uint8, device="cuda")
+    pf.mlp_select(flt.vflags[1:n], flt.count[1:n], 4, 16, tr1, sp1, c1, ws)
+    nt1, ns1 = (int(v) for v in c1.cpu().numpy())
+    assert np.array_equal(tr1[:nt1].cpu().numpy(), np.nonzero((ok & (R.cnt >= 16))[1:])[0])
+    assert np.array_equal(sp1[:ns1].cpu().numpy(), np.nonzero((ok & (R.cnt < 4))[1:])[0])
     # empty input: counts become zero
     counts = torch.full((2,), 7, dtype=torch.int32, device="cuda")
     e = torch.empty(0, dtype=torch.int32, device="cuda")

@@ -479,6 +479,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     __syncthreads();
 
     // weight gradients over the block's 64 samples; wave w owns tiles w, w+4, ...
+    // (the partials are stored non-temporally: read once, by the reduction)
     // dW1 [64 x 80]: 20 tiles
     for (int tile = wave; tile < 20; tile += 4) {
         const int mt = tile / 5, nt = tile % 5;
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             acc = mfma(ld4(L.gz1t + (mt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
                        ld4(L.xt + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg), acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[kOffW1 + (mt * 16 + 4 * lg + i) * kIn + nt * 16 + lr] = acc[i];
+        for (int i = 0; i < 4; ++i) __builtin_nontemporal_store(acc[i], &out[kOffW1 + (mt * 16 + 4 * lg + i) * kIn + nt * 16 + lr]);
     }
     // dW2 [64 x 64]: 16 tiles
     for (int tile = wave; tile < 16; tile += 4) {
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             acc = mfma(ld4(L.gz2t + (mt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
                        ld4(L.a1t + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg), acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[kOffW2 + (mt * 16 + 4 * lg + i) * kH + nt * 16 + lr] = acc[i];
+        for (int i = 0; i < 4; ++i) __builtin_nontemporal_store(acc[i], &out[kOffW2 + (mt * 16 + 4 * lg + i) * kH + nt * 16 + lr]);
     }
     // dW3 [16 x 64]: 4 tiles, one per wave
     {
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             acc = mfma(ld4(L.gyt + lr * kLdS + kk * 16 + 4 * lg), ld4(L.a2t + (nt * 16 + lr) * kLdS + kk * 16 + 4 * lg),
                        acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[kOffW3 + (4 * lg + i) * kH + nt * 16 + lr] = acc[i];
+        for (int i = 0; i < 4; ++i) __builtin_nontemporal_store(acc[i], &out[kOffW3 + (4 * lg + i) * kH + nt * 16 + lr]);
     }
     // bias gradients and loss: the 4 waves' sums in wave order
     for (int i = threadIdx.x; i < kH + kH + kOutPad + 1; i += kThreads) {
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         else if (i < 2 * kH) dst = kOffB2 + (i - kH);
         else if (i < 2 * kH + kOutPad) dst = kOffB3 + (i - 2 * kH);
         else dst = kNParam;
-        out[dst] = s;
+        __builtin_nontemporal_store(s, &out[dst]);
     }
 }
 

@@ -12,6 +12,7 @@
 // with plain loads and stores, and blends the cells with the previous
 // frame's values.  The per-vertex and per-cell arithmetic is that of the
 // single-view kernels (pf_ops.h).
+#include "pf_grid.h"
 #include "pf_kernels.h"
 #include "pf_merge.h"
 #include "pf_ops.h"
@@ -20,29 +21,14 @@ namespace pfk {
 
 namespace views {
 
+using grid::Barrier;
+using grid::grid_barrier;
+using grid::kCounterStride;
+using grid::kSubCounters;
+using grid::poll;
+
 constexpr int kIters = 8;            // block-sized steps per work item
 constexpr uint32_t kParts = 8;       // bucket parts per bin: one per XCD
-constexpr int kSubCounters = 64;     // first level of the grid barrier
-constexpr int kCounterStride = 16;   // uint32 words between counters (64 B)
-
-struct Barrier {
-    uint32_t *status;   // [0] non-zero once a wait has timed out
-    uint32_t *sub;      // kSubCounters arrival counters, kCounterStride apart
-    uint32_t *rel;      // kSubCounters release flags, kCounterStride apart
-    uint32_t *top;      // sub-groups arrived
-    uint64_t limit;     // wall-clock ticks a wait may last
-};
-
-// Reads a counter at the coherence point with a read-modify-write that adds
-// 0: loads may be served by an XCD's L2, which does not see atomics made
-// elsewhere.  The zero is hidden from the optimiser, which would otherwise
-// turn the idempotent read-modify-write back into a plain load.
-__device__ __forceinline__ uint32_t poll(uint32_t *p) {
-    uint32_t zero = 0;
-    asm volatile("" : "+v"(zero));
-    return __hip_atomic_fetch_add(p, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ Tab to_tab(const pf_table &t) {
     Tab k;
     k.rec = reinterpret_cast<unsigned char *>(t.cell);
@@ -53,64 +39,6 @@ __device__ __forceinline__ Tab to_tab(const pf_table &t) {
     k.frac_bits = t.frac_bits;
     k.fsum = 0;  // float tables are rejected on the host
     return k;
-}
-
-// Grid-wide barrier number `epoch` (1, 2, 3 ...).  A workgroup arrives at
-// one of 64 sub-counters; the last arrival of a sub-group advances the top
-// counter, waits for all sub-groups, then raises its sub-group's release
-// flag, on which the other members wait.  So at most ~64 workgroups poll any
-// one address.  Release/acquire fences make the phase's writes visible
-// across XCDs.  Every wait is bounded in wall-clock time; a timed-out wait
-// sets the status word and returns false (the workgroup then leaves).
-__device__ bool grid_barrier(const Barrier &bar, uint32_t epoch) {
-    __shared__ uint32_t s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t G = gridDim.x;
-        const uint32_t nsub = G < (uint32_t)kSubCounters ? G : (uint32_t)kSubCounters;
-        const uint32_t sub = blockIdx.x % nsub;
-        const uint32_t in_sub = (G - sub + nsub - 1) / nsub;  // workgroups of this sub-group
-        const uint32_t old = __hip_atomic_fetch_add(bar.sub + sub * kCounterStride, 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t t0 = wall_clock64();
-        uint32_t ok = 1;
-        if (old + 1 == epoch * in_sub) {
-            __hip_atomic_fetch_add(bar.top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (poll(bar.top) < epoch * nsub) {
-                if (wall_clock64() - t0 > bar.limit) {
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-            __hip_atomic_fetch_max(bar.rel + sub * kCounterStride, ok ? epoch : 0xffffffffu, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            for (;;) {
-                const uint32_t r = poll(bar.rel + sub * kCounterStride);
-                if (r == 0xffffffffu) {
-                    ok = 0;
-                    break;
-                }
-                if (r >= epoch) break;
-                if (wall_clock64() - t0 > bar.limit) {
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-        }
-        if (!ok) {
-            __hip_atomic_fetch_or(bar.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(bar.status + 2, poll(bar.top), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(bar.status + 3, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
 }
 
 // LDS merge table of the insert phase: a window of agg_width consecutive
@@ -697,14 +625,8 @@ hipError_t launch_b(const ViewDev *views, uint32_t nviews, uint32_t agg, uint32_
         if (e != hipSuccess) return e;
         ticks_per_s = (uint64_t)(khz > 0 ? khz : 100000) * 1000ull;
     }
-    Barrier bar;
-    bar.status = ws;
-    bar.sub = ws + kCounterStride;
-    bar.rel = ws + kCounterStride * (1 + kSubCounters);
-    bar.top = ws + kCounterStride * (1 + 2 * kSubCounters);
-    bar.limit = 2 * ticks_per_s;  // a phase never takes seconds
-    const uint32_t words = kCounterStride * (2 + 2 * kSubCounters);
-    views_reset_kernel<<<1, 256, 0, st>>>(ws, words);
+    const Barrier bar = grid::barrier_at(ws, 2 * ticks_per_s);  // a phase never takes seconds
+    views_reset_kernel<<<1, 256, 0, st>>>(ws, grid::kWords);
     const uint32_t per = (per_cu == 0 || per_cu > (uint32_t)resident) ? (uint32_t)resident : per_cu;
     uint32_t grid = per * (uint32_t)cus;
     void *args[] = {(void *)&views, (void *)&nviews, (void *)&agg, (void *)&bar};

@@ -55,15 +55,24 @@ __device__ __forceinline__ uint16_t bf16(float f) {
 // lanes; global loads issued ahead stay in flight.
 __device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
+// Two floats -> two bfloat16 (low, high half) with gfx950's conversion
+// instruction: round to nearest even, identical to bf16() for every value
+// but FP32 denormals, which it flushes to zero.  Used where a denormal
+// cannot occur (the positional features) or would not matter (activations
+// and gradients inside the products); the weights' BF16 copy and the
+// normal and view-direction features keep bf16().
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2(float lo, float hi) {
+    const f32x2_t v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
 __device__ __forceinline__ v4s ld4(const uint16_t *p) { return *reinterpret_cast<const v4s *>(p); }
 
 __device__ __forceinline__ void st4(uint16_t *p, float a, float b, float c, float d) {
-    v4s v;
-    v.x = (short)bf16(a);
-    v.y = (short)bf16(b);
-    v.z = (short)bf16(c);
-    v.w = (short)bf16(d);
-    *reinterpret_cast<v4s *>(p) = v;
+    const uint2 v = {bf16x2(a, b), bf16x2(c, d)};
+    *reinterpret_cast<uint2 *>(p) = v;
 }
 
 // FP64 -> FP32 -> BF16, zeros as +0 (sinpi and cospi may return -0)
@@ -76,6 +85,10 @@ __device__ __forceinline__ uint16_t to_feature(double v) {
 // exact phase t = (q + 1/2) 2^(lp - 10 + j) = (2q + 1) 2^e, e = lp - 11 + j.
 // For e >= 0 the phase is an integer (even for e >= 1) and the values are
 // 0 and +-1 exactly; otherwise one FP64 sincospi gives both.
+// FP64 -> FP32 -> BF16 of both values is one conversion instruction: the
+// values are 0, +-1 or at least sin(pi 2^-27) in magnitude (the phase is an
+// odd multiple of 2^e, e >= -27, so it is never within 2^-27 of an
+// integer), never an FP32 denormal.
 __device__ __forceinline__ void pe_pair(int32_t qc, int lp, int j, uint16_t &sv, uint16_t &cv) {
     const int e = lp - 11 + j;
     double sn = 0.0, cs = 1.0;
@@ -85,8 +98,9 @@ __device__ __forceinline__ void pe_pair(int32_t qc, int lp, int j, uint16_t &sv,
         const double t = ldexp((double)qc + 0.5, lp - 10 + j);  // exact
         sincospi(t, &sn, &cs);
     }
-    sv = to_feature(sn);
-    cv = to_feature(cs);
+    const uint32_t both = bf16x2((float)(sn + 0.0), (float)(cs + 0.0));  // zeros as +0
+    sv = (uint16_t)both;
+    cv = (uint16_t)(both >> 16);
 }
 
 // Feature f of a vertex (f in [0, 80)), FP64 then FP64 -> FP32 -> BF16, zeros as +0.
@@ -197,9 +211,10 @@ struct WeightsT {
 // The weights' global loads, all issued before any is stored (16-byte loads
 // of the BF16 copy; wb is 16-byte aligned and every matrix starts and every
 // row ends on a 16-byte boundary), held in registers until stage().
-struct WeightLoads {
+template <int NT>
+struct WeightLoadsT {
     static constexpr int kW1 = kH * kIn / 8, kW2 = kH * kH / 8, kW3 = kOutPad * kH / 8, kB = kH + kH + kOutPad;
-    static constexpr int kN1 = (kW1 + kThreads - 1) / kThreads, kN2 = (kW2 + kThreads - 1) / kThreads;
+    static constexpr int kN1 = (kW1 + NT - 1) / NT, kN2 = (kW2 + NT - 1) / NT;
     uint4 w1[kN1], w2[kN2], w3;
     float b;
 
@@ -211,9 +226,9 @@ struct WeightLoads {
         // branch that waits for it); stage() stores only the valid ones
         const int t = threadIdx.x;
 #pragma unroll
-        for (int k = 0; k < kN1; ++k) w1[k] = v1[min(t + k * kThreads, kW1 - 1)];
+        for (int k = 0; k < kN1; ++k) w1[k] = v1[min(t + k * NT, kW1 - 1)];
 #pragma unroll
-        for (int k = 0; k < kN2; ++k) w2[k] = v2[min(t + k * kThreads, kW2 - 1)];
+        for (int k = 0; k < kN2; ++k) w2[k] = v2[min(t + k * NT, kW2 - 1)];
         w3 = v3[min(t, kW3 - 1)];
         const int tb = min(t, kB - 1);
         b = w[tb < kH ? kOffB1 + tb : (tb < 2 * kH ? kOffB2 + tb - kH : kOffB3 + tb - 2 * kH)];
@@ -235,7 +250,7 @@ struct WeightLoads {
         const int t = threadIdx.x;
 #pragma unroll
         for (int k = 0; k < kN1; ++k) {
-            const int e = 8 * min(t + k * kThreads, kW1 - 1), row = e / kIn, f0 = e % kIn;
+            const int e = 8 * min(t + k * NT, kW1 - 1), row = e / kIn, f0 = e % kIn;
             if (kSlotOrder) {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) W.w1[row * kLdIn + slot_of_input(f0 + j)] = half(w1[k], j);
@@ -245,7 +260,7 @@ struct WeightLoads {
         }
 #pragma unroll
         for (int k = 0; k < kN2; ++k) {
-            const int i = min(t + k * kThreads, kW2 - 1);
+            const int i = min(t + k * NT, kW2 - 1);
             const int row = (8 * i) / kH, col = (8 * i) % kH;
             *reinterpret_cast<uint4 *>(W.w2 + row * kLdH + col) = w2[k];
             if (T) {
@@ -267,6 +282,8 @@ struct WeightLoads {
         *bias = b;
     }
 };
+
+using WeightLoads = WeightLoadsT<kThreads>;
 
 // Forward pass of one wave's 16-row tile (rows r0..r0+15 of x, a1, a2 with
 // row strides kIn / lda).  Keeps z1, z2 (C layout) for the backward pass and
@@ -292,7 +309,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         for (int i = 0; i < 4; ++i) {
             z1[nt][i] += W.b1[n];
             h[i] = z1[nt][i] > 0.0f ? z1[nt][i] : 0.0f;
-            a1[(r0 + 4 * lg + i) * lda + n] = bf16(h[i]);
+            a1[(r0 + 4 * lg + i) * lda + n] = (uint16_t)bf16x2(h[i], 0.0f);
         }
         if (a1t) st4(a1t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
@@ -315,7 +332,7 @@ __device__ __forceinline__ v4f forward_tile(const Weights &W, const uint16_t *x,
         for (int i = 0; i < 4; ++i) {
             z2[nt][i] += W.b2[n];
             h[i] = z2[nt][i] > 0.0f ? z2[nt][i] : 0.0f;
-            a2[(r0 + 4 * lg + i) * lda + n] = bf16(h[i]);
+            a2[(r0 + 4 * lg + i) * lda + n] = (uint16_t)bf16x2(h[i], 0.0f);
         }
         if (a2t) st4(a2t + n * ldt + r0 + 4 * lg, h[0], h[1], h[2], h[3]);
     }
@@ -424,7 +441,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (lr < kOut) d = y[i] - L.target[row * 4 + lr];
         loss += d * d;
         gyv[i] = A.gscale * d;
-        L.gy[row * kOutPad + lr] = bf16(gyv[i]);
+        L.gy[row * kOutPad + lr] = (uint16_t)bf16x2(gyv[i], 0.0f);
     }
     st4(L.gyt + lr * kLdS + r0 + 4 * lg, gyv[0], gyv[1], gyv[2], gyv[3]);
     {
@@ -451,7 +468,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             g[i] = z2[nt][i] > 0.0f ? d[i] : 0.0f;
-            L.gz2[(r0 + 4 * lg + i) * kLdH + n] = bf16(g[i]);
+            L.gz2[(r0 + 4 * lg + i) * kLdH + n] = (uint16_t)bf16x2(g[i], 0.0f);
         }
         st4(L.gz2t + n * kLdS + r0 + 4 * lg, g[0], g[1], g[2], g[3]);
         const float s = col_sum((g[0] + g[1]) + (g[2] + g[3]));
@@ -587,12 +604,8 @@ struct InferLds {
 };
 
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
-    v4s v;
-    v.x = (short)bf16(a);
-    v.y = (short)bf16(b);
-    v.z = (short)bf16(c);
-    v.w = (short)bf16(d);
-    return v;
+    const uint2 v = {bf16x2(a, b), bf16x2(c, d)};
+    return __builtin_bit_cast(v4s, v);
 }
 
 // One wave's 16 vertices: xf[kk] holds this lane's slots 16 kk + 4 lg + i
@@ -630,7 +643,11 @@ __device__ __forceinline__ v4f forward_regs(const Weights &W, const v4s xf[5]) {
     return y;
 }
 
-__global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *__restrict__ wb,
+// One workgroup of 16 waves per compute unit: the weights are staged once
+// per CU (with four workgroups of 4 waves, the same 20 KB were requested
+// four times as often and the staging took up to 24 us behind the L2).
+constexpr int kInferThreads = 1024, kInferWaves = kInferThreads / 64;
+__global__ __launch_bounds__(kInferThreads) void infer_kernel(Geo g, const uint16_t *__restrict__ wb,
                                                           const float *__restrict__ w, const uint32_t *idx,
                                                           const uint32_t *counts, float *r, float *gc, float *b) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -639,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
     if (n == 0) return;
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
     {
-        WeightLoads wl;
+        WeightLoadsT<kInferThreads> wl;
         wl.issue(wb, w);
         wl.stage<true>(L.W, nullptr);
     }
@@ -650,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
     // ahead and its list entries two tiles ahead, so that the two dependent
     // random loads before a tile's features overlap the tiles before it.
     const uint32_t ntiles = (n + 15) / 16;
-    const uint32_t stride = gridDim.x * 4;
+    const uint32_t stride = gridDim.x * kInferWaves;
     constexpr uint32_t kNone = 0xffffffffu;
     auto entry = [&](uint32_t t) -> uint32_t {  // this lane's vertex in tile t (kNone: none)
         const uint32_t e = t * 16 + lr;
@@ -672,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void infer_kernel(Geo g, const uint16_t *
         in.nv[2] = g.nz[v];
         return in;
     };
-    uint32_t tile = blockIdx.x * 4 + wave;
+    uint32_t tile = blockIdx.x * kInferWaves + wave;
     uint32_t vtx = entry(tile);
     In cur = inputs(vtx);
     uint32_t vtx_next = entry(tile + stride);
@@ -955,17 +972,17 @@ hipError_t launch_mlp_infer(const MlpArgs &a, const GeoArgs &g, const uint32_t *
     if (resident[dev] == 0) {
         int per_cu = 0, cus = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(mlp::infer_kernel),
-                                                         mlp::kThreads, lds);
+                                                         mlp::kInferThreads, lds);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
         resident[dev] = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
     }
     const uint32_t tiles = (n_max + 15) / 16;
-    uint32_t blocks = (tiles + 3) / 4;
+    uint32_t blocks = (tiles + mlp::kInferWaves - 1) / mlp::kInferWaves;
     if (blocks > resident[dev]) blocks = resident[dev];
     if (blocks == 0) blocks = 1;
-    mlp::infer_kernel<<<blocks, mlp::kThreads, lds, st>>>(G, a.wb, a.w, idx, counts, r, gc, b);
+    mlp::infer_kernel<<<blocks, mlp::kInferThreads, lds, st>>>(G, a.wb, a.w, idx, counts, r, gc, b);
     return hipGetLastError();
 }
 

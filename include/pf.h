@@ -616,6 +616,27 @@ typedef struct pf_view {
  * per vertex) with their bucket counts.  0 for bad arguments. */
 size_t pf_views_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews);
 
+/* [host] Device workspace bytes of pf_filter_views_concurrent: the binned
+ * insert's workspace of every view (pf_insert_workspace_bytes), each
+ * 256-byte aligned.  0 for bad arguments. */
+size_t pf_views_concurrent_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews);
+
+/* The frame of pf_filter_views (same descriptors, the same results bit for
+ * bit) with each view through the single-view calls: pf_clear(cur), then
+ * pf_build_keys_insert_binned_temporal with prev (NULL when prev.cell is
+ * NULL) and alpha_old, or pf_build_keys_insert_binned when temporal is 0,
+ * then pf_query_average_clear emptying prev, or pf_query_average when there
+ * is no prev.  The views go to the library's streams of the current device
+ * (created at the first call, default priority), which wait on an event
+ * recorded on `stream`; the largest views first, each to the stream with the
+ * fewest vertices so far, so that small views run beside large ones; then
+ * `stream` waits on an event of every library stream.  Calls are serialised
+ * on the host per device.  workspace: pf_views_concurrent_workspace_bytes
+ * device bytes, 256-byte aligned.
+ * Errors: those of pf_filter_views (not block, agg_width, grid_per_cu). */
+pf_status pf_filter_views_concurrent(const pf_view *views, uint32_t nviews, uint32_t nstreams, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+
 /* Filters nviews views in ONE persistent launch (a cooperative grid of
  * resident workgroups of `block` threads), in four phases separated by
  * grid-wide barriers, the work items of all views spread over all

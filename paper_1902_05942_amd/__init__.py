@@ -15,7 +15,7 @@ from ._lib import (SLOT_BYTES, STAT_DISP, STAT_HIST, STAT_OVERFLOW, STAT_TEMPORA
                    V_OVERFLOW, V_RADRANGE, Mlp, PfError, Table, build_keys, clear, geometry, insert_accumulate,
                    mlp_features, mlp_infer, mlp_init, mlp_select, mlp_select_workspace_bytes, mlp_train_step,
                    query_average, read_stats, table_init, temporal_update, version, table_bytes, make_view,
-                   filter_views, views_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
+                   filter_views, views_workspace_bytes, filter_views_concurrent, views_concurrent_workspace_bytes, insert_workspace_bytes, insert_accumulate_binned,
                    microbench, MB_COPY, MB_GATHER, MB_SCATTER, MB_RMW, MB_CAS, temporal_integrate, MAX_SAMPLES,
                    build_keys_insert_binned, low_density_fallback, LD_NEIGHBOURS, LD_NORMALS, coarsen_keys,
                    query_multilevel, History, temporal_history, resolve_pixels, TEMPORAL_ACROSS_LEVELS,
@@ -216,17 +216,20 @@ class FrameFilter:
 
 
 class MultiViewFilter:
-    """Many views filtered by one persistent launch per frame.
+    """Many views filtered per frame, by one persistent launch
+    (mode "persistent", pf_filter_views) or by every view's single-view calls
+    spread over library streams (mode "concurrent",
+    pf_filter_views_concurrent); the same results.
 
     Each view has two tables (current, previous) carved from ONE arena, and
     its own key/flag/slot/count/output buffers.  filter() takes one frame dict
-    per view (device streams px..nz, valid, r, g, b and cam, s, seed) and runs
-    pf_filter_views with the given workgroup size and aggregation width, then
-    swaps every view's tables.
+    per view (device streams px..nz, valid, r, g, b and cam, s, seed), runs
+    the frame (persistent: with the given workgroup size and aggregation
+    width), then swaps every view's tables.
     """
 
     def __init__(self, views, max_probe: int = 64, frac_bits: int = 24, temporal: bool = True,
-                 alpha_old: float = 0.2, device="cuda", keys: bool = True):
+                 alpha_old: float = 0.2, device="cuda", keys: bool = True, mode: str = "persistent"):
         # views: list of (n_max, log2_slots); keys: write every vertex's key (8 bytes a vertex)
         self.temporal, self.alpha_old, self.keys = temporal, alpha_old, keys
         sizes = [table_bytes(l, True) for _, l in views]
@@ -250,7 +253,11 @@ class MultiViewFilter:
                 "count": torch.empty(n, dtype=torch.int32, device=device),
                 "out": tuple(torch.empty(n, dtype=torch.float32, device=device) for _ in range(3)),
             })
-        ws = views_workspace_bytes([n for n, _ in views], [l for _, l in views])
+        if mode not in ("persistent", "concurrent"):
+            raise ValueError(f"mode {mode!r}")
+        self.mode = mode
+        ns, ls = [n for n, _ in views], [l for _, l in views]
+        ws = views_workspace_bytes(ns, ls) if mode == "persistent" else views_concurrent_workspace_bytes(ns, ls)
         self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self.ws = self.workspace[(-base) % 256:][:ws]
@@ -268,10 +275,13 @@ class MultiViewFilter:
                                    b["count"][:n] if with_count else None, self.temporal, self.alpha_old))
         return descs
 
-    def filter(self, frames, block=256, agg_width=None, with_count=False, grid_per_cu=0):
+    def filter(self, frames, block=256, agg_width=None, with_count=False, grid_per_cu=0, nstreams=1):
         """agg_width: None = 2 x block (windows of 2 x block vertices merged in LDS)."""
-        agg = 2 * block if agg_width is None else agg_width
-        filter_views(self.descriptors(frames, with_count), block, agg, self.ws, grid_per_cu)
+        if self.mode == "concurrent":
+            filter_views_concurrent(self.descriptors(frames, with_count), self.ws, nstreams)
+        else:
+            agg = 2 * block if agg_width is None else agg_width
+            filter_views(self.descriptors(frames, with_count), block, agg, self.ws, grid_per_cu)
         if self.temporal:
             for pair in self.tables:
                 pair.reverse()

@@ -110,6 +110,8 @@ def _load():
         "pf_read_stats": ([T, vp, vp], i),
         "pf_views_workspace_bytes": ([ctypes.POINTER(u64), ctypes.POINTER(u32), u32], ctypes.c_size_t),
         "pf_filter_views": ([ctypes.POINTER(pf_view), u32, u32, u32, u32, vp, ctypes.c_size_t, vp], i),
+        "pf_views_concurrent_workspace_bytes": ([ctypes.POINTER(u64), ctypes.POINTER(u32), u32], ctypes.c_size_t),
+        "pf_filter_views_concurrent": ([ctypes.POINTER(pf_view), u32, u32, vp, ctypes.c_size_t, vp], i),
         "pf_mlp_bytes": ([u32], ctypes.c_size_t),
         "pf_mlp_carve": ([vp, u32, ctypes.POINTER(pf_mlp)], i),
         "pf_mlp_init": ([ctypes.POINTER(pf_mlp), vp], i),
@@ -135,6 +137,7 @@ EXPORTED = ("pf_version", "pf_table_bytes", "pf_table_carve", "pf_table_init", "
             "pf_insert_accumulate", "pf_query_average", "pf_temporal_update", "pf_read_stats", "pf_mlp_bytes",
             "pf_mlp_carve", "pf_mlp_init", "pf_mlp_select_workspace_bytes", "pf_mlp_select", "pf_mlp_train_step",
             "pf_mlp_features", "pf_mlp_infer", "pf_views_workspace_bytes", "pf_filter_views",
+            "pf_views_concurrent_workspace_bytes", "pf_filter_views_concurrent",
             "pf_insert_workspace_bytes", "pf_insert_accumulate_binned", "pf_microbench",
             "pf_temporal_integrate", "pf_build_keys_insert_binned", "pf_wall_clock_hz", "pf_low_density_fallback",
             "pf_coarsen_keys", "pf_query_multilevel", "pf_history_bytes", "pf_history_carve", "pf_history_init",
@@ -516,6 +519,19 @@ def views_workspace_bytes(ns, log2_slots) -> int:
     """Workspace bytes of pf_filter_views for views of ns[v] vertices and 2^log2_slots[v]-slot tables."""
     k = len(ns)
     return int(lib.pf_views_workspace_bytes((ctypes.c_uint64 * k)(*ns), (ctypes.c_uint32 * k)(*log2_slots), k))
+
+
+def views_concurrent_workspace_bytes(ns, log2_slots) -> int:
+    """Workspace bytes of pf_filter_views_concurrent."""
+    k = len(ns)
+    return int(lib.pf_views_concurrent_workspace_bytes((ctypes.c_uint64 * k)(*ns), (ctypes.c_uint32 * k)(*log2_slots),
+                                                       k))
+
+
+def filter_views_concurrent(descs, workspace, nstreams=1, stream=None):
+    arr = (pf_view * len(descs))(*descs)
+    _check("pf_filter_views_concurrent", lib.pf_filter_views_concurrent(
+        arr, len(descs), nstreams, _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def make_view(f, key, vflags, slot, out, cur: Table, prev=None, count_out=None, temporal=True, alpha_old=0.2,

@@ -1,9 +1,10 @@
-"""Autotuner of the persistent multi-view launch.
+"""Autotuner of the multi-view calls.
 
 Times pf_filter_views for every (workgroup size, aggregation width) pair on
 the caller's actual views and frames, keeps the fastest, and caches the
 choice in a JSON file keyed by the device (name, compute units) and the
-views' shapes.  Every configuration computes identical results; only the
+views' shapes; tune_streams times pf_filter_views_concurrent for 1 .. 3
+library streams.  Every configuration computes identical results; only the
 time differs.
 """
 from __future__ import annotations
@@ -78,3 +79,25 @@ def tune(mvf, frames, blocks=BLOCKS, factors=AGG_FACTORS, reps=5, use_cache=True
             json.dump(cache, fh, indent=1)
         os.replace(tmp, path)
     return best[0], best[1], res
+
+
+STREAMS = (1, 2, 3)
+
+
+def tune_streams(mvf, frames, choices=STREAMS, reps=5):
+    """For a MultiViewFilter in mode "concurrent": (fastest stream count,
+    {streams: median ms})."""
+    res = {}
+    for ns in choices:
+        mvf.filter(frames, nstreams=ns)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mvf.filter(frames, nstreams=ns)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        res[ns] = ts[len(ts) // 2]
+    return min(res, key=res.get), res

@@ -4,6 +4,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "pf_device.h"
 #include "pf_kernels.h"
 
@@ -613,6 +616,127 @@ pf_status check_view(const pf_view &d) {
     return PF_OK;
 }
 }  // namespace
+
+size_t pf_views_concurrent_workspace_bytes(const uint64_t *n, const uint32_t *log2_slots, uint32_t nviews) {
+    if (!n || !log2_slots || nviews == 0 || nviews > PF_MAX_VIEWS) return 0;
+    size_t total = 0;
+    for (uint32_t v = 0; v < nviews; ++v) {
+        if (n[v] > kMaxN || log2_slots[v] < 4 || log2_slots[v] > 30) return 0;
+        const size_t b = pf_insert_workspace_bytes(n[v], log2_slots[v]);
+        if (b == 0) return 0;
+        total += align_up(b, 256);
+    }
+    return total;
+}
+
+namespace {
+// Library streams of a device for pf_filter_views_concurrent (default
+// priority, non-blocking), with the events of one fork and join; created at
+// the first call on the device.  `lock` serialises the calls' host side,
+// which records and waits on the shared events.
+constexpr int kViewStreams = 4;
+struct ViewStreams {
+    std::mutex lock;
+    bool ready = false;
+    hipStream_t s[kViewStreams];
+    hipEvent_t fork, join[kViewStreams];
+};
+ViewStreams g_view_streams[64];
+
+hipError_t view_streams(int dev, ViewStreams *&vs) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    vs = &g_view_streams[dev];
+    if (vs->ready) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&vs->fork, hipEventDisableTiming);
+    for (int k = 0; k < kViewStreams && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&vs->s[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&vs->join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) vs->ready = true;
+    return e;
+}
+}  // namespace
+
+pf_status pf_filter_views_concurrent(const pf_view *views, uint32_t nviews, uint32_t nstreams, void *workspace,
+                                     size_t workspace_bytes, void *stream) {
+    if (!views || !workspace || (reinterpret_cast<uintptr_t>(workspace) % 256)) return PF_EINVAL;
+    if (nviews == 0 || nviews > PF_MAX_VIEWS || nstreams == 0 || nstreams > (uint32_t)kViewStreams) return PF_ERANGE;
+    uint64_t n[PF_MAX_VIEWS];
+    uint32_t lg[PF_MAX_VIEWS];
+    for (uint32_t v = 0; v < nviews; ++v) {
+        const pf_view &d = views[v];
+        const pf_status s = check_view(d);
+        if (s != PF_OK) return s;
+        if (!(d.kp.s > 0.0f) || !isfinite(d.kp.s) || !isfinite(d.kp.cam[0]) || !isfinite(d.kp.cam[1]) ||
+            !isfinite(d.kp.cam[2]))
+            return PF_ERANGE;
+        if (d.temporal && !(d.alpha_old >= 0.0f && d.alpha_old <= 1.0f)) return PF_ERANGE;
+        for (uint32_t u = 0; u < v; ++u)  // every view owns its tables
+            if (views[u].cur.cell == d.cur.cell || views[u].cur.cell == d.prev.cell ||
+                views[u].prev.cell == d.cur.cell)
+                return PF_EINVAL;
+        n[v] = d.n;
+        lg[v] = d.cur.log2_slots;
+    }
+    if (workspace_bytes < pf_views_concurrent_workspace_bytes(n, lg, nviews)) return PF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PF_ELAUNCH;
+    ViewStreams *vs = nullptr;
+    static std::mutex create;
+    {
+        std::lock_guard<std::mutex> g(create);
+        if (view_streams(dev, vs) != hipSuccess) return PF_ELAUNCH;
+    }
+    std::lock_guard<std::mutex> g(vs->lock);
+    hipStream_t caller = (hipStream_t)stream;
+    if (hipEventRecord(vs->fork, caller) != hipSuccess) return PF_ELAUNCH;
+    const int K = (int)nstreams;
+    for (int k = 0; k < K; ++k)
+        if (hipStreamWaitEvent(vs->s[k], vs->fork, 0) != hipSuccess) return PF_ELAUNCH;
+    // largest views first, each to the stream with the fewest vertices so far
+    uint32_t order[PF_MAX_VIEWS];
+    for (uint32_t v = 0; v < nviews; ++v) order[v] = v;
+    std::sort(order, order + nviews, [&](uint32_t a, uint32_t b) { return n[a] > n[b] || (n[a] == n[b] && a < b); });
+    uint64_t load[kViewStreams] = {};
+    size_t off[PF_MAX_VIEWS];
+    size_t o = 0;
+    for (uint32_t v = 0; v < nviews; ++v) {
+        off[v] = o;
+        o += align_up(pf_insert_workspace_bytes(n[v], lg[v]), 256);
+    }
+    pf_status status = PF_OK;
+    for (uint32_t i = 0; i < nviews && status == PF_OK; ++i) {
+        const uint32_t v = order[i];
+        int k = 0;
+        for (int j = 1; j < K; ++j)
+            if (load[j] < load[k]) k = j;
+        load[k] += n[v] + 1;
+        const pf_view &d = views[v];
+        void *st = vs->s[k];
+        void *ws = reinterpret_cast<char *>(workspace) + off[v];
+        const size_t wsb = pf_insert_workspace_bytes(n[v], lg[v]);
+        const pf_table *prev = d.prev.cell ? &d.prev : nullptr;
+        status = pf_clear(&d.cur, st);
+        if (status == PF_OK)
+            status = d.temporal
+                         ? pf_build_keys_insert_binned_temporal(&d.cur, d.px, d.py, d.pz, d.nx, d.ny, d.nz, d.valid,
+                                                                &d.kp, d.r, d.g, d.b, d.n, d.key, d.vflags, d.slot, ws,
+                                                                wsb, prev, d.alpha_old, 0, st)
+                         : pf_build_keys_insert_binned(&d.cur, d.px, d.py, d.pz, d.nx, d.ny, d.nz, d.valid, &d.kp,
+                                                       d.r, d.g, d.b, d.n, d.key, d.vflags, d.slot, ws, wsb, st);
+        if (status == PF_OK)
+            status = prev ? pf_query_average_clear(&d.cur, nullptr, d.slot, d.r, d.g, d.b, d.vflags, d.n, d.temporal,
+                                                   d.r_out, d.g_out, d.b_out, d.count_out, prev, st)
+                          : pf_query_average(&d.cur, nullptr, d.slot, d.r, d.g, d.b, d.vflags, d.n, d.temporal,
+                                             d.r_out, d.g_out, d.b_out, d.count_out, st);
+    }
+    // join every stream back into the caller's, also after a failure
+    for (int k = 0; k < K; ++k)
+        if (hipEventRecord(vs->join[k], vs->s[k]) != hipSuccess ||
+            hipStreamWaitEvent(caller, vs->join[k], 0) != hipSuccess)
+            status = PF_ELAUNCH;
+    return status;
+}
 
 pf_status pf_filter_views(const pf_view *views, uint32_t nviews, uint32_t block, uint32_t agg_width,
                           uint32_t grid_per_cu, void *workspace, size_t workspace_bytes, void *stream) {

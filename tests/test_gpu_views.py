@@ -57,7 +57,16 @@ PICKS = autotune.candidates()
 
 @pytest.mark.parametrize("block,agg", PICKS)
 def test_views_bit_exact_over_frames(gpu, block, agg):
-    mvf = pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=True, alpha_old=0.2)
+    _views_over_frames("persistent", block, agg)
+
+
+def test_views_concurrent_bit_exact_over_frames(gpu):
+    """The single-view calls of every view on the library's streams."""
+    _views_over_frames("concurrent", 0, 0)
+
+
+def _views_over_frames(mode, block, agg):
+    mvf = pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=True, alpha_old=0.2, mode=mode)
     states = [None] * len(SHAPES)
     expected = _oracle_frames()
     for frame in range(3):
@@ -65,7 +74,8 @@ def test_views_bit_exact_over_frames(gpu, block, agg):
         dev = [{k: (v.cuda() if torch.is_tensor(v) else v) for k, v in f.items()} for f in fs]
         outs = mvf.filter(dev, block, agg, with_count=True)
         torch.cuda.synchronize()
-        assert mvf.status() == 0, mvf.status_words()
+        if mode == "persistent":
+            assert mvf.status() == 0, mvf.status_words()
         for v, f in enumerate(fs):
             R, _ = expected[frame][v]
             b = mvf.bufs[v]
@@ -151,3 +161,34 @@ def test_eight_views_full_size_one_frame(gpu):
             st = pf.read_stats(t)
             assert int(st[pf.STAT_USED]) == len(R.gkey) and int(st[pf.STAT_DISP]) == R.table.total_disp
             assert int(st[pf.STAT_TEMPORAL_HIT]) == int(np.isin(R.gkey, states[v][0]).sum())
+
+
+def test_eight_views_full_size_concurrent_equals_persistent(gpu):
+    """Two frames of the full 8-view workload through the single-view calls
+    on the library's streams and through the persistent launch (checked
+    against the oracle above): every output, flag and count equal, and every
+    table's cells (by key) and occupied slots (linear probing occupies the
+    same slots in any order of insertion; which of two colliding keys takes
+    the first depends on the order)."""
+    wl = synth.get("multiview_8")
+    shapes = [(v.width * v.height * v.verts_per_path, v.log2_slots) for v in wl.views]
+    filters = [pf.MultiViewFilter(shapes, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
+                                  keys=False, mode=m) for m in ("persistent", "concurrent")]
+    for frame in range(2):
+        fs = [synth.generate(wl, view=v, frame=frame) for v in range(len(wl.views))]
+        dev = [{k: (x.cuda() if torch.is_tensor(x) else x) for k, x in f.items()} for f in fs]
+        outs = [mvf.filter(dev, 1024, 4096, with_count=True) for mvf in filters]
+        torch.cuda.synchronize()
+        assert filters[0].status() == 0
+        for v in range(len(fs)):
+            for a, b in zip(outs[0][v], outs[1][v]):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (frame, v)
+            for name in ("vflags", "count"):  # slots: which of two colliding keys sits first depends on order
+                n = fs[v]["px"].numel()
+                assert torch.equal(filters[0].bufs[v][name][:n], filters[1].bufs[v][name][:n]), (frame, v, name)
+            ta, tb = (table_contents(mvf.tables[v][1]) for mvf in filters)
+            oa, ob = np.argsort(ta["key"]), np.argsort(tb["key"])
+            for k in ("key", "count", "sum", "blend"):
+                assert np.array_equal(ta[k][oa], tb[k][ob]), (frame, v, k)
+            assert np.array_equal(ta["occupied"], tb["occupied"]), (frame, v)
+        del dev

@@ -114,6 +114,38 @@ def test_features_are_bit_exact(gpu):
     assert np.array_equal(got, want), int((got != want).sum())
 
 
+def test_positional_features_exhaustive(gpu):
+    """Every phase the positional encoding can take: the quantised position
+    q in [-2^16, 2^16) on all three axes at levels l' = -16, -4, 8, whose 12
+    frequencies cover every exponent e = l' - 11 + j from -27 to 8 (the
+    phases (2q + 1) 2^e with e < 0 are the ones evaluated with sinpi and
+    cospi; e >= 0 gives 0 and +-1).  All 80 inputs of 393,216 keys equal
+    the reference's bit for bit."""
+    q = np.arange(-65536, 65536, dtype=np.int64)
+    keys = []
+    for lp in (-16, -4, 8):
+        u = (q + 65536).astype(np.uint64)
+        keys.append(u | (u << np.uint64(17)) | (u << np.uint64(34)) | np.uint64(lp + 16) << np.uint64(51))
+    k = np.concatenate(keys)
+    n = k.size
+    rng = np.random.default_rng(11)
+    pos = rng.uniform(-4, 4, (n, 3)).astype(np.float32)
+    nrm = rng.normal(0, 1, (n, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    cam = np.array([0.5, 1.5, -7.0], np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    geo = pf.geometry(dev(k.view(np.int64)), dev(pos[:, 0]), dev(pos[:, 1]), dev(pos[:, 2]), dev(nrm[:, 0]),
+                      dev(nrm[:, 1]), dev(nrm[:, 2]), cam)
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    out = torch.empty((n, 80), dtype=torch.int16, device="cuda")
+    pf.mlp_features(geo, idx, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint16)
+    want = om.bf16_bits(om.features(k, pos, nrm, cam))
+    bad = got != want
+    assert not bad.any(), (int(bad.sum()), np.argwhere(bad)[:5].tolist())
+
+
 def test_inference_matches_reference(gpu):
     wl, f = _frame()
     g, flt, out, R = _filtered(f)

@@ -122,6 +122,24 @@ def test_views_argument_checks(gpu):
     del mvf
 
 
+def test_views_concurrent_argument_checks(gpu):
+    wl, fs = _views(0)
+    f = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in fs[1].items()}
+    n = f["px"].numel()
+    mvf = pf.MultiViewFilter([(n, 14)], temporal=True, mode="concurrent")
+    d = mvf.descriptors([f])
+    for ns in (0, 5):
+        with pytest.raises(pf.PfError):
+            pf.filter_views_concurrent(d, mvf.ws, nstreams=ns)          # stream count outside 1..4
+    with pytest.raises(pf.PfError):
+        pf.filter_views_concurrent(d, mvf.ws[:1024], nstreams=1)        # workspace too small
+    with pytest.raises(pf.PfError):
+        pf.filter_views_concurrent(d + d, mvf.ws, nstreams=2)           # two views sharing tables
+    d[0].r_out = d[0].r
+    with pytest.raises(pf.PfError):
+        pf.filter_views_concurrent(d, mvf.ws, nstreams=1)               # output aliasing the input
+
+
 def test_eight_views_full_size_one_frame(gpu):
     """One frame of the full 8-view workload (59.5M vertex slots, per-view
     tables of 2^19 .. 2^24 slots in one arena) at the configuration the

@@ -468,8 +468,7 @@ def main():
         # the other configurations, each as one block of this line: the learned
         # fallback on the same frames, one 8-view launch, the 4K frame
         print("[bench] learned fallback leg", file=sys.stderr, flush=True)
-        legs["mlp"] = mlp_leg(frames, wl, dev, per.get("build_keys_insert_temporal", 0.0) +
-                              per.get("query_average_clear", 0.0))
+        legs["mlp"] = mlp_leg(frames, wl, dev)
         print("[bench] 8-view leg", file=sys.stderr, flush=True)
         legs["multiview"] = multiview_leg(a, dev, steps=20, warmup=4)
         print("[bench] 4K leg", file=sys.stderr, flush=True)
@@ -757,7 +756,7 @@ def uhd_leg(a, dev, probes, reps):
             "scene": frame, "scene_small_cells": scene_small, "key_sweep": sweep}
 
 
-def mlp_leg(frames, wl, dev, frame_us_plain):
+def mlp_leg(frames, wl, dev):
     """The learned fallback for sparse cells on the same 1080p frames (the
     network trained online from scratch, 4 steps of 16384 samples per frame):
     16 frames to train, then 32 timed frames; RMSE against the noise-free
@@ -784,17 +783,31 @@ def mlp_leg(frames, wl, dev, frame_us_plain):
     for k in range(warm):
         run(flt, k)
     torch.cuda.synchronize()
-    evs = []
+    # whole frames with the fallback, events between frames only (an event
+    # recorded between two kernels costs a few microseconds of idle GPU)
+    fe = [torch.cuda.Event(enable_timing=True) for _ in range(timed + 1)]
+    fe[0].record()
     for k in range(warm, warm + timed):
+        run(flt, k)
+        fe[k - warm + 1].record()
+    torch.cuda.synchronize()
+    frame_with_us = float(np.mean([fe[k].elapsed_time(fe[k + 1]) for k in range(timed)])) * 1e3
+    # the stages' split, from further frames with events between the stages
+    split = 8
+    evs = []
+    t_wall = time.perf_counter()
+    for k in range(warm + timed, warm + timed + split):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         e[0].record()
         out = run(flt, k, mlp_timing=e[1:5])
         e[5].record()
         evs.append(e)
     torch.cuda.synchronize()
+    wall_us = (time.perf_counter() - t_wall) * 1e6 / split
     ms = lambda i, j: float(np.mean([e[i].elapsed_time(e[j]) for e in evs])) * 1e3  # noqa: E731
-    frame_us, select_us, train_us, infer_us = ms(0, 5), ms(1, 2), ms(2, 3), ms(3, 4)
-    f_last = frames[(warm + timed - 1) % nfr]
+    select_us, train_us, infer_us = ms(1, 2), ms(2, 3), ms(3, 4)
+    last = warm + timed + split - 1
+    f_last = frames[last % nfr]
     n_ = n
     sparse = (flt.vflags[:n_] == 0) & (flt.count[:n_] < 4)
     truth = f_last["truth"]
@@ -804,27 +817,33 @@ def mlp_leg(frames, wl, dev, frame_us_plain):
         return float(torch.sqrt(((torch.stack(o, 1)[msk] - truth[msk]) ** 2).mean()))
     q_with, q_with_all = rmse(out, sparse), rmse(out, valid)
     res = {}
-    # the same 16 frames ending on the same one: the moving average alone, then the paper's fallbacks
+    frame_without_us = None
+    # the same 16 frames ending on the same one: the moving average alone (its last 12 frames timed as the
+    # frames with the fallback were), then the paper's fallbacks
     for name, opt in (("without", {}), ("neighbours", {"low_density": (4, pf.LD_NEIGHBOURS)}),
                       ("normals", {"low_density": (4, pf.LD_NORMALS)}), ("multilevel_1", {"multilevel": (4, 1)})):
         ref = pf.FrameFilter(n, view.log2_slots, wl.max_probe, wl.frac_bits, temporal=True, alpha_old=wl.alpha_old,
                              device=dev, fused=True, **opt)
-        for k in range(warm + timed - 16, warm + timed):
+        we = [torch.cuda.Event(enable_timing=True) for _ in range(17)]
+        for j, k in enumerate(range(last - 15, last + 1)):
             o = run(ref, k)
+            we[j + 1].record()
+        if name == "without":
+            torch.cuda.synchronize()
+            frame_without_us = float(np.mean([we[j].elapsed_time(we[j + 1]) for j in range(4, 16)])) * 1e3
         res[name] = {"rmse_sparse": round(rmse(o, sparse), 5), "rmse_all": round(rmse(o, valid), 5)}
         del ref
     flops = fb.steps * fb.batch * 2 * (10240 + 15360)
-    mlp_us = select_us + train_us + infer_us
+    mlp_us = frame_with_us - frame_without_us
     return {"workload": "hd_1080p_x3_mlp", "frames_trained_before_timing": warm, "timed_frames": timed,
             "sparse_vertices": int(sparse.sum()),
             "rmse_sparse_without": res["without"]["rmse_sparse"], "rmse_sparse_with": round(q_with, 5),
             "rmse_all_without": res["without"]["rmse_all"], "rmse_all_with": round(q_with_all, 5),
+            # the fallback's cost: frames with it minus the same frames without it, events between frames only
             "us_per_frame": round(mlp_us, 2),
-            # the frame's kernels: the plain frame's (the default run's events) plus the fallback's stages
-            "frame_gpu_us_without": round(frame_us_plain, 2), "frame_gpu_us_with": round(frame_us_plain + mlp_us, 2),
-            # between the first and the last event of a frame driven from Python, one library call at a time:
-            # the host's time to issue the fallback's eleven calls exceeds the kernels'
-            "frame_wall_us_python_driven": round(frame_us, 2),
+            "frame_gpu_us_without": round(frame_without_us, 2), "frame_gpu_us_with": round(frame_with_us, 2),
+            "frame_wall_us_python_driven": round(wall_us, 2),
+            # the stages, from frames with events between them (each such event adds a few microseconds)
             "select_us": round(select_us, 2), "train_us": round(train_us, 2), "infer_us": round(infer_us, 2),
             "train_flops_per_frame": flops, "train_bf16_tflops": round(flops / (train_us * 1e-6) / 1e12, 3),
             "train_frac_of_mfma_peak": round(flops / (train_us * 1e-6) / 2.5e15, 5),

@@ -210,3 +210,23 @@ def test_eight_views_full_size_concurrent_equals_persistent(gpu):
                 assert np.array_equal(ta[k][oa], tb[k][ob]), (frame, v, k)
             assert np.array_equal(ta["occupied"], tb["occupied"]), (frame, v)
         del dev
+
+
+def test_views_without_temporal_blend_concurrent_equals_persistent(gpu):
+    """Views filtered without the moving average (the plain lookup, no
+    previous table): both ways of filtering many views give the same
+    outputs, flags and counts over two frames."""
+    filters = [pf.MultiViewFilter([(w * h * vpp, m) for w, h, vpp, m in SHAPES], temporal=False, mode=m)
+               for m in ("persistent", "concurrent")]
+    for frame in range(2):
+        wl, fs = _views(frame)
+        dev = [{k: (v.cuda() if torch.is_tensor(v) else v) for k, v in f.items()} for f in fs]
+        outs = [mvf.filter(dev, 256, 512, with_count=True) for mvf in filters]
+        torch.cuda.synchronize()
+        assert filters[0].status() == 0
+        for v, f in enumerate(fs):
+            n = f["px"].numel()
+            for a, b in zip(outs[0][v], outs[1][v]):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (frame, v)
+            for name in ("vflags", "count"):
+                assert torch.equal(filters[0].bufs[v][name][:n], filters[1].bufs[v][name][:n]), (frame, v, name)

@@ -950,7 +950,7 @@ def _oracle_worker(wname, frame0, k, barrier, results):
 
 
 def host_cores():
-    """Cores this process may run on, at most 16 (a one-GPU machine's share)."""
+    """Cores this process may run on, at most 16 (the host cores that go with one GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

@@ -81,24 +81,71 @@ __device__ __forceinline__ uint16_t to_feature(double v) {
     return bf16((float)v);
 }
 
+// sin(pi t) and cos(pi t) in FP32 for the dyadic phase t = m 2^e (m odd,
+// |m| < 2^17, -27 <= e <= -1).  The phase is reduced exactly with integers:
+// t = k/2 + r, |r| <= 1/4, and r = R 2^(e-1) with |R| < 2^18 is exact in FP32.
+// sin(pi r) and cos(pi r) come from their Taylor series (through r^9 and
+// r^10, truncation below 2^-28 relative at |r| = 1/4), coefficients rounded
+// to FP32 and evaluated with explicit fused multiply-adds; each value lies
+// within 3 FP32 ulps of the true one (2 observed over every phase), and
+// the quadrant k swaps and negates them exactly.  Returns true when either
+// value lies within kTieGuard bit patterns of a BF16 rounding midpoint:
+// only there could the FP64 value, rounded FP64 -> FP32 -> BF16, round to
+// a different BF16 than this FP32 value does.
+constexpr uint32_t kTieGuard = 16;
+__device__ __forceinline__ bool near_bf16_tie(float y) {
+    const uint32_t lo = __float_as_uint(y) & 0xffffu;
+    return lo - (0x8000u - kTieGuard) <= 2u * kTieGuard;
+}
+__device__ __forceinline__ bool dyadic_sincospi(int32_t m, int e, float &so, float &co) {
+    const int sh = -e;
+    const int32_t n = 1 << sh;                       // t = m / n
+    const int32_t mm = m & (2 * n - 1);              // m mod 2n: t mod 2 in [0, 2)
+    const int32_t k = (2 * mm + (n >> 1)) >> sh;     // nearest multiple of 1/2
+    const int32_t R = 2 * mm - k * n;                // r = R / (2n)
+    const float r = ldexpf((float)R, e - 1);
+    const float r2 = r * r;
+    float p = fmaf(r2, 0x1.507834p-4f, -0x1.32d2ccp-1f);  // pi^9/9!, -pi^7/7!
+    p = fmaf(r2, p, 0x1.466bc6p+1f);                      // pi^5/5!
+    p = fmaf(r2, p, -0x1.4abbcep+2f);                     // -pi^3/3!
+    p = fmaf(r2, p, 0x1.921fb6p+1f);                      // pi
+    const float sr = r * p;
+    float c = fmaf(r2, -0x1.a6d1f2p-6f, 0x1.e1f506p-3f);  // -pi^10/10!, pi^8/8!
+    c = fmaf(r2, c, -0x1.55d3c8p+0f);                     // -pi^6/6!
+    c = fmaf(r2, c, 0x1.03c1f0p+2f);                      // pi^4/4!
+    c = fmaf(r2, c, -0x1.3bd3ccp+2f);                     // -pi^2/2!
+    const float cr = fmaf(r2, c, 1.0f);
+    const bool odd = (k & 1) != 0, neg_s = (k & 2) != 0, neg_c = ((k + 1) & 2) != 0;
+    const float sv = odd ? cr : sr, cv = odd ? sr : cr;
+    so = (neg_s ? -sv : sv) + 0.0f;  // zeros as +0
+    co = (neg_c ? -cv : cv) + 0.0f;
+    return near_bf16_tie(so) || near_bf16_tie(co);
+}
+
 // Positional-encoding pair j of coordinate c: sin and cos of pi t with the
 // exact phase t = (q + 1/2) 2^(lp - 10 + j) = (2q + 1) 2^e, e = lp - 11 + j.
 // For e >= 0 the phase is an integer (even for e >= 1) and the values are
-// 0 and +-1 exactly; otherwise one FP64 sincospi gives both.
-// FP64 -> FP32 -> BF16 of both values is one conversion instruction: the
-// values are 0, +-1 or at least sin(pi 2^-27) in magnitude (the phase is an
-// odd multiple of 2^e, e >= -27, so it is never within 2^-27 of an
-// integer), never an FP32 denormal.
+// 0 and +-1 exactly; otherwise dyadic_sincospi gives both, or, near a BF16
+// rounding midpoint, one FP64 sincospi, so that both are the FP64 values
+// rounded FP64 -> FP32 -> BF16.
+// FP32 -> BF16 of both values is one conversion instruction: the values are
+// 0, +-1 or at least sin(pi 2^-27) in magnitude (the phase is an odd
+// multiple of 2^e, e >= -27, so it is never within 2^-27 of an integer),
+// never an FP32 denormal.
 __device__ __forceinline__ void pe_pair(int32_t qc, int lp, int j, uint16_t &sv, uint16_t &cv) {
     const int e = lp - 11 + j;
-    double sn = 0.0, cs = 1.0;
+    float sn = 0.0f, cs = 1.0f;
     if (e == 0) {
-        cs = -1.0;  // odd integer
+        cs = -1.0f;  // odd integer
     } else if (e < 0) {
-        const double t = ldexp((double)qc + 0.5, lp - 10 + j);  // exact
-        sincospi(t, &sn, &cs);
+        if (dyadic_sincospi(2 * qc + 1, e, sn, cs)) {
+            double s64, c64;
+            sincospi(ldexp((double)qc + 0.5, lp - 10 + j), &s64, &c64);  // exact phase
+            sn = (float)(s64 + 0.0);
+            cs = (float)(c64 + 0.0);
+        }
     }
-    const uint32_t both = bf16x2((float)(sn + 0.0), (float)(cs + 0.0));  // zeros as +0
+    const uint32_t both = bf16x2(sn, cs);
     sv = (uint16_t)both;
     cv = (uint16_t)(both >> 16);
 }

@@ -82,28 +82,28 @@ __device__ __forceinline__ uint16_t to_feature(double v) {
 }
 
 // sin(pi t) and cos(pi t) in FP32 for the dyadic phase t = m 2^e (m odd,
-// |m| < 2^17, -27 <= e <= -1).  The phase is reduced exactly with integers:
-// t = k/2 + r, |r| <= 1/4, and r = R 2^(e-1) with |R| < 2^18 is exact in FP32.
-// sin(pi r) and cos(pi r) come from their Taylor series (through r^9 and
-// r^10, truncation below 2^-28 relative at |r| = 1/4), coefficients rounded
-// to FP32 and evaluated with explicit fused multiply-adds; each value lies
-// within 3 FP32 ulps of the true one (2 observed over every phase), and
-// the quadrant k swaps and negates them exactly.  Returns true when either
-// value lies within kTieGuard bit patterns of a BF16 rounding midpoint:
-// only there could the FP64 value, rounded FP64 -> FP32 -> BF16, round to
-// a different BF16 than this FP32 value does.
+// |m| < 2^17, e <= 15).  Every step of the reduction is exact: t itself
+// (with e clamped to 1: every even integer phase gives 0 and 1, as 2 does),
+// 2t, its nearest integer k, and r = t - k/2 with |r| <= 1/4 (a multiple of
+// 2^e with at most 18 significant bits).  sin(pi r) and cos(pi r) come from
+// their Taylor series (through r^9 and r^10, truncation below 2^-28
+// relative at |r| = 1/4), coefficients rounded to FP32 and evaluated with
+// explicit fused multiply-adds; each value lies within 3 FP32 ulps of the
+// true one (2 observed over every phase), and the quadrant k mod 4 swaps
+// and negates them exactly.  Returns true when either value lies within
+// kTieGuard bit patterns of a BF16 rounding midpoint: only there could the
+// FP64 value, rounded FP64 -> FP32 -> BF16, round to a different BF16 than
+// this FP32 value does (never for an integer phase, whose values are exact).
 constexpr uint32_t kTieGuard = 16;
 __device__ __forceinline__ bool near_bf16_tie(float y) {
     const uint32_t lo = __float_as_uint(y) & 0xffffu;
     return lo - (0x8000u - kTieGuard) <= 2u * kTieGuard;
 }
 __device__ __forceinline__ bool dyadic_sincospi(int32_t m, int e, float &so, float &co) {
-    const int sh = -e;
-    const int32_t n = 1 << sh;                       // t = m / n
-    const int32_t mm = m & (2 * n - 1);              // m mod 2n: t mod 2 in [0, 2)
-    const int32_t k = (2 * mm + (n >> 1)) >> sh;     // nearest multiple of 1/2
-    const int32_t R = 2 * mm - k * n;                // r = R / (2n)
-    const float r = ldexpf((float)R, e - 1);
+    const float t = ldexpf((float)m, e < 1 ? e : 1);
+    const float k = __builtin_rintf(2.0f * t);  // nearest multiple of 1/2, ties to even
+    const float r = fmaf(k, -0.5f, t);
+    const int kq = (int)k;
     const float r2 = r * r;
     float p = fmaf(r2, 0x1.507834p-4f, -0x1.32d2ccp-1f);  // pi^9/9!, -pi^7/7!
     p = fmaf(r2, p, 0x1.466bc6p+1f);                      // pi^5/5!
@@ -115,7 +115,7 @@ __device__ __forceinline__ bool dyadic_sincospi(int32_t m, int e, float &so, flo
     c = fmaf(r2, c, 0x1.03c1f0p+2f);                      // pi^4/4!
     c = fmaf(r2, c, -0x1.3bd3ccp+2f);                     // -pi^2/2!
     const float cr = fmaf(r2, c, 1.0f);
-    const bool odd = (k & 1) != 0, neg_s = (k & 2) != 0, neg_c = ((k + 1) & 2) != 0;
+    const bool odd = (kq & 1) != 0, neg_s = (kq & 2) != 0, neg_c = ((kq + 1) & 2) != 0;
     const float sv = odd ? cr : sr, cv = odd ? sr : cr;
     so = (neg_s ? -sv : sv) + 0.0f;  // zeros as +0
     co = (neg_c ? -cv : cv) + 0.0f;
@@ -123,27 +123,21 @@ __device__ __forceinline__ bool dyadic_sincospi(int32_t m, int e, float &so, flo
 }
 
 // Positional-encoding pair j of coordinate c: sin and cos of pi t with the
-// exact phase t = (q + 1/2) 2^(lp - 10 + j) = (2q + 1) 2^e, e = lp - 11 + j.
-// For e >= 0 the phase is an integer (even for e >= 1) and the values are
-// 0 and +-1 exactly; otherwise dyadic_sincospi gives both, or, near a BF16
-// rounding midpoint, one FP64 sincospi, so that both are the FP64 values
-// rounded FP64 -> FP32 -> BF16.
-// FP32 -> BF16 of both values is one conversion instruction: the values are
-// 0, +-1 or at least sin(pi 2^-27) in magnitude (the phase is an odd
-// multiple of 2^e, e >= -27, so it is never within 2^-27 of an integer),
-// never an FP32 denormal.
+// exact phase t = (q + 1/2) 2^(lp - 10 + j) = (2q + 1) 2^e, e = lp - 11 + j,
+// from dyadic_sincospi, or, near a BF16 rounding midpoint, from one FP64
+// sincospi, so that both are the FP64 values rounded FP64 -> FP32 -> BF16.
+// No other branch: the lanes of a wavefront hold vertices of different
+// levels.  FP32 -> BF16 of both values is one conversion instruction: the
+// values are 0, +-1 or at least sin(pi 2^-27) in magnitude (the phase is an
+// odd multiple of 2^e, e >= -27, so it is never within 2^-27 of an
+// integer), never an FP32 denormal.
 __device__ __forceinline__ void pe_pair(int32_t qc, int lp, int j, uint16_t &sv, uint16_t &cv) {
-    const int e = lp - 11 + j;
-    float sn = 0.0f, cs = 1.0f;
-    if (e == 0) {
-        cs = -1.0f;  // odd integer
-    } else if (e < 0) {
-        if (dyadic_sincospi(2 * qc + 1, e, sn, cs)) {
-            double s64, c64;
-            sincospi(ldexp((double)qc + 0.5, lp - 10 + j), &s64, &c64);  // exact phase
-            sn = (float)(s64 + 0.0);
-            cs = (float)(c64 + 0.0);
-        }
+    float sn, cs;
+    if (dyadic_sincospi(2 * qc + 1, lp - 11 + j, sn, cs)) {
+        double s64, c64;
+        sincospi(ldexp((double)qc + 0.5, lp - 10 + j), &s64, &c64);  // exact phase
+        sn = (float)(s64 + 0.0);
+        cs = (float)(c64 + 0.0);
     }
     const uint32_t both = bf16x2(sn, cs);
     sv = (uint16_t)both;
@@ -793,12 +787,14 @@ __global__ void init_kernel(const float *__restrict__ w, uint16_t *__restrict__ 
 }
 
 // ----------------------------------------------------------- selection
-// Two passes over blocks of 4096 vertices, 16 consecutive vertices a thread
-// (one 16-byte load of flags, four of counts where both arrays are 16-byte
-// aligned): the first counts each block's listed vertices; the second sums
-// the counts of the blocks before its own (a few KB from L2, so there is no
-// separate scan), ranks its threads, and writes its part of each list as
-// one contiguous run staged in LDS, in vertex order.
+// Two passes over blocks of 4096 vertices, 16 consecutive vertices a thread.
+// The first reads the flags and counts (one 16-byte load of flags, four of
+// counts where both arrays are 16-byte aligned), counts each block's listed
+// vertices and keeps each thread's two 16-bit masks in one word (1 bit per
+// vertex and list instead of the 5 bytes read).  The second reads the masks,
+// sums the counts of the blocks before its own (a few KB from L2, so there
+// is no separate scan), ranks its threads, and writes its part of each list
+// as one contiguous run staged in LDS, in vertex order.
 constexpr int kSelPerThread = 16;
 constexpr int kSelPerBlock = kThreads * kSelPerThread;  // 4096
 
@@ -865,11 +861,14 @@ __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t &pa
     __syncthreads();  // s_wave is reused by the next call
 }
 
+// bcnt: [0, nblocks) training counts, [nblocks, 2 nblocks) sparse counts,
+// then a word per thread: training mask (low 16 bits), sparse mask (high)
 __global__ __launch_bounds__(kThreads) void select_count_kernel(const uint8_t *flags, const uint32_t *count,
                                                                 uint32_t n, uint32_t lo, uint32_t hi, bool vec,
                                                                 uint32_t *bcnt, uint32_t nblocks) {
     uint32_t tr, sp;
     sel_masks(blockIdx.x * kSelPerBlock + threadIdx.x * kSelPerThread, n, flags, count, lo, hi, vec, tr, sp);
+    bcnt[2 * nblocks + blockIdx.x * kThreads + threadIdx.x] = tr | sp << 16;
     uint32_t pa, pb, ta, tb;
     block_scan2(__popc(tr), __popc(sp), pa, pb, ta, tb);
     if (threadIdx.x == 0) {
@@ -878,14 +877,16 @@ __global__ __launch_bounds__(kThreads) void select_count_kernel(const uint8_t *f
     }
 }
 
-__global__ __launch_bounds__(kThreads) void select_scatter_kernel(const uint8_t *flags, const uint32_t *count,
-                                                                  uint32_t n, uint32_t lo, uint32_t hi, bool vec,
-                                                                  const uint32_t *bcnt, uint32_t nblocks,
+__global__ __launch_bounds__(kThreads) void select_scatter_kernel(const uint32_t *bcnt, uint32_t nblocks,
                                                                   uint32_t *tr_idx, uint32_t *sp_idx,
                                                                   uint32_t *counts) {
     const uint32_t base = blockIdx.x * kSelPerBlock + threadIdx.x * kSelPerThread;
-    uint32_t tr, sp;
-    sel_masks(base, n, flags, count, lo, hi, vec, tr, sp);
+    uint32_t tr = 0, sp = 0;
+    if (nblocks) {
+        const uint32_t m = bcnt[2 * nblocks + blockIdx.x * kThreads + threadIdx.x];
+        tr = m & 0xffffu;
+        sp = m >> 16;
+    }
     // this block's offsets: the counts of the blocks before it
     uint32_t before_t = 0, before_s = 0;
     for (uint32_t k = threadIdx.x; k < blockIdx.x; k += kThreads) {
@@ -930,8 +931,8 @@ hipError_t launch_mlp_select(const uint8_t *flags, const uint32_t *count, uint32
     if (nblocks)
         mlp::select_count_kernel<<<nblocks, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, vec, ws, nblocks);
     // n == 0: one block writes zero counts
-    mlp::select_scatter_kernel<<<nblocks ? nblocks : 1, mlp::kThreads, 0, st>>>(flags, count, n, lo, hi, vec, ws,
-                                                                                nblocks, tr_idx, sp_idx, counts);
+    mlp::select_scatter_kernel<<<nblocks ? nblocks : 1, mlp::kThreads, 0, st>>>(ws, nblocks, tr_idx, sp_idx,
+                                                                                counts);
     return hipGetLastError();
 }
 

@@ -528,7 +528,9 @@ pf_status pf_mlp_init(const pf_mlp *m, void *stream) {
 
 size_t pf_mlp_select_workspace_bytes(uint64_t n) {
     if (n > kMaxN) return 0;
-    return (size_t)2 * pfk::mlp_select_blocks((uint32_t)n) * sizeof(uint32_t) + 4;
+    // two counts per block of 4096 vertices, then a mask word per 16 vertices
+    const size_t blocks = pfk::mlp_select_blocks((uint32_t)n);
+    return (2 * blocks + blocks * 256) * sizeof(uint32_t) + 4;
 }
 
 pf_status pf_mlp_select(const uint8_t *vflags, const uint32_t *count, uint64_t n, uint32_t sparse_below,

@@ -69,23 +69,32 @@ def test_select_lists_are_exact(gpu):
     assert nt == len(want_tr) and ns == len(want_sp) and nt > 1000 and ns > 1000
     assert np.array_equal(tr[:nt].cpu().numpy(), want_tr)
     assert np.array_equal(sp[:ns].cpu().numpy(), want_sp)
-    # arrays that start one vertex in (not 16-byte aligned: the per-vertex
-    # loads instead of the 16-byte ones): the lists of vertices 1..n-1, renumbered
-    m = n - 1
-    tr1 = torch.empty(m, dtype=torch.int32, device="cuda")
-    sp1 = torch.empty(m, dtype=torch.int32, device="cuda")
-    c1 = torch.zeros(2, dtype=torch.int32, device="cuda")
-    ws = torch.empty(pf.mlp_select_workspace_bytes(m), dtype=torch.uint8, device="cuda")
-    pf.mlp_select(flt.vflags[1:n], flt.count[1:n], 4, 16, tr1, sp1, c1, ws)
-    nt1, ns1 = (int(v) for v in c1.cpu().numpy())
-    assert np.array_equal(tr1[:nt1].cpu().numpy(), np.nonzero((ok & (R.cnt >= 16))[1:])[0])
-    assert np.array_equal(sp1[:ns1].cpu().numpy(), np.nonzero((ok & (R.cnt < 4))[1:])[0])
+    # one workspace through a sequence of calls: arrays that start one vertex
+    # in (not 16-byte aligned: the per-vertex loads instead of the 16-byte
+    # ones), ragged and short ranges (one block, a few, 71), the whole frame
+    # again, then an empty call
+    ws = torch.empty(pf.mlp_select_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    want_t, want_s = ok & (R.cnt >= 16), ok & (R.cnt < 4)
+    for lo_v, hi_v in ((1, n), (0, n), (0, 4096), (5, 3 * 4096 + 17), (0, 70 * 4096 + 1000), (3, n), (0, 1)):
+        m = hi_v - lo_v
+        tr1 = torch.full((m,), -1, dtype=torch.int32, device="cuda")
+        sp1 = torch.full((m,), -1, dtype=torch.int32, device="cuda")
+        c1 = torch.full((2,), -1, dtype=torch.int32, device="cuda")
+        pf.mlp_select(flt.vflags[lo_v:hi_v], flt.count[lo_v:hi_v], 4, 16, tr1, sp1, c1, ws)
+        nt1, ns1 = (int(v) for v in c1.cpu().numpy())
+        et, es = np.nonzero(want_t[lo_v:hi_v])[0], np.nonzero(want_s[lo_v:hi_v])[0]
+        assert (nt1, ns1) == (len(et), len(es)), (lo_v, hi_v)
+        assert np.array_equal(tr1[:nt1].cpu().numpy(), et), (lo_v, hi_v)
+        assert np.array_equal(sp1[:ns1].cpu().numpy(), es), (lo_v, hi_v)
     # empty input: counts become zero
     counts = torch.full((2,), 7, dtype=torch.int32, device="cuda")
     e = torch.empty(0, dtype=torch.int32, device="cuda")
-    pf.mlp_select(torch.empty(0, dtype=torch.uint8, device="cuda"), e, 4, 16, e, e, counts,
-                  torch.empty(4, dtype=torch.uint8, device="cuda"))
+    pf.mlp_select(torch.empty(0, dtype=torch.uint8, device="cuda"), e, 4, 16, e, e, counts, ws)
     assert counts.cpu().tolist() == [0, 0]
+    pf.mlp_select(flt.vflags[:n], flt.count[:n], 4, 16, tr, sp, counts, ws)
+    assert counts.cpu().tolist() == [nt, ns]
+    assert np.array_equal(tr[:nt].cpu().numpy(), want_tr)
+    assert np.array_equal(sp[:ns].cpu().numpy(), want_sp)
 
 
 def _geo(g, flt, f):
